@@ -1,0 +1,162 @@
+/*
+ * gp_l1.h - C ABI of the MI355X (gfx950) gradient-projection solver for
+ * l1-constrained least squares.
+ *
+ * Problem (the constrained form (2) of Section 1 of Loris, Bertero, De Mol,
+ * Zanella, Zanni, "Accelerating gradient projection methods for
+ * l1-constrained signal recovery by steplength selection rules"):
+ *
+ *     x~(rho) = argmin_{ ||x||_1 <= rho }  f(x),   f(x) = ||K x - y||^2
+ *
+ * with K an n x p matrix, y in R^n, x in R^p.  f carries no 1/2 factor, so
+ * grad f(x) = 2 K^T (K x - y).  The method is Algorithm 1 of Section 3
+ * (gradient projection along the feasible direction d = P(x - alpha g) - x
+ * with an Armijo backtracking line search) driven by the adaptive
+ * Barzilai-Borwein alternation of Algorithm 2 (equation (5)), with the
+ * parameter values that close Section 3 as defaults.
+ *
+ * Conventions shared by every call:
+ *  - Layout: K is row-major, element (i, j) at K[i * ldk + j], ldk >= p.
+ *    Batched right-hand sides and solutions are stored one problem per row:
+ *    Y[b * ldy + i], X[b * ldx + j].
+ *  - Precision: the dtype names K's storage.  Vectors (y, x0, x_out, Y, X,
+ *    v, h) are double for GP_F64 and float for GP_F32 / GP_BF16.  Scalars
+ *    (steplengths, threshold sums, line-search tests, objective) are double
+ *    on the device for every dtype.  GP_BF16 stores K as raw bfloat16 bits
+ *    (uint16) and accumulates products in float.
+ *  - Memory: every data pointer is a DEVICE pointer owned by the caller
+ *    (for example a torch tensor's data_ptr()), except the ones marked
+ *    "host".  The library never frees caller memory.  Inputs are read only;
+ *    an output may alias the matching input (x_out == x0).
+ *  - Streams: `stream` is a hipStream_t passed as void* (NULL = the default
+ *    stream).  Work is enqueued on it; calls that fill a host result struct
+ *    synchronise that stream before returning.
+ *  - Errors: every call returns a gp_status.  Values >= 0 are solver
+ *    outcomes with a valid x; negative values mean no valid output, and
+ *    gp_last_error() describes the problem.  No C++ exception crosses this
+ *    boundary.  A handle is used by one host thread at a time.
+ */
+#ifndef GP_L1_H
+#define GP_L1_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum { GP_F64 = 0, GP_F32 = 1, GP_BF16 = 2 } gp_dtype;
+
+typedef enum {
+    GP_OK_TOL = 0,          /* relative objective change fell below tol        */
+    GP_STATIONARY = 1,      /* P(x - alpha g) == x, or grad'd >= 0 in rounding  */
+    GP_MAX_ITER = 2,        /* iteration budget used up                         */
+    GP_REACHED_TARGET = 3,  /* f(x) <= opts.f_target                            */
+    GP_BACKTRACK_LIMIT = 4, /* Armijo test failed after backtrack_cap reductions */
+    GP_E_ARG = -1,          /* bad argument (sizes, rho, tol, null pointer)      */
+    GP_E_NONFINITE = -2,    /* NaN/Inf in K, y or arising during the run         */
+    GP_E_HIP = -3,          /* a HIP runtime call failed                         */
+    GP_E_NOMEM = -4,        /* workspace allocation failed                       */
+    GP_E_UNSUPPORTED = -5   /* shape outside what the kernels handle             */
+} gp_status;
+
+/* Solver options.  gp_opts_default() fills the values the paper uses for
+ * GPSS (end of Section 3): M = 1, theta = 0.5, beta = 1e-4,
+ * alpha_min = 1e-10, alpha_max = 1e10, tau1 = 0.5, M_alpha = 2. */
+typedef struct {
+    int32_t M;            /* line-search memory: f_max over the last M values, 1..16 */
+    double theta;         /* backtracking factor, (0,1)                        */
+    double beta;          /* sufficient-decrease constant, (0,1)               */
+    double alpha_min;     /* steplength clamp, 0 < alpha_min < alpha_max       */
+    double alpha_max;
+    double tau1;          /* initial alternation threshold, (0,1)              */
+    int32_t M_alpha;      /* alpha^(2) window = last M_alpha+1 iterations, 0..3 */
+    int32_t max_iter;     /* iteration budget (>= 0)                           */
+    double f_target;      /* stop once f <= f_target (ignored if < 0)          */
+    int32_t refresh_every;/* recompute r = Kx - y, g = 2K^T r every R iters (0 = never) */
+    int32_t backtrack_cap;/* max reductions of the line-search step            */
+    int32_t chunk;        /* iterations enqueued between host status polls     */
+    int32_t fused_cfg;    /* tuning: fused K/K^T kernel shape, 1..6 (0 = automatic) */
+    int32_t fused_grid;   /* tuning: workgroups (row slabs) of that kernel (0 = automatic) */
+} gp_opts;
+
+typedef struct {
+    int32_t status;       /* gp_status                                         */
+    int32_t iters;        /* accepted updates                                  */
+    int32_t backtracks;   /* total step reductions                             */
+    int32_t projected_x0; /* 1 if x0 was outside the ball and was projected    */
+    double f;             /* ||K x - y||^2 at the returned x                   */
+    double rel_change;    /* (f_prev - f)/f_prev of the last update            */
+    double lambda_est;    /* ||K^T (y - K x)||_inf: the lambda paired with rho (Section 1) */
+    double l1norm;        /* ||x||_1                                           */
+} gp_result;
+
+typedef struct gp_handle_s* gp_handle;
+
+/* Fill `o` with the paper's GPSS parameters, max_iter = 100000,
+ * f_target = -1 (off), refresh_every = 0, backtrack_cap = 60, chunk = 64,
+ * automatic kernel shapes. */
+void gp_opts_default(gp_opts* o);
+
+/* Create a handle bound to HIP device `device`; it owns the solver's scratch
+ * workspace, which grows on demand and is freed by gp_destroy. */
+int gp_create(gp_handle* out, int device);
+int gp_destroy(gp_handle h);
+/* Message for the last failing call on `h` (never NULL; static if h == NULL). */
+const char* gp_last_error(gp_handle h);
+
+/* Euclidean projection onto {||h||_1 <= rho}, the operator P_Omega used by
+ * Algorithm 1 (Section 2, item 5, and Section 3):
+ * h = sgn(v) max(|v| - mu, 0) with mu >= 0 the threshold for which
+ * ||h||_1 = rho, or h = v when ||v||_1 <= rho.
+ * vdtype: GP_F64 (double vectors) or GP_F32 (float vectors).  v, h_out:
+ * device, p elements; h_out may alias v.  mu_out: host, may be NULL (then the
+ * call does not synchronise).  p == 0 is a no-op.  rho < 0 or NaN: GP_E_ARG. */
+int gp_l1_project(gp_handle h, gp_dtype vdtype, const void* v, int64_t p,
+                  double rho, void* h_out, double* mu_out, void* stream);
+
+/* Solve problem (2) with GPSS.  K: device n x p (ldk).  y: device n.
+ * x0: device p, or NULL for x0 = 0 (projected onto the ball if outside).
+ * tol: stop when (f_prev - f)/f_prev < tol (0 disables).  x_out: device p.
+ * opts: host, NULL = defaults.  res: host, required.
+ * Errors: n <= 0, p <= 0, ldk < p, rho < 0 or not finite, tol < 0 -> GP_E_ARG.
+ * rho == 0 returns x = 0 with GP_STATIONARY. */
+int gp_l1_solve(gp_handle h, gp_dtype kdtype, const void* K, int64_t n,
+                int64_t p, int64_t ldk, const void* y, double rho,
+                const void* x0, double tol, void* x_out, const gp_opts* opts,
+                gp_result* res, void* stream);
+
+/* B independent problems that share one K (B right-hand sides).
+ * Y: device B x n (ldy >= n), rho: host array of B radii, X0: device B x p
+ * (ldx >= p) or NULL, X_out: device B x p (ldx).  Each problem runs its own
+ * steplength, threshold and line search; finished problems are frozen.
+ * res: host array of B results.  Returns the most severe status. */
+int gp_l1_solve_batched_shared(gp_handle h, gp_dtype kdtype, const void* K,
+                               int64_t n, int64_t p, int64_t ldk,
+                               const void* Y, int64_t ldy, int64_t B,
+                               const double* rho, const void* X0, int64_t ldx,
+                               double tol, void* X_out, const gp_opts* opts,
+                               gp_result* res, void* stream);
+
+/* One problem of an uneven batch: device pointers, its own sizes and radius. */
+typedef struct {
+    const void* K;     /* device, n x p row-major with leading dimension ldk */
+    const void* y;     /* device, n                                          */
+    const void* x0;    /* device, p, or NULL for 0                           */
+    void* x_out;       /* device, p                                          */
+    int64_t n, p, ldk;
+    double rho;
+} gp_instance;
+
+/* B independent problems of different sizes, all of dtype kdtype.
+ * inst: host array of B descriptors (pointers inside are device pointers).
+ * res: host array of B results.  Returns the most severe status. */
+int gp_l1_solve_batched_var(gp_handle h, gp_dtype kdtype,
+                            const gp_instance* inst, int64_t B, double tol,
+                            const gp_opts* opts, gp_result* res, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GP_L1_H */

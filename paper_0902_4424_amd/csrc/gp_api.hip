@@ -1,0 +1,466 @@
+// C ABI of the GPSS solver: handle, workspace, argument checks, launch
+// sequence.  The iteration runs entirely on the device; the host enqueues
+// `chunk` iterations at a time and reads one status word between chunks.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "gp_l1.h"
+#include "gp_kernels.hpp"
+#include "gp_internal.hpp"
+
+using namespace gpl1;
+
+namespace gpl1 {
+
+const char* status_name(int s) {
+    switch (s) {
+        case GP_OK_TOL: return "ok_tol";
+        case GP_STATIONARY: return "stationary";
+        case GP_MAX_ITER: return "max_iter";
+        case GP_REACHED_TARGET: return "reached_target";
+        case GP_BACKTRACK_LIMIT: return "backtrack_limit";
+        case GP_E_ARG: return "bad argument";
+        case GP_E_NONFINITE: return "non-finite value";
+        case GP_E_HIP: return "HIP error";
+        case GP_E_NOMEM: return "out of memory";
+        case GP_E_UNSUPPORTED: return "unsupported shape";
+    }
+    return "unknown";
+}
+
+int fail(gp_handle h, int code, const std::string& msg) {
+    if (h) h->err = msg;
+    return code;
+}
+
+int hip_fail(gp_handle h, hipError_t e, const char* where) {
+    return fail(h, GP_E_HIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+int ensure_workspace(gp_handle h, size_t bytes) {
+    if (bytes <= h->ws_bytes) return GP_OK_TOL;
+    if (h->ws) {
+        hipError_t e = hipFree(h->ws);
+        h->ws = nullptr;
+        h->ws_bytes = 0;
+        if (e != hipSuccess) return hip_fail(h, e, "hipFree(workspace)");
+    }
+    size_t want = std::max(bytes, (size_t)1 << 20);
+    hipError_t e = hipMalloc(&h->ws, want);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        h->ws = nullptr;
+        return fail(h, GP_E_NOMEM, "workspace allocation of " + std::to_string(want) + " bytes failed");
+    }
+    h->ws_bytes = want;
+    return GP_OK_TOL;
+}
+
+GPParams make_params(const gp_opts& o, double rho, double tol) {
+    GPParams P;
+    P.theta = o.theta;
+    P.beta = o.beta;
+    P.amin = o.alpha_min;
+    P.amax = o.alpha_max;
+    P.tau1 = o.tau1;
+    P.f_target = o.f_target;
+    P.tol = tol;
+    P.rho = rho;
+    P.M = o.M;
+    P.Malpha = o.M_alpha;
+    P.max_iter = o.max_iter;
+    P.bt_cap = o.backtrack_cap;
+    return P;
+}
+
+int check_opts(gp_handle h, const gp_opts& o) {
+    if (!(o.M >= 1 && o.M <= MAX_M)) return fail(h, GP_E_ARG, "opts.M must be in 1..16");
+    if (!(o.theta > 0.0 && o.theta < 1.0)) return fail(h, GP_E_ARG, "opts.theta must be in (0,1)");
+    if (!(o.beta > 0.0 && o.beta < 1.0)) return fail(h, GP_E_ARG, "opts.beta must be in (0,1)");
+    if (!(o.alpha_min > 0.0 && o.alpha_min < o.alpha_max && std::isfinite(o.alpha_max)))
+        return fail(h, GP_E_ARG, "need 0 < alpha_min < alpha_max < inf");
+    if (!(o.tau1 > 0.0 && o.tau1 < 1.0)) return fail(h, GP_E_ARG, "opts.tau1 must be in (0,1)");
+    if (!(o.M_alpha >= 0 && o.M_alpha <= MAX_RING - 1)) return fail(h, GP_E_ARG, "opts.M_alpha must be in 0..3");
+    if (o.max_iter < 0) return fail(h, GP_E_ARG, "opts.max_iter must be >= 0");
+    if (o.refresh_every < 0) return fail(h, GP_E_ARG, "opts.refresh_every must be >= 0");
+    if (o.backtrack_cap < 0 || o.backtrack_cap > 1000) return fail(h, GP_E_ARG, "opts.backtrack_cap must be in 0..1000");
+    if (o.chunk < 1) return fail(h, GP_E_ARG, "opts.chunk must be >= 1");
+    if (std::isnan(o.f_target)) return fail(h, GP_E_ARG, "opts.f_target is NaN");
+    return GP_OK_TOL;
+}
+
+// ---------------------------------------------------------------------------
+// fused-kernel configurations
+// ---------------------------------------------------------------------------
+// (threads, column chunks per thread, rows per block); columns covered by one
+// workgroup = T * CPT * VEC.
+struct FusedCfg { int T, CPT, RB; };
+static const FusedCfg kFusedCfgs[] = {
+    {256, 1, 4}, {256, 2, 4}, {256, 4, 2}, {512, 4, 2}, {512, 8, 1}, {1024, 8, 1},
+};
+constexpr int kNumFusedCfgs = sizeof(kFusedCfgs) / sizeof(kFusedCfgs[0]);
+
+int esize(gp_dtype dt) { return dt == GP_F64 ? 8 : dt == GP_F32 ? 4 : 2; }
+
+// Pick the smallest configuration whose workgroup covers all p columns.
+int pick_fused_cfg(gp_dtype dt, int64_t p, int want) {
+    const int vec = 16 / esize(dt);
+    if (want > 0 && want <= kNumFusedCfgs) {
+        const FusedCfg& c = kFusedCfgs[want - 1];
+        return (int64_t)c.T * c.CPT * vec >= p ? want - 1 : -1;
+    }
+    for (int i = 0; i < kNumFusedCfgs; ++i) {
+        const FusedCfg& c = kFusedCfgs[i];
+        if ((int64_t)c.T * c.CPT * vec >= p) return i;
+    }
+    return -1;
+}
+
+int64_t pick_fused_grid(int64_t n, int64_t p, gp_dtype dt, int want) {
+    if (want > 0) return std::min<int64_t>(want, n);
+    // one workgroup per CU for large problems; fewer for small ones so that
+    // the partial vectors stay small next to K
+    const double kbytes = (double)n * (double)p * esize(dt);
+    int64_t g = kbytes >= 32e6 ? 256 : kbytes >= 4e6 ? 128 : 64;
+    g = std::min<int64_t>(g, std::max<int64_t>(1, n / 2));
+    return std::max<int64_t>(1, std::min(g, n));
+}
+
+template <typename TK, typename ACC, int T, int CPT, int RB>
+void launch_fused_t(bool aligned, hipStream_t s, int64_t G, const GPState* st, const void* K, int64_t n,
+                    int64_t p, int64_t ldk, int64_t rows, const double* v, const double* ysub,
+                    const double* rvec, double* tout, void* wpart, int64_t ldw, double* spart) {
+    if (aligned)
+        hipLaunchKernelGGL((k_fused<TK, ACC, T, CPT, RB, true>), dim3((unsigned)G), dim3(T), 0, s, st,
+                           (const TK*)K, n, p, ldk, rows, v, ysub, rvec, tout, (ACC*)wpart, ldw, spart);
+    else
+        hipLaunchKernelGGL((k_fused<TK, ACC, T, CPT, RB, false>), dim3((unsigned)G), dim3(T), 0, s, st,
+                           (const TK*)K, n, p, ldk, rows, v, ysub, rvec, tout, (ACC*)wpart, ldw, spart);
+}
+
+template <typename TK, typename ACC>
+void launch_fused_dt(int cfg, bool aligned, hipStream_t s, int64_t G, const GPState* st, const void* K,
+                     int64_t n, int64_t p, int64_t ldk, int64_t rows, const double* v, const double* ysub,
+                     const double* rvec, double* tout, void* wpart, int64_t ldw, double* spart) {
+#define GPL1_FUSED_CASE(i, T, C, R)                                                                       \
+    case i:                                                                                              \
+        launch_fused_t<TK, ACC, T, C, R>(aligned, s, G, st, K, n, p, ldk, rows, v, ysub, rvec, tout, wpart, \
+                                         ldw, spart);                                                    \
+        break;
+    switch (cfg) {
+        GPL1_FUSED_CASE(0, 256, 1, 4)
+        GPL1_FUSED_CASE(1, 256, 2, 4)
+        GPL1_FUSED_CASE(2, 256, 4, 2)
+        GPL1_FUSED_CASE(3, 512, 4, 2)
+        GPL1_FUSED_CASE(4, 512, 8, 1)
+        GPL1_FUSED_CASE(5, 1024, 8, 1)
+    }
+#undef GPL1_FUSED_CASE
+}
+
+void launch_fused(gp_dtype dt, int cfg, bool aligned, hipStream_t s, int64_t G, const GPState* st,
+                  const void* K, int64_t n, int64_t p, int64_t ldk, int64_t rows, const double* v,
+                  const double* ysub, const double* rvec, double* tout, void* wpart, int64_t ldw,
+                  double* spart) {
+    if (dt == GP_F64)
+        launch_fused_dt<double, double>(cfg, aligned, s, G, st, K, n, p, ldk, rows, v, ysub, rvec, tout, wpart,
+                                        ldw, spart);
+    else if (dt == GP_F32)
+        launch_fused_dt<float, float>(cfg, aligned, s, G, st, K, n, p, ldk, rows, v, ysub, rvec, tout, wpart,
+                                      ldw, spart);
+    else
+        launch_fused_dt<bf16_t, float>(cfg, aligned, s, G, st, K, n, p, ldk, rows, v, ysub, rvec, tout, wpart,
+                                       ldw, spart);
+}
+
+int proj_vpt(int64_t p) {
+    const int64_t per = (p + PROJ_T - 1) / PROJ_T;
+    if (per <= 1) return 1;
+    if (per <= 2) return 2;
+    if (per <= 4) return 4;
+    if (per <= 8) return 8;
+    if (per <= 16) return 16;
+    if (per <= 32) return 32;
+    return 0;
+}
+
+void launch_proj(hipStream_t s, GPState* st, int mode, int64_t p, double* x, const double* g, double* dout,
+                 const double* upart, int GU, double* vbuf) {
+    switch (proj_vpt(p)) {
+#define GPL1_PROJ_CASE(V) \
+    case V: hipLaunchKernelGGL(k_proj<V>, dim3(1), dim3(PROJ_T), 0, s, st, mode, p, x, g, dout, upart, GU, vbuf); break;
+        GPL1_PROJ_CASE(1)
+        GPL1_PROJ_CASE(2)
+        GPL1_PROJ_CASE(4)
+        GPL1_PROJ_CASE(8)
+        GPL1_PROJ_CASE(16)
+        GPL1_PROJ_CASE(32)
+        GPL1_PROJ_CASE(0)
+#undef GPL1_PROJ_CASE
+    }
+}
+
+void launch_update(gp_dtype dt, hipStream_t s, GPState* st, int mode, const double* spart, int GF,
+                   const void* wpart, int64_t ldw, int64_t p, int64_t n, double* x, double* g, const double* d,
+                   double* r, const double* tq, double* upart) {
+    const int nbp = (int)((p + UPD_COLS - 1) / UPD_COLS);
+    const int nbn = (int)((n + UPD_ROWS - 1) / UPD_ROWS);
+    if (dt == GP_F64)
+        hipLaunchKernelGGL(k_update<double>, dim3(nbp + nbn), dim3(UPD_T), 0, s, st, mode, spart, GF,
+                           (const double*)wpart, ldw, p, n, nbp, x, g, d, r, tq, upart);
+    else
+        hipLaunchKernelGGL(k_update<float>, dim3(nbp + nbn), dim3(UPD_T), 0, s, st, mode, spart, GF,
+                           (const float*)wpart, ldw, p, n, nbp, x, g, d, r, tq, upart);
+}
+
+template <typename TV>
+void launch_to_f64(hipStream_t s, const void* in, double* out, int64_t n) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_to_f64<TV>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, (const TV*)in, out, n);
+}
+template <typename TV>
+void launch_from_f64(hipStream_t s, const double* in, void* out, int64_t n) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_from_f64<TV>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, in, (TV*)out, n);
+}
+
+// ---------------------------------------------------------------------------
+// one problem
+// ---------------------------------------------------------------------------
+Plan plan_single(gp_dtype dt, int64_t n, int64_t p, const gp_opts& o) {
+    Plan P{};
+    P.cfg = pick_fused_cfg(dt, p, o.fused_cfg);
+    P.G = pick_fused_grid(n, p, dt, o.fused_grid);
+    P.rows = (n + P.G - 1) / P.G;
+    P.G = (n + P.rows - 1) / P.rows;
+    P.ldw = (p + 63) / 64 * 64;
+    P.nbp = (int)((p + UPD_COLS - 1) / UPD_COLS);
+    P.GU = P.nbp + (int)((n + UPD_ROWS - 1) / UPD_ROWS);
+    const int wsz = dt == GP_F64 ? 8 : 4;
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t o2 = off; off += (bytes + 255) / 256 * 256; return o2; };
+    P.o_state = take(sizeof(GPState));
+    P.o_x = take(sizeof(double) * p);
+    P.o_g = take(sizeof(double) * p);
+    P.o_d = take(sizeof(double) * p);
+    P.o_vbuf = take(sizeof(double) * p);
+    P.o_r = take(sizeof(double) * n);
+    P.o_q = take(sizeof(double) * n);
+    P.o_y = take(sizeof(double) * n);
+    P.o_spart = take(sizeof(double) * 2 * P.G);
+    P.o_upart = take(sizeof(double) * 4 * P.GU);
+    P.o_wpart = take((size_t)wsz * P.ldw * P.G);
+    P.bytes = off;
+    return P;
+}
+
+}  // namespace gpl1
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+void gp_opts_default(gp_opts* o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->M = 1;
+    o->theta = 0.5;
+    o->beta = 1e-4;
+    o->alpha_min = 1e-10;
+    o->alpha_max = 1e10;
+    o->tau1 = 0.5;
+    o->M_alpha = 2;
+    o->max_iter = 100000;
+    o->f_target = -1.0;
+    o->refresh_every = 0;
+    o->backtrack_cap = 60;
+    o->chunk = 64;
+    o->fused_cfg = 0;
+    o->fused_grid = 0;
+}
+
+int gp_create(gp_handle* out, int device) {
+    if (!out) return GP_E_ARG;
+    *out = nullptr;
+    int count = 0;
+    hipError_t e = hipGetDeviceCount(&count);
+    if (e != hipSuccess || device < 0 || device >= count) return GP_E_ARG;
+    gp_handle h = new (std::nothrow) gp_handle_s();
+    if (!h) return GP_E_NOMEM;
+    h->device = device;
+    e = hipSetDevice(device);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&h->host_state, sizeof(GPState), hipHostMallocDefault);
+    if (e != hipSuccess) {
+        delete h;
+        return GP_E_HIP;
+    }
+    *out = h;
+    return GP_OK_TOL;
+}
+
+int gp_destroy(gp_handle h) {
+    if (!h) return GP_OK_TOL;
+    (void)hipSetDevice(h->device);
+    if (h->ws) (void)hipFree(h->ws);
+    if (h->host_state) (void)hipHostFree(h->host_state);
+    delete h;
+    return GP_OK_TOL;
+}
+
+const char* gp_last_error(gp_handle h) {
+    if (!h) return "null handle";
+    return h->err.c_str();
+}
+
+int gp_l1_project(gp_handle h, gp_dtype vdtype, const void* v, int64_t p, double rho, void* h_out,
+                  double* mu_out, void* stream) {
+    if (!h) return GP_E_ARG;
+    h->err.clear();
+    if (vdtype != GP_F64 && vdtype != GP_F32) return fail(h, GP_E_ARG, "projection vectors must be GP_F64 or GP_F32");
+    if (p < 0) return fail(h, GP_E_ARG, "p must be >= 0");
+    if (!(rho >= 0.0) || !std::isfinite(rho)) return fail(h, GP_E_ARG, "rho must be finite and >= 0");
+    if (p == 0) { if (mu_out) *mu_out = 0.0; return GP_OK_TOL; }
+    if (!v || !h_out) return fail(h, GP_E_ARG, "null vector pointer");
+    if (p > (int64_t)1 << 31) return fail(h, GP_E_UNSUPPORTED, "p too large");
+    hipError_t e = hipSetDevice(h->device);
+    if (e != hipSuccess) return hip_fail(h, e, "hipSetDevice");
+    hipStream_t s = (hipStream_t)stream;
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t o2 = off; off += (bytes + 255) / 256 * 256; return o2; };
+    size_t o_state = take(sizeof(GPState)), o_x = take(8 * p), o_h = take(8 * p), o_vb = take(8 * p);
+    int rc = ensure_workspace(h, off);
+    if (rc) return rc;
+    char* ws = (char*)h->ws;
+    GPState* st = (GPState*)(ws + o_state);
+    double* x = (double*)(ws + o_x);
+    double* hv = (double*)(ws + o_h);
+    double* vb = (double*)(ws + o_vb);
+    gp_opts o;
+    gp_opts_default(&o);
+    hipLaunchKernelGGL(k_init_state, dim3(1), dim3(1), 0, s, st, make_params(o, rho, 0.0));
+    if (vdtype == GP_F64) launch_to_f64<double>(s, v, x, p);
+    else launch_to_f64<float>(s, v, x, p);
+    launch_proj(s, st, PM_PLAIN, p, x, nullptr, hv, nullptr, 0, vb);
+    if (vdtype == GP_F64) launch_from_f64<double>(s, hv, h_out, p);
+    else launch_from_f64<float>(s, hv, h_out, p);
+    e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(h, e, "projection launch");
+    if (mu_out) {
+        e = hipMemcpyAsync(h->host_state, st, sizeof(GPState), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return hip_fail(h, e, "projection sync");
+        if (h->host_state->status == ST_NONFINITE) return fail(h, GP_E_NONFINITE, "non-finite input vector");
+        *mu_out = h->host_state->mu;
+    }
+    return GP_OK_TOL;
+}
+
+int gp_l1_solve(gp_handle h, gp_dtype kdtype, const void* K, int64_t n, int64_t p, int64_t ldk, const void* y,
+                double rho, const void* x0, double tol, void* x_out, const gp_opts* opts, gp_result* res,
+                void* stream) {
+    if (!h) return GP_E_ARG;
+    h->err.clear();
+    if (!res) return fail(h, GP_E_ARG, "res must not be NULL");
+    std::memset(res, 0, sizeof(*res));
+    res->status = GP_E_ARG;
+    gp_opts o;
+    if (opts) o = *opts; else gp_opts_default(&o);
+    if (kdtype != GP_F64 && kdtype != GP_F32 && kdtype != GP_BF16) return fail(h, GP_E_ARG, "bad dtype");
+    if (n <= 0 || p <= 0) return fail(h, GP_E_ARG, "n and p must be positive");
+    if (ldk < p) return fail(h, GP_E_ARG, "ldk must be >= p");
+    if (!(rho >= 0.0) || !std::isfinite(rho)) return fail(h, GP_E_ARG, "rho must be finite and >= 0");
+    if (!(tol >= 0.0)) return fail(h, GP_E_ARG, "tol must be >= 0");
+    if (!K || !y || !x_out) return fail(h, GP_E_ARG, "null pointer argument");
+    int rc = check_opts(h, o);
+    if (rc) return rc;
+    if (n > ((int64_t)1 << 31) || p > ((int64_t)1 << 31)) return fail(h, GP_E_UNSUPPORTED, "n or p too large");
+    Plan P = plan_single(kdtype, n, p, o);
+    if (P.cfg < 0)
+        return fail(h, GP_E_UNSUPPORTED, "p = " + std::to_string(p) + " exceeds the fused kernel's column capacity");
+    hipError_t e = hipSetDevice(h->device);
+    if (e != hipSuccess) return hip_fail(h, e, "hipSetDevice");
+    rc = ensure_workspace(h, P.bytes);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    char* ws = (char*)h->ws;
+    GPState* st = (GPState*)(ws + P.o_state);
+    double* x = (double*)(ws + P.o_x);
+    double* g = (double*)(ws + P.o_g);
+    double* d = (double*)(ws + P.o_d);
+    double* vb = (double*)(ws + P.o_vbuf);
+    double* r = (double*)(ws + P.o_r);
+    double* q = (double*)(ws + P.o_q);
+    double* y64 = (double*)(ws + P.o_y);
+    double* spart = (double*)(ws + P.o_spart);
+    double* upart = (double*)(ws + P.o_upart);
+    void* wpart = ws + P.o_wpart;
+    const int vec = 16 / esize(kdtype);
+    const bool aligned = (ldk % vec == 0) && (((uintptr_t)K) % 16 == 0);
+    const bool f64v = kdtype == GP_F64;
+
+    hipLaunchKernelGGL(k_init_state, dim3(1), dim3(1), 0, s, st, make_params(o, rho, tol));
+    if (f64v) { launch_to_f64<double>(s, y, y64, n); launch_to_f64<double>(s, x0, x, p); }
+    else { launch_to_f64<float>(s, y, y64, n); launch_to_f64<float>(s, x0, x, p); }
+    if (x0) launch_proj(s, st, PM_INIT_X0, p, x, nullptr, nullptr, nullptr, 0, vb);
+    // r = K x - y, g = 2 K^T r, f = ||r||^2
+    auto refresh = [&]() {
+        launch_fused(kdtype, P.cfg, aligned, s, P.G, st, K, n, p, ldk, P.rows, x, y64, nullptr, q, wpart, P.ldw,
+                     spart);
+        launch_update(kdtype, s, st, UM_REFRESH, spart, (int)P.G, wpart, P.ldw, p, n, x, g, d, r, q, upart);
+    };
+    refresh();
+    launch_proj(s, st, PM_ALPHA0, p, x, g, nullptr, nullptr, 0, vb);
+    e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(h, e, "init launch");
+
+    int it = 0;
+    while (it < o.max_iter) {
+        const int end = std::min(o.max_iter, it + o.chunk);
+        for (; it < end; ++it) {
+            launch_proj(s, st, PM_ITER, p, x, g, d, upart, P.GU, vb);
+            launch_fused(kdtype, P.cfg, aligned, s, P.G, st, K, n, p, ldk, P.rows, d, nullptr, r, q, wpart,
+                         P.ldw, spart);
+            launch_update(kdtype, s, st, UM_ITER, spart, (int)P.G, wpart, P.ldw, p, n, x, g, d, r, q, upart);
+            if (o.refresh_every > 0 && (it + 1) % o.refresh_every == 0 && it + 1 < o.max_iter) refresh();
+        }
+        e = hipGetLastError();
+        if (e != hipSuccess) return hip_fail(h, e, "iteration launch");
+        if (it < o.max_iter) {
+            e = hipMemcpyAsync(h->host_state, st, sizeof(GPState), hipMemcpyDeviceToHost, s);
+            if (e == hipSuccess) e = hipStreamSynchronize(s);
+            if (e != hipSuccess) return hip_fail(h, e, "status poll");
+            if (h->host_state->done || h->host_state->stop_req) break;
+        }
+    }
+    hipLaunchKernelGGL(k_finish, dim3(1), dim3(PROJ_T), 0, s, st, x, g, p);
+    if (f64v) launch_from_f64<double>(s, x, x_out, p);
+    else launch_from_f64<float>(s, x, x_out, p);
+    e = hipMemcpyAsync(h->host_state, st, sizeof(GPState), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(h, e, "final sync");
+    fill_result(*h->host_state, res);
+    if (res->status < 0) return fail(h, res->status, "solve ended with a non-finite value");
+    return res->status;
+}
+
+}  // extern "C"
+
+namespace gpl1 {
+void fill_result(const GPState& s, gp_result* res) {
+    res->status = s.status;
+    res->iters = s.k;
+    res->backtracks = s.backtracks;
+    res->projected_x0 = s.projected;
+    res->f = s.f;
+    res->rel_change = s.rel;
+    res->lambda_est = s.gmax / 2.0;
+    res->l1norm = s.l1;
+}
+}  // namespace gpl1

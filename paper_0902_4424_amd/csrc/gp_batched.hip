@@ -1,0 +1,61 @@
+// Batched entry points.  This translation unit runs the batch as a sequence
+// of single-problem solves on the caller's stream; every problem keeps its
+// own steplength, threshold and line-search state.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <string>
+
+#include "gp_internal.hpp"
+#include "gp_l1.h"
+
+using namespace gpl1;
+
+namespace {
+int severity(int s) {            // errors first, then unfinished, then finished
+    if (s < 0) return 100 - s;
+    if (s == GP_BACKTRACK_LIMIT) return 4;
+    if (s == GP_MAX_ITER) return 3;
+    return 1;
+}
+}  // namespace
+
+extern "C" int gp_l1_solve_batched_shared(gp_handle h, gp_dtype kdtype, const void* K, int64_t n, int64_t p,
+                                          int64_t ldk, const void* Y, int64_t ldy, int64_t B,
+                                          const double* rho, const void* X0, int64_t ldx, double tol,
+                                          void* X_out, const gp_opts* opts, gp_result* res, void* stream) {
+    if (!h) return GP_E_ARG;
+    if (B < 0) return fail(h, GP_E_ARG, "B must be >= 0");
+    if (B == 0) return GP_OK_TOL;
+    if (!res || !rho || !Y || !X_out) return fail(h, GP_E_ARG, "null pointer argument");
+    if (ldy < n || ldx < p) return fail(h, GP_E_ARG, "ldy must be >= n and ldx >= p");
+    const size_t vsz = kdtype == GP_F64 ? 8 : 4;
+    int worst = GP_OK_TOL;
+    for (int64_t b = 0; b < B; ++b) {
+        const char* yb = (const char*)Y + (size_t)b * ldy * vsz;
+        const char* x0b = X0 ? (const char*)X0 + (size_t)b * ldx * vsz : nullptr;
+        char* xb = (char*)X_out + (size_t)b * ldx * vsz;
+        int rc = gp_l1_solve(h, kdtype, K, n, p, ldk, yb, rho[b], x0b, tol, xb, opts, &res[b], stream);
+        if (rc == GP_E_ARG || rc == GP_E_HIP || rc == GP_E_NOMEM || rc == GP_E_UNSUPPORTED) return rc;
+        if (severity(rc) > severity(worst)) worst = rc;
+    }
+    return worst;
+}
+
+extern "C" int gp_l1_solve_batched_var(gp_handle h, gp_dtype kdtype, const gp_instance* inst, int64_t B,
+                                       double tol, const gp_opts* opts, gp_result* res, void* stream) {
+    if (!h) return GP_E_ARG;
+    if (B < 0) return fail(h, GP_E_ARG, "B must be >= 0");
+    if (B == 0) return GP_OK_TOL;
+    if (!inst || !res) return fail(h, GP_E_ARG, "null pointer argument");
+    int worst = GP_OK_TOL;
+    for (int64_t b = 0; b < B; ++b) {
+        const gp_instance& I = inst[b];
+        int rc = gp_l1_solve(h, kdtype, I.K, I.n, I.p, I.ldk, I.y, I.rho, I.x0, tol, I.x_out, opts, &res[b],
+                             stream);
+        if (rc == GP_E_ARG || rc == GP_E_HIP || rc == GP_E_NOMEM || rc == GP_E_UNSUPPORTED) return rc;
+        if (severity(rc) > severity(worst)) worst = rc;
+    }
+    return worst;
+}

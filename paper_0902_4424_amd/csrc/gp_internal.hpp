@@ -1,0 +1,38 @@
+// Host-side internals shared by the API translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <string>
+
+#include "gp_l1.h"
+#include "gp_state.hpp"
+
+struct gp_handle_s {
+    int device = 0;
+    std::string err;
+    void* ws = nullptr;                  // device workspace, grows on demand
+    size_t ws_bytes = 0;
+    gpl1::GPState* host_state = nullptr; // pinned copy of a state for status reads
+    void* extra = nullptr;               // batched-solver resources
+};
+
+namespace gpl1 {
+
+// Workspace layout and launch shapes of one problem.
+struct Plan {
+    int cfg;          // fused-kernel configuration index
+    int64_t G;        // fused-kernel workgroups (row slabs)
+    int64_t rows;     // rows per slab
+    int64_t ldw;      // stride of the partial w vectors
+    int nbp, GU;      // update kernel: column workgroups, all workgroups
+    size_t o_state, o_x, o_g, o_d, o_vbuf, o_r, o_q, o_y, o_spart, o_upart, o_wpart, bytes;
+};
+
+int fail(gp_handle h, int code, const std::string& msg);
+int hip_fail(gp_handle h, hipError_t e, const char* where);
+int ensure_workspace(gp_handle h, size_t bytes);
+void fill_result(const GPState& s, gp_result* res);
+void destroy_extra(gp_handle h);
+const char* status_name(int s);
+
+}  // namespace gpl1

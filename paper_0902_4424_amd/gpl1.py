@@ -1,0 +1,300 @@
+"""ctypes binding of libgpl1.so (the C ABI declared in include/gp_l1.h).
+
+Argument marshalling only: torch tensors supply device memory (data_ptr())
+and the current HIP stream; every step of the solver runs in the library's
+kernels.  Importing this module does not load the library; the first call
+does, and raises if it is missing (there is no fallback path).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "lib", "libgpl1.so")
+
+GP_F64, GP_F32, GP_BF16 = 0, 1, 2
+STATUS = {0: "ok_tol", 1: "stationary", 2: "max_iter", 3: "reached_target",
+          4: "backtrack_limit", -1: "bad_argument", -2: "nonfinite",
+          -3: "hip_error", -4: "out_of_memory", -5: "unsupported"}
+
+SYMBOLS = ("gp_opts_default", "gp_create", "gp_destroy", "gp_last_error",
+           "gp_l1_project", "gp_l1_solve", "gp_l1_solve_batched_shared",
+           "gp_l1_solve_batched_var")
+
+
+class GPOpts(C.Structure):
+    _fields_ = [("M", C.c_int32), ("theta", C.c_double), ("beta", C.c_double),
+                ("alpha_min", C.c_double), ("alpha_max", C.c_double),
+                ("tau1", C.c_double), ("M_alpha", C.c_int32),
+                ("max_iter", C.c_int32), ("f_target", C.c_double),
+                ("refresh_every", C.c_int32), ("backtrack_cap", C.c_int32),
+                ("chunk", C.c_int32), ("fused_cfg", C.c_int32),
+                ("fused_grid", C.c_int32)]
+
+
+class GPResult(C.Structure):
+    _fields_ = [("status", C.c_int32), ("iters", C.c_int32),
+                ("backtracks", C.c_int32), ("projected_x0", C.c_int32),
+                ("f", C.c_double), ("rel_change", C.c_double),
+                ("lambda_est", C.c_double), ("l1norm", C.c_double)]
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_}
+        d["status_name"] = STATUS.get(self.status, str(self.status))
+        return d
+
+
+class GPInstance(C.Structure):
+    _fields_ = [("K", C.c_void_p), ("y", C.c_void_p), ("x0", C.c_void_p),
+                ("x_out", C.c_void_p), ("n", C.c_int64), ("p", C.c_int64),
+                ("ldk", C.c_int64), ("rho", C.c_double)]
+
+
+_lib = None
+
+
+def load():
+    """Load libgpl1.so and declare the signatures.  Raises if it is absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                           "`python -m paper_0902_4424_amd.build`")
+    lib = C.CDLL(LIB_PATH)
+    vp, i64, dbl, i32 = C.c_void_p, C.c_int64, C.c_double, C.c_int
+    lib.gp_opts_default.argtypes = [C.POINTER(GPOpts)]
+    lib.gp_opts_default.restype = None
+    lib.gp_create.argtypes = [C.POINTER(vp), i32]
+    lib.gp_create.restype = i32
+    lib.gp_destroy.argtypes = [vp]
+    lib.gp_destroy.restype = i32
+    lib.gp_last_error.argtypes = [vp]
+    lib.gp_last_error.restype = C.c_char_p
+    lib.gp_l1_project.argtypes = [vp, i32, vp, i64, dbl, vp, C.POINTER(dbl), vp]
+    lib.gp_l1_project.restype = i32
+    lib.gp_l1_solve.argtypes = [vp, i32, vp, i64, i64, i64, vp, dbl, vp, dbl, vp,
+                                C.POINTER(GPOpts), C.POINTER(GPResult), vp]
+    lib.gp_l1_solve.restype = i32
+    lib.gp_l1_solve_batched_shared.argtypes = [
+        vp, i32, vp, i64, i64, i64, vp, i64, i64, C.POINTER(dbl), vp, i64, dbl,
+        vp, C.POINTER(GPOpts), C.POINTER(GPResult), vp]
+    lib.gp_l1_solve_batched_shared.restype = i32
+    lib.gp_l1_solve_batched_var.argtypes = [vp, i32, C.POINTER(GPInstance), i64,
+                                            dbl, C.POINTER(GPOpts),
+                                            C.POINTER(GPResult), vp]
+    lib.gp_l1_solve_batched_var.restype = i32
+    _lib = lib
+    return lib
+
+
+def default_opts(**kw) -> GPOpts:
+    o = GPOpts()
+    load().gp_opts_default(C.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise TypeError(f"unknown option {k!r}")
+        setattr(o, k, v)
+    return o
+
+
+class GPError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+# ---------------------------------------------------------------------------
+# torch helpers (torch is only a source of device memory and streams)
+# ---------------------------------------------------------------------------
+def _torch():
+    import torch
+    return torch
+
+
+def _stream(stream=None):
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def k_dtype(K) -> int:
+    torch = _torch()
+    if K.dtype == torch.float64:
+        return GP_F64
+    if K.dtype == torch.float32:
+        return GP_F32
+    if K.dtype in (torch.bfloat16, torch.int16, torch.uint16):
+        return GP_BF16
+    raise TypeError(f"unsupported K dtype {K.dtype}")
+
+
+def vec_dtype(kdt: int):
+    torch = _torch()
+    return torch.float64 if kdt == GP_F64 else torch.float32
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else C.c_void_p(0)
+
+
+def _check_dev(*ts):
+    for t in ts:
+        if t is not None and not t.is_cuda:
+            raise ValueError("all tensors must live on the GPU")
+
+
+class Handle:
+    """Owns one gp_handle (device workspace).  Use as a context manager or
+    keep it alive for many solves; the library reuses its workspace."""
+
+    def __init__(self, device: int = 0):
+        self.lib = load()
+        h = C.c_void_p()
+        rc = self.lib.gp_create(C.byref(h), int(device))
+        if rc != 0:
+            raise GPError(rc, f"gp_create(device={device}) failed")
+        self.h = h
+        self.device = device
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.gp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def error(self) -> str:
+        return self.lib.gp_last_error(self.h).decode()
+
+    def _raise(self, rc):
+        if rc < 0:
+            raise GPError(rc, self.error())
+
+    # -- projection -----------------------------------------------------
+    def project(self, v, rho: float, out=None, want_mu=True, stream=None):
+        torch = _torch()
+        _check_dev(v)
+        if v.dtype not in (torch.float64, torch.float32):
+            raise TypeError("v must be float64 or float32")
+        v = v.contiguous()
+        out = torch.empty_like(v) if out is None else out
+        mu = C.c_double(0.0)
+        rc = self.lib.gp_l1_project(self.h, GP_F64 if v.dtype == torch.float64 else GP_F32,
+                                    _ptr(v), v.numel(), float(rho), _ptr(out),
+                                    C.byref(mu) if want_mu else None, _stream(stream))
+        self._raise(rc)
+        return out, (mu.value if want_mu else None)
+
+    # -- one problem ----------------------------------------------------
+    def solve(self, K, y, rho: float, x0=None, tol: float = 1e-10, out=None,
+              opts: GPOpts | None = None, stream=None, **kw):
+        torch = _torch()
+        _check_dev(K, y, x0)
+        kdt = k_dtype(K)
+        vdt = vec_dtype(kdt)
+        if K.dim() != 2 or K.stride(1) != 1:
+            raise ValueError("K must be a row-major 2-D tensor")
+        n, p = K.shape
+        ldk = K.stride(0)
+        if y.dtype != vdt or y.numel() != n or not y.is_contiguous():
+            raise ValueError(f"y must be contiguous {vdt} of length {n}")
+        if x0 is not None and (x0.dtype != vdt or x0.numel() != p or not x0.is_contiguous()):
+            raise ValueError(f"x0 must be contiguous {vdt} of length {p}")
+        out = torch.empty(p, dtype=vdt, device=K.device) if out is None else out
+        o = opts if opts is not None else default_opts(**kw)
+        res = GPResult()
+        rc = self.lib.gp_l1_solve(self.h, kdt, _ptr(K), n, p, ldk, _ptr(y), float(rho),
+                                  _ptr(x0), float(tol), _ptr(out), C.byref(o),
+                                  C.byref(res), _stream(stream))
+        self._raise(rc)
+        return out, res.as_dict()
+
+    # -- many right-hand sides, one K -------------------------------------
+    def solve_batched_shared(self, K, Y, rho, X0=None, tol: float = 1e-10, out=None,
+                             opts: GPOpts | None = None, stream=None, **kw):
+        torch = _torch()
+        _check_dev(K, Y, X0)
+        kdt = k_dtype(K)
+        vdt = vec_dtype(kdt)
+        n, p = K.shape
+        B = Y.shape[0]
+        if Y.dim() != 2 or Y.shape[1] != n or Y.dtype != vdt or Y.stride(1) != 1:
+            raise ValueError(f"Y must be a row-major B x {n} {vdt} tensor")
+        rho_arr = (C.c_double * B)(*[float(r) for r in rho])
+        if X0 is not None and (X0.shape != (B, p) or X0.dtype != vdt or X0.stride(1) != 1):
+            raise ValueError("X0 must be a row-major B x p tensor of the vector dtype")
+        out = torch.empty(B, p, dtype=vdt, device=K.device) if out is None else out
+        ldx = out.stride(0)
+        if X0 is not None and X0.stride(0) != ldx:
+            raise ValueError("X0 and out must share a leading dimension")
+        o = opts if opts is not None else default_opts(**kw)
+        res = (GPResult * B)()
+        rc = self.lib.gp_l1_solve_batched_shared(
+            self.h, kdt, _ptr(K), n, p, K.stride(0), _ptr(Y), Y.stride(0), B, rho_arr,
+            _ptr(X0), ldx, float(tol), _ptr(out), C.byref(o), res, _stream(stream))
+        self._raise(rc)
+        return out, [r.as_dict() for r in res]
+
+    # -- many independent problems of different sizes ---------------------
+    def solve_batched_var(self, problems, tol: float = 1e-10, opts: GPOpts | None = None,
+                          stream=None, **kw):
+        """problems: list of (K, y, rho[, x0]) with device tensors of one K dtype.
+        Returns (list of solution tensors, list of result dicts)."""
+        torch = _torch()
+        B = len(problems)
+        if B == 0:
+            return [], []
+        kdt = k_dtype(problems[0][0])
+        vdt = vec_dtype(kdt)
+        inst = (GPInstance * B)()
+        outs = []
+        for b, prob in enumerate(problems):
+            K, y, rho = prob[0], prob[1], prob[2]
+            x0 = prob[3] if len(prob) > 3 else None
+            _check_dev(K, y, x0)
+            if k_dtype(K) != kdt or K.stride(1) != 1:
+                raise ValueError("all K must share one dtype and be row-major")
+            n, p = K.shape
+            out = torch.empty(p, dtype=vdt, device=K.device)
+            outs.append(out)
+            inst[b] = GPInstance(K.data_ptr(), y.data_ptr(),
+                                 x0.data_ptr() if x0 is not None else None,
+                                 out.data_ptr(), n, p, K.stride(0), float(rho))
+        o = opts if opts is not None else default_opts(**kw)
+        res = (GPResult * B)()
+        rc = self.lib.gp_l1_solve_batched_var(self.h, kdt, inst, B, float(tol), C.byref(o),
+                                              res, _stream(stream))
+        self._raise(rc)
+        return outs, [r.as_dict() for r in res]
+
+
+_default_handles = {}
+
+
+def handle(device: int = 0) -> Handle:
+    if device not in _default_handles:
+        _default_handles[device] = Handle(device)
+    return _default_handles[device]
+
+
+def solve(K, y, rho, x0=None, tol=1e-10, **kw):
+    """x, result = solve(K, y, rho): GPSS on min ||Kx-y||^2 s.t. ||x||_1 <= rho."""
+    return handle(K.device.index or 0).solve(K, y, rho, x0=x0, tol=tol, **kw)
+
+
+def project(v, rho, **kw):
+    return handle(v.device.index or 0).project(v, rho, **kw)

@@ -1,0 +1,83 @@
+"""CPU checks of the C ABI boundary: the library loads, exports every entry
+point the header declares, the ctypes mirrors of the structs match the C
+layout, and the defaults are the paper's GPSS parameters.  No kernel runs."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_0902_4424_amd import gpl1
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "gp_l1.h")
+
+
+def _declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^\s*(?:int|void|const char\*)\s+(gp_\w+)\s*\(", src, flags=re.M)
+    return sorted(set(names))
+
+
+def test_library_exports_every_declared_symbol():
+    names = _declared_functions()
+    assert len(names) >= 8
+    lib = gpl1.load()
+    for nm in names:
+        assert hasattr(lib, nm), f"{nm} declared in gp_l1.h but not exported"
+    assert set(names) == set(gpl1.SYMBOLS)
+    out = subprocess.run(["nm", "-D", "--defined-only", gpl1.LIB_PATH],
+                         capture_output=True, text=True).stdout
+    exported = set(re.findall(r" T (gp_\w+)", out))
+    assert set(names) <= exported
+
+
+def test_struct_layout_matches_header(tmp_path):
+    prog = tmp_path / "sz.c"
+    prog.write_text(r'''
+#include <stdio.h>
+#include <stddef.h>
+#include "gp_l1.h"
+int main(void) {
+  printf("%zu %zu %zu\n", sizeof(gp_opts), sizeof(gp_result), sizeof(gp_instance));
+  printf("%zu %zu %zu %zu %zu\n", offsetof(gp_opts, theta), offsetof(gp_opts, M_alpha),
+         offsetof(gp_opts, f_target), offsetof(gp_opts, chunk), offsetof(gp_opts, fused_grid));
+  printf("%zu %zu %zu\n", offsetof(gp_result, f), offsetof(gp_result, lambda_est),
+         offsetof(gp_result, l1norm));
+  printf("%zu %zu\n", offsetof(gp_instance, n), offsetof(gp_instance, rho));
+  return 0;
+}''')
+    exe = tmp_path / "sz"
+    subprocess.run(["gcc", f"-I{os.path.join(ROOT, 'include')}", str(prog), "-o", str(exe)],
+                   check=True)
+    vals = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True,
+                                           check=True).stdout.split()]
+    O, R, I = gpl1.GPOpts, gpl1.GPResult, gpl1.GPInstance
+    want = [C.sizeof(O), C.sizeof(R), C.sizeof(I),
+            O.theta.offset, O.M_alpha.offset, O.f_target.offset, O.chunk.offset,
+            O.fused_grid.offset, R.f.offset, R.lambda_est.offset, R.l1norm.offset,
+            I.n.offset, I.rho.offset]
+    assert vals == want
+
+
+def test_defaults_are_the_papers_gpss_parameters():
+    o = gpl1.default_opts()
+    # M = 1 (monotone), theta = 0.5, beta = 1e-4, alpha_min = 1e-10,
+    # alpha_max = 1e10, tau_1 = 0.5, M_alpha = 2 (end of Section 3)
+    assert (o.M, o.theta, o.beta, o.alpha_min, o.alpha_max, o.tau1, o.M_alpha) == \
+        (1, 0.5, 1e-4, 1e-10, 1e10, 0.5, 2)
+    assert o.backtrack_cap == 60 and o.f_target < 0 and o.refresh_every == 0
+    with pytest.raises(TypeError):
+        gpl1.default_opts(no_such_option=1)
+
+
+def test_null_handle_is_rejected_without_gpu_work():
+    lib = gpl1.load()
+    assert lib.gp_last_error(None) == b"null handle"
+    res = gpl1.GPResult()
+    assert lib.gp_l1_solve(None, 1, None, 1, 1, 1, None, 1.0, None, 0.0, None, None,
+                           C.byref(res), None) == -1
+    assert lib.gp_destroy(None) == 0
+    assert lib.gp_l1_project(None, 0, None, 0, 1.0, None, None, None) == -1

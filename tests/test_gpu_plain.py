@@ -1,0 +1,276 @@
+"""GPU parity of the projection and the plain GPSS solver against the FP64
+oracle, through the C ABI.
+
+Tolerances (stated per dtype):
+  * projection: FP64 vectors 1e-12 relative to max|v| (the threshold comes
+    from a different summation order); FP32 vectors: output rounded to FP32,
+    4 ulp of max|v|.
+  * FP64 solver: relative objective gap <= 1e-10 and
+    ||x - x_oracle|| / ||x_oracle|| <= 1e-6.  Both runs stop at the FP64
+    stationarity floor, where either is ~1e-8 from the exact minimiser.
+  * FP32 / BF16-storage solver: gap <= 1e-6 and x error <= 1e-4 against the
+    oracle run on the same stored K (widened to FP64).
+The gap is (f(x) - f*)/f* with f(x) recomputed in FP64 on the CPU from the
+returned x, and f* the oracle's objective at its tight run.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import gpss, project_l1_mu
+from paper_0902_4424_amd import gpl1, instances
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def H():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    h = gpl1.Handle(0)
+    yield h
+    h.close()
+
+
+def _dev(a, dtype=None):
+    t = torch.from_numpy(np.ascontiguousarray(a))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.to(DEV)
+
+
+def _K_tensor(inst):
+    if inst.dtype == "bf16":
+        return _dev(inst.K_store.view(np.int16))
+    return _dev(inst.K_store)
+
+
+def _gap_err(inst, x, ref):
+    K, y = inst.K64, inst.y64
+    x = np.asarray(x, dtype=np.float64)
+    fx = float(np.sum((K @ x - y) ** 2))
+    gap = (fx - ref["f"]) / ref["f"]
+    err = np.linalg.norm(x - ref["x"]) / max(np.linalg.norm(ref["x"]), 1e-300)
+    return gap, err, fx
+
+
+# ---------------------------------------------------------------------------
+# projection
+# ---------------------------------------------------------------------------
+PROJ_CASES = [
+    # (p, scale of rho relative to ||v||_1, kind)
+    (1, 0.5, "gauss"), (7, 0.3, "gauss"), (1000, 0.1, "gauss"), (1025, 0.5, "gauss"),
+    (4096, 0.05, "ties"), (16384, 0.2, "wide"), (16384, 2.0, "gauss"),
+    (40000, 0.3, "gauss"), (3000, 0.0, "gauss"), (5000, 1e-9, "wide"),
+    (2048, 0.5, "zeros"),
+]
+
+
+@pytest.mark.parametrize("p,frac,kind", PROJ_CASES)
+@pytest.mark.parametrize("vdt", ["f64", "f32"])
+def test_projection_matches_oracle(H, p, frac, kind, vdt):
+    say(f"[proj] p={p} frac={frac} kind={kind} dtype={vdt}")
+    rng = np.random.default_rng(p + int(frac * 1000))
+    v = rng.standard_normal(p)
+    if kind == "wide":
+        v *= np.exp(rng.uniform(-12, 12, p))
+    elif kind == "ties":
+        v = rng.choice([-2.0, -1.0, 0.5, 1.0, 3.0], size=p)
+    elif kind == "zeros":
+        v[rng.random(p) < 0.7] = 0.0
+    if vdt == "f32":
+        v = v.astype(np.float32).astype(np.float64)
+    rho = frac * np.abs(v).sum()
+    want, mu_want = project_l1_mu(v, rho)
+    vt = _dev(v, torch.float64 if vdt == "f64" else torch.float32)
+    h, mu = H.project(vt, rho)
+    got = h.cpu().double().numpy()
+    scale = max(np.abs(v).max(), 1e-300)
+    tol = 1e-12 * scale if vdt == "f64" else 4 * np.finfo(np.float32).eps * scale
+    assert np.abs(got - want).max() <= tol
+    assert abs(mu - mu_want) <= 1e-12 * scale
+    assert np.abs(got).sum() <= rho * (1 + 1e-6) + 1e-300
+
+
+def test_projection_inplace_and_empty(H):
+    say("[proj] in-place and p=0")
+    v = torch.tensor([3.0, 1.0], dtype=torch.float64, device=DEV)
+    H.project(v, 1.0, out=v)
+    assert v.cpu().tolist() == [1.0, 0.0]
+    e = torch.empty(0, dtype=torch.float64, device=DEV)
+    _, mu = H.project(e, 1.0)
+    assert mu == 0.0
+    with pytest.raises(gpl1.GPError):
+        H.project(v, -1.0)
+
+
+# ---------------------------------------------------------------------------
+# hand-derived trajectories (same fixtures as the oracle pins)
+# ---------------------------------------------------------------------------
+def test_hand_examples_on_gpu(H):
+    say("[solve] hand examples 2x2")
+    for K, y, rho, iters, want in (
+            ([[1.0, 0.0], [0.0, 0.5]], [1.0, 1.0], 100.0, 1, [1.0, 0.5]),
+            ([[1.0, 0.0], [0.0, 0.5]], [1.0, 1.0], 100.0, 2, [1.0, 16 / 17]),
+            ([[1.0, 0.0], [0.0, 0.1]], [1.0, 100.0], 1000.0, 2, [190.1 / 101, 2099 / 101]),
+            ([[2.0]], [1.0], 10.0, 1, [0.5])):
+        Kt = _dev(np.array(K))
+        yt = _dev(np.array(y))
+        x, res = H.solve(Kt, yt, rho, tol=0.0, max_iter=iters)
+        np.testing.assert_allclose(x.cpu().numpy(), want, rtol=1e-13)
+        assert res["iters"] == iters
+
+
+# ---------------------------------------------------------------------------
+# full solves
+# ---------------------------------------------------------------------------
+def test_fp64_gaussian_256x1024(H):
+    say("[solve] gauss 256x1024 f64 tol=0 (stationary)")
+    inst = instances.plain_small(seed=1, dtype="f64")
+    ref = gpss(inst.K64, inst.y64, inst.rho, tol=0.0, max_iter=100000)
+    x, res = H.solve(_K_tensor(inst), _dev(inst.y_store), inst.rho, tol=0.0)
+    gap, err, fx = _gap_err(inst, x.cpu().numpy(), ref)
+    say(f"   gpu iters={res['iters']} status={res['status_name']} oracle iters={ref['iters']} "
+        f"gap={gap:.2e} err={err:.2e}")
+    assert res["status_name"] == "stationary"
+    assert gap <= 1e-10 and err <= 1e-6
+    assert abs(res["f"] - fx) <= 1e-9 * fx
+    assert res["l1norm"] <= inst.rho * (1 + 1e-12)
+    lam = np.abs(inst.K64.T @ (inst.y64 - inst.K64 @ x.cpu().numpy())).max()
+    assert res["lambda_est"] == pytest.approx(lam, rel=1e-6)
+
+
+def test_fp64_tol_stop_matches_oracle_iteration_count(H):
+    say("[solve] gauss 256x1024 f64 tol=1e-10")
+    inst = instances.plain_small(seed=1, dtype="f64")
+    ref = gpss(inst.K64, inst.y64, inst.rho, tol=1e-10)
+    x, res = H.solve(_K_tensor(inst), _dev(inst.y_store), inst.rho, tol=1e-10)
+    assert res["status_name"] == "ok_tol"
+    # same trajectory up to rounding: the stop lands within a few iterations
+    assert abs(res["iters"] - ref["iters"]) <= 5
+    gap, err, _ = _gap_err(inst, x.cpu().numpy(), ref)
+    assert abs(gap) <= 1e-8
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_reduced_precision_gaussian(H, dtype):
+    say(f"[solve] gauss 1024x4096 {dtype}")
+    inst = instances.gaussian_instance(1024, 4096, 50, amp="pm1", sigma=1e-2, dtype=dtype,
+                                       seed=21)
+    ref = gpss(inst.K64, inst.y64, inst.rho, tol=0.0, max_iter=100000)
+    x, res = H.solve(_K_tensor(inst), _dev(inst.y_store), inst.rho, tol=1e-12,
+                     refresh_every=50, max_iter=5000)
+    gap, err, _ = _gap_err(inst, x.cpu().numpy(), ref)
+    say(f"   gpu iters={res['iters']} status={res['status_name']} oracle iters={ref['iters']} "
+        f"gap={gap:.2e} err={err:.2e}")
+    assert gap <= 1e-6 and err <= 1e-4
+
+
+def test_fp32_illconditioned(H):
+    say("[solve] illcond 512 f32, 2000 iterations")
+    inst = instances.plain_illcond(seed=3, dtype="f32", m=512)
+    ref = gpss(inst.K64, inst.y64, inst.rho, tol=0.0, max_iter=2000)
+    x, res = H.solve(_K_tensor(inst), _dev(inst.y_store), inst.rho, tol=0.0, max_iter=2000,
+                     refresh_every=50)
+    gap, err, _ = _gap_err(inst, x.cpu().numpy(), ref)
+    tight = gpss(inst.K64, inst.y64, inst.rho, tol=0.0, max_iter=50000)
+    g_gpu = (np.sum((inst.K64 @ x.cpu().numpy() - inst.y64) ** 2) - tight["f"]) / tight["f"]
+    g_ora = (ref["f"] - tight["f"]) / tight["f"]
+    say(f"   gpu gap={g_gpu:.2e} oracle gap={g_ora:.2e} at 2000 iterations")
+    # ill-conditioned: both at a fixed budget; the GPU must be as close to f*
+    # as the oracle is, within a factor 10 (or both at the 1e-6 target)
+    assert g_gpu <= max(10 * g_ora, 1e-6)
+
+
+@pytest.mark.parametrize("p", [1, 3, 1001, 4097])
+def test_ragged_and_padded_shapes(H, p):
+    say(f"[solve] ragged p={p}")
+    n = 37
+    inst = instances.gaussian_instance(n, p, min(3, p), dtype="f32", seed=100 + p)
+    ref = gpss(inst.K64, inst.y64, inst.rho, tol=1e-13, max_iter=20000)
+    # padded leading dimension (ldk = p + 3) exercises the unaligned loads
+    Kp = np.zeros((n, p + 3), dtype=np.float32)
+    Kp[:, :p] = inst.K_store
+    Kt = _dev(Kp)[:, :p]
+    x, res = H.solve(Kt, _dev(inst.y_store), inst.rho, tol=1e-13, max_iter=20000)
+    gap, err, _ = _gap_err(inst, x.cpu().numpy(), ref)
+    assert gap <= 1e-6
+    x2, _ = H.solve(_dev(inst.K_store), _dev(inst.y_store), inst.rho, tol=1e-13, max_iter=20000)
+    g2, _, _ = _gap_err(inst, x2.cpu().numpy(), ref)
+    assert g2 <= 1e-6
+
+
+def test_special_cases(H):
+    say("[solve] special cases")
+    inst = instances.gaussian_instance(64, 256, 5, dtype="f64", seed=9)
+    K, y = _K_tensor(inst), _dev(inst.y_store)
+    x, res = H.solve(K, y, 0.0)
+    assert res["status_name"] == "stationary" and not x.any().item()
+    x, res = H.solve(K, torch.zeros_like(y), 2.0)
+    assert res["status_name"] == "stationary" and res["iters"] == 0
+    x0 = _dev(np.random.default_rng(0).standard_normal(256) * 10)
+    x, res = H.solve(K, y, 1.0, x0=x0, max_iter=1, tol=0.0)
+    assert res["projected_x0"] == 1 and res["l1norm"] <= 1.0 + 1e-12
+    x, res = H.solve(K, y, 1.0, max_iter=0)
+    assert res["status_name"] == "max_iter" and res["iters"] == 0
+    ref = gpss(inst.K64, inst.y64, 1.0, max_iter=3, tol=0.0)
+    x, res = H.solve(K, y, 1.0, max_iter=3, tol=0.0)
+    np.testing.assert_allclose(x.cpu().numpy(), ref["x"], atol=1e-12)
+    # warm start from the oracle's answer stops almost at once
+    ref = gpss(inst.K64, inst.y64, inst.rho, tol=0.0)
+    x, res = H.solve(K, y, inst.rho, x0=_dev(ref["x"]), tol=1e-12)
+    assert res["iters"] <= 3
+    # f_target stop
+    x, res = H.solve(K, y, inst.rho, tol=0.0, f_target=ref["f"] * 1.01)
+    assert res["status_name"] == "reached_target" and res["f"] <= ref["f"] * 1.01
+
+
+def test_errors(H):
+    say("[solve] argument errors and non-finite data")
+    inst = instances.gaussian_instance(16, 32, 2, dtype="f64", seed=2)
+    K, y = _K_tensor(inst), _dev(inst.y_store)
+    for bad in (dict(rho=-1.0), dict(rho=float("nan")), dict(tol=-1.0)):
+        kw = dict(rho=1.0, tol=1e-10)
+        kw.update(bad)
+        with pytest.raises(gpl1.GPError) as e:
+            H.solve(K, y, kw["rho"], tol=kw["tol"])
+        assert e.value.code == -1
+    with pytest.raises(gpl1.GPError):
+        H.solve(K, y, 1.0, M=0)
+    ybad = y.clone()
+    ybad[3] = float("nan")
+    with pytest.raises(gpl1.GPError) as e:
+        H.solve(K, ybad, 1.0)
+    assert e.value.code == -2
+    # the handle still works after an error
+    x, res = H.solve(K, y, 1.0)
+    assert res["status"] >= 0
+
+
+def test_deterministic(H):
+    say("[solve] determinism")
+    inst = instances.gaussian_instance(512, 2048, 20, dtype="f32", seed=5)
+    K, y = _K_tensor(inst), _dev(inst.y_store)
+    a, ra = H.solve(K, y, inst.rho, tol=0.0, max_iter=200)
+    b, rb = H.solve(K, y, inst.rho, tol=0.0, max_iter=200)
+    assert torch.equal(a, b) and ra == rb
+
+
+def test_nonmonotone_memory(H):
+    say("[solve] M=5 non-monotone line search")
+    inst = instances.plain_small(seed=1, dtype="f64")
+    from oracle import GPSSParams
+    ref = gpss(inst.K64, inst.y64, inst.rho, tol=0.0, params=GPSSParams(M=5))
+    x, res = H.solve(_K_tensor(inst), _dev(inst.y_store), inst.rho, tol=0.0, M=5)
+    gap, err, _ = _gap_err(inst, x.cpu().numpy(), ref)
+    assert gap <= 1e-10 and err <= 1e-6
