@@ -1,0 +1,208 @@
+#!/usr/bin/env python3
+"""Benchmark of the plain GPSS solver on MI355X.
+
+Workload: Gaussian compressed sensing, K 4096 x 16384 stored in FP32
+(N(0, 1/4096) entries, 256 MiB), x_true 400-sparse with N(0,1) amplitudes,
+noise sigma = 1e-2, rho = 0.9 ||x_true||_1, x0 = 0, exactly 500 iterations
+per solve (residual refreshed every 50).  One step = one full solve.
+Inputs are resident in HBM before the timed region starts.
+
+Prints ONE JSON line: iterations/s (whole job), the fused K/K^T kernel's
+roofline (algorithmic bytes per launch / its HIP-event-timed duration inside
+the timed solves), wall time to a 1e-6 relative objective gap, parity of the
+returned x against the FP64 CPU oracle, and the oracle's own iteration rate
+on this host as a reported CPU baseline.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+ITERS = 500
+REFRESH = 50
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fused_traffic_gauss_4096x16384.json")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_0902_4424_amd", "csrc", f)
+                  for f in ("gp_kernels.hpp", "gp_device.hpp")]
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def kernel_hash():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per fused launch from committed rocprofv3 counter runs,
+    valid only while the kernel sources are unchanged."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_hash") != kernel_hash():
+        return None
+    return t.get("bytes_per_launch")
+
+
+def blas_threads():
+    try:
+        from threadpoolctl import threadpool_info
+        n = [i.get("num_threads") for i in threadpool_info() if i.get("user_api") == "blas"]
+        if n:
+            return int(max(n))
+    except Exception:
+        pass
+    return os.cpu_count()
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-gap", action="store_true", help="skip the time-to-gap leg")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this solver runs on one GPU; --gpus {args.gpus} is not supported "
+              "(independent problems shard across GPUs without exchange, see the design notes)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_0902_4424_amd import gpl1, instances
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    t = time.time()
+    inst = instances.plain_large(seed=2, dtype="f32")
+    n, p = inst.n, inst.p
+    log(f"instance {inst.name}: n={n} p={p} rho={inst.rho:.4f} ({time.time() - t:.1f}s)")
+    K = torch.from_numpy(inst.K_store).to(dev)
+    y = torch.from_numpy(inst.y_store).to(dev)
+    torch.cuda.synchronize()
+    H = gpl1.Handle(0)
+    opts = gpl1.default_opts(max_iter=ITERS, refresh_every=REFRESH, profile=1)
+
+    for i in range(args.warmup):
+        H.solve(K, y, inst.rho, tol=0.0, opts=opts)
+        log(f"warmup {i} done")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    results = []
+    for _ in range(args.steps):
+        x, res = H.solve(K, y, inst.rho, tol=0.0, opts=opts)
+        results.append(res)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    elapsed = t1 - t0
+    iters = sum(r["iters"] for r in results)
+    value = iters / elapsed
+    ms_per_step = 1e3 * elapsed / args.steps
+    fused_ms = sum(r["t_fused_ms"] for r in results)
+    fused_n = sum(r["n_fused"] for r in results)
+    avg_fused_s = fused_ms / max(fused_n, 1) / 1e3
+    # algorithmic bytes of one fused launch: K once, d (p doubles) in,
+    # q (n doubles) out, r (n doubles) in, w (p floats) out
+    alg_bytes = n * p * 4 + 8 * p + 16 * n + 4 * p
+    achieved = alg_bytes / avg_fused_s / 1e9
+    log(f"timed: {args.steps} solves, {iters} iterations in {elapsed:.3f}s -> {value:.1f} it/s; "
+        f"fused avg {avg_fused_s * 1e6:.1f} us -> {achieved:.0f} GB/s")
+    x_gpu = x.cpu().double().numpy()
+    status = results[-1]["status_name"]
+
+    out = {
+        "metric": "GP iterations/s (plain GPSS, FP32 K, FP64 scalars)",
+        "value": round(value, 2),
+        "unit": "iterations/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded Gaussian compressed-sensing instance)",
+        "config": {"workload": "plain GPSS, Gaussian K 4096x16384 fp32, 400-sparse x, "
+                               "sigma 1e-2, rho 0.9||x||_1, 500 iterations/solve",
+                   "n": n, "p": p, "iterations_per_step": ITERS, "refresh_every": REFRESH,
+                   "status": status,
+                   "threshold_passes_per_iter": round(results[-1]["proj_passes"] /
+                                                      max(results[-1]["iters"], 1), 2)},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": measured_traffic(),
+                     "kernel": "k_fused (K d and K^T (K d), one read of K)",
+                     "alg_bytes_per_launch": alg_bytes,
+                     "avg_launch_us": round(avg_fused_s * 1e6, 2)},
+    }
+
+    # ---- wall time to a 1e-6 relative objective gap ----------------------
+    K64 = y64 = None
+    if not args.no_gap:
+        K64 = inst.K64
+        y64 = inst.y64
+        xl, rl = H.solve(K, y, inst.rho, tol=0.0, max_iter=3000, refresh_every=REFRESH)
+        xl = xl.cpu().double().numpy()
+        rl64 = K64 @ xl - y64
+        f_ref = float(rl64 @ rl64)
+        g = 2.0 * (K64.T @ rl64)
+        fw = float(g @ xl + inst.rho * np.abs(g).max())
+        target = f_ref * (1 + 1e-6)
+        gopts = gpl1.default_opts(max_iter=20000, refresh_every=REFRESH, f_target=target, chunk=16)
+        H.solve(K, y, inst.rho, tol=0.0, opts=gopts)       # warm
+        torch.cuda.synchronize()
+        tg0 = time.perf_counter()
+        xg, rg = H.solve(K, y, inst.rho, tol=0.0, opts=gopts)
+        torch.cuda.synchronize()
+        tg = time.perf_counter() - tg0
+        xg = xg.cpu().double().numpy()
+        fg = float(np.sum((K64 @ xg - y64) ** 2))
+        out["time_to_gap_1e-6"] = {
+            "seconds": round(tg, 5), "iterations": rg["iters"], "status": rg["status_name"],
+            "gap_vs_ref": (fg - f_ref) / f_ref,
+            "f_ref_source": "3000-iteration GPU run, f recomputed in FP64 on the host",
+            "f_ref_frank_wolfe_bound_rel": fw / f_ref}
+        log(f"time to 1e-6 gap: {tg * 1e3:.2f} ms, {rg['iters']} iterations, "
+            f"gap {(fg - f_ref) / f_ref:.2e} (FW bound of ref {fw / f_ref:.1e})")
+
+    # ---- CPU oracle baseline + parity at 500 iterations --------------------
+    if not args.no_cpu_baseline:
+        from oracle import gpss
+        if K64 is None:
+            K64, y64 = inst.K64, inst.y64
+        threads = blas_threads()
+        tc0 = time.perf_counter()
+        ref = gpss(K64, y64, inst.rho, tol=0.0, max_iter=ITERS)
+        tc = time.perf_counter() - tc0
+        out["cpu_baseline"] = {"value": round(ref["iters"] / tc, 3), "unit": "iterations/s",
+                               "cores": threads, "kind": "oracle",
+                               "sample": f"one full {ITERS}-iteration FP64 numpy solve of the "
+                                         f"same stored instance ({tc:.1f} s)"}
+        fx = float(np.sum((K64 @ x_gpu - y64) ** 2))
+        out["parity"] = {"rel_objective_diff_vs_oracle_500": (fx - ref["f"]) / ref["f"],
+                         "x_rel_err_vs_oracle_500":
+                             float(np.linalg.norm(x_gpu - ref["x"]) / np.linalg.norm(ref["x"])),
+                         "oracle_status": ref["status"], "oracle_iters": ref["iters"]}
+        log(f"cpu oracle: {ref['iters'] / tc:.2f} it/s on {threads} threads; parity "
+            f"{out['parity']}")
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

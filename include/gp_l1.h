@@ -78,6 +78,8 @@ typedef struct {
     int32_t chunk;        /* iterations enqueued between host status polls     */
     int32_t fused_cfg;    /* tuning: fused K/K^T kernel shape, 1..6 (0 = automatic) */
     int32_t fused_grid;   /* tuning: workgroups (row slabs) of that kernel (0 = automatic) */
+    int32_t profile;      /* 1: time every fused K/K^T launch with HIP events (result.t_fused_ms) */
+    int32_t reserved;
 } gp_opts;
 
 typedef struct {
@@ -89,6 +91,9 @@ typedef struct {
     double rel_change;    /* (f_prev - f)/f_prev of the last update            */
     double lambda_est;    /* ||K^T (y - K x)||_inf: the lambda paired with rho (Section 1) */
     double l1norm;        /* ||x||_1                                           */
+    double t_fused_ms;    /* with opts.profile: summed duration of the fused launches */
+    int32_t n_fused;      /* with opts.profile: number of fused launches timed  */
+    int32_t proj_passes;  /* threshold-search passes summed over the iterations */
 } gp_result;
 
 typedef struct gp_handle_s* gp_handle;

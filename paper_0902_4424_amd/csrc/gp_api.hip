@@ -62,6 +62,27 @@ int ensure_workspace(gp_handle h, size_t bytes) {
     return GP_OK_TOL;
 }
 
+hipEvent_t prof_event(gp_handle h) {
+    if (h->ev_used == (int)h->events.size()) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        h->events.push_back(e);
+    }
+    return h->events[h->ev_used++];
+}
+
+double prof_collect(gp_handle h, int* pairs) {
+    double ms = 0.0;
+    int np = 0;
+    for (int i = 0; i + 1 < h->ev_used; i += 2) {
+        float t = 0.f;
+        if (hipEventElapsedTime(&t, h->events[i], h->events[i + 1]) == hipSuccess) { ms += t; ++np; }
+    }
+    h->ev_used = 0;
+    if (pairs) *pairs = np;
+    return ms;
+}
+
 GPParams make_params(const gp_opts& o, double rho, double tol) {
     GPParams P;
     P.theta = o.theta;
@@ -132,27 +153,28 @@ int64_t pick_fused_grid(int64_t n, int64_t p, gp_dtype dt, int want) {
     return std::max<int64_t>(1, std::min(g, n));
 }
 
+// Arguments of one fused launch (see k_fused).
+struct FusedArgs {
+    const GPState* st; const void* K; int64_t n, p, ldk, rows;
+    const double *v, *vsub, *g, *ysub, *rvec; double* tout; void* wpart; int64_t ldw; double* spart;
+};
+
 template <typename TK, typename ACC, int T, int CPT, int RB>
-void launch_fused_t(bool aligned, hipStream_t s, int64_t G, const GPState* st, const void* K, int64_t n,
-                    int64_t p, int64_t ldk, int64_t rows, const double* v, const double* ysub,
-                    const double* rvec, double* tout, void* wpart, int64_t ldw, double* spart) {
+void launch_fused_t(bool aligned, hipStream_t s, int64_t G, const FusedArgs& a) {
     if (aligned)
-        hipLaunchKernelGGL((k_fused<TK, ACC, T, CPT, RB, true>), dim3((unsigned)G), dim3(T), 0, s, st,
-                           (const TK*)K, n, p, ldk, rows, v, ysub, rvec, tout, (ACC*)wpart, ldw, spart);
+        hipLaunchKernelGGL((k_fused<TK, ACC, T, CPT, RB, true>), dim3((unsigned)G), dim3(T), 0, s, a.st,
+                           (const TK*)a.K, a.n, a.p, a.ldk, a.rows, a.v, a.vsub, a.g, a.ysub, a.rvec, a.tout,
+                           (ACC*)a.wpart, a.ldw, a.spart);
     else
-        hipLaunchKernelGGL((k_fused<TK, ACC, T, CPT, RB, false>), dim3((unsigned)G), dim3(T), 0, s, st,
-                           (const TK*)K, n, p, ldk, rows, v, ysub, rvec, tout, (ACC*)wpart, ldw, spart);
+        hipLaunchKernelGGL((k_fused<TK, ACC, T, CPT, RB, false>), dim3((unsigned)G), dim3(T), 0, s, a.st,
+                           (const TK*)a.K, a.n, a.p, a.ldk, a.rows, a.v, a.vsub, a.g, a.ysub, a.rvec, a.tout,
+                           (ACC*)a.wpart, a.ldw, a.spart);
 }
 
 template <typename TK, typename ACC>
-void launch_fused_dt(int cfg, bool aligned, hipStream_t s, int64_t G, const GPState* st, const void* K,
-                     int64_t n, int64_t p, int64_t ldk, int64_t rows, const double* v, const double* ysub,
-                     const double* rvec, double* tout, void* wpart, int64_t ldw, double* spart) {
-#define GPL1_FUSED_CASE(i, T, C, R)                                                                       \
-    case i:                                                                                              \
-        launch_fused_t<TK, ACC, T, C, R>(aligned, s, G, st, K, n, p, ldk, rows, v, ysub, rvec, tout, wpart, \
-                                         ldw, spart);                                                    \
-        break;
+void launch_fused_dt(int cfg, bool aligned, hipStream_t s, int64_t G, const FusedArgs& a) {
+#define GPL1_FUSED_CASE(i, T, C, R) \
+    case i: launch_fused_t<TK, ACC, T, C, R>(aligned, s, G, a); break;
     switch (cfg) {
         GPL1_FUSED_CASE(0, 256, 1, 4)
         GPL1_FUSED_CASE(1, 256, 2, 4)
@@ -164,29 +186,20 @@ void launch_fused_dt(int cfg, bool aligned, hipStream_t s, int64_t G, const GPSt
 #undef GPL1_FUSED_CASE
 }
 
-void launch_fused(gp_dtype dt, int cfg, bool aligned, hipStream_t s, int64_t G, const GPState* st,
-                  const void* K, int64_t n, int64_t p, int64_t ldk, int64_t rows, const double* v,
-                  const double* ysub, const double* rvec, double* tout, void* wpart, int64_t ldw,
-                  double* spart) {
-    if (dt == GP_F64)
-        launch_fused_dt<double, double>(cfg, aligned, s, G, st, K, n, p, ldk, rows, v, ysub, rvec, tout, wpart,
-                                        ldw, spart);
-    else if (dt == GP_F32)
-        launch_fused_dt<float, float>(cfg, aligned, s, G, st, K, n, p, ldk, rows, v, ysub, rvec, tout, wpart,
-                                      ldw, spart);
-    else
-        launch_fused_dt<bf16_t, float>(cfg, aligned, s, G, st, K, n, p, ldk, rows, v, ysub, rvec, tout, wpart,
-                                       ldw, spart);
+void launch_fused(gp_dtype dt, int cfg, bool aligned, hipStream_t s, int64_t G, const FusedArgs& a) {
+    if (dt == GP_F64) launch_fused_dt<double, double>(cfg, aligned, s, G, a);
+    else if (dt == GP_F32) launch_fused_dt<float, float>(cfg, aligned, s, G, a);
+    else launch_fused_dt<bf16_t, float>(cfg, aligned, s, G, a);
 }
 
 int proj_vpt(int64_t p) {
+    // register slots per thread (pairs of neighbours, so at least 2)
     const int64_t per = (p + PROJ_T - 1) / PROJ_T;
-    if (per <= 1) return 1;
     if (per <= 2) return 2;
     if (per <= 4) return 4;
     if (per <= 8) return 8;
     if (per <= 16) return 16;
-    if (per <= 32) return 32;
+    if (per <= 22) return 22;
     return 0;
 }
 
@@ -195,28 +208,27 @@ void launch_proj(hipStream_t s, GPState* st, int mode, int64_t p, double* x, con
     switch (proj_vpt(p)) {
 #define GPL1_PROJ_CASE(V) \
     case V: hipLaunchKernelGGL(k_proj<V>, dim3(1), dim3(PROJ_T), 0, s, st, mode, p, x, g, dout, upart, GU, vbuf); break;
-        GPL1_PROJ_CASE(1)
         GPL1_PROJ_CASE(2)
         GPL1_PROJ_CASE(4)
         GPL1_PROJ_CASE(8)
         GPL1_PROJ_CASE(16)
-        GPL1_PROJ_CASE(32)
+        GPL1_PROJ_CASE(22)
         GPL1_PROJ_CASE(0)
 #undef GPL1_PROJ_CASE
     }
 }
 
 void launch_update(gp_dtype dt, hipStream_t s, GPState* st, int mode, const double* spart, int GF,
-                   const void* wpart, int64_t ldw, int64_t p, int64_t n, double* x, double* g, const double* d,
+                   const void* wpart, int64_t ldw, int64_t p, int64_t n, double* x, double* g, const double* h,
                    double* r, const double* tq, double* upart) {
     const int nbp = (int)((p + UPD_COLS - 1) / UPD_COLS);
     const int nbn = (int)((n + UPD_ROWS - 1) / UPD_ROWS);
     if (dt == GP_F64)
         hipLaunchKernelGGL(k_update<double>, dim3(nbp + nbn), dim3(UPD_T), 0, s, st, mode, spart, GF,
-                           (const double*)wpart, ldw, p, n, nbp, x, g, d, r, tq, upart);
+                           (const double*)wpart, ldw, p, n, nbp, x, g, h, r, tq, upart);
     else
         hipLaunchKernelGGL(k_update<float>, dim3(nbp + nbn), dim3(UPD_T), 0, s, st, mode, spart, GF,
-                           (const float*)wpart, ldw, p, n, nbp, x, g, d, r, tq, upart);
+                           (const float*)wpart, ldw, p, n, nbp, x, g, h, r, tq, upart);
 }
 
 template <typename TV>
@@ -253,7 +265,7 @@ Plan plan_single(gp_dtype dt, int64_t n, int64_t p, const gp_opts& o) {
     P.o_r = take(sizeof(double) * n);
     P.o_q = take(sizeof(double) * n);
     P.o_y = take(sizeof(double) * n);
-    P.o_spart = take(sizeof(double) * 2 * P.G);
+    P.o_spart = take(sizeof(double) * SPART * P.G);
     P.o_upart = take(sizeof(double) * 4 * P.GU);
     P.o_wpart = take((size_t)wsz * P.ldw * P.G);
     P.bytes = off;
@@ -284,6 +296,7 @@ void gp_opts_default(gp_opts* o) {
     o->chunk = 64;
     o->fused_cfg = 0;
     o->fused_grid = 0;
+    o->profile = 0;
 }
 
 int gp_create(gp_handle* out, int device) {
@@ -310,6 +323,7 @@ int gp_destroy(gp_handle h) {
     (void)hipSetDevice(h->device);
     if (h->ws) (void)hipFree(h->ws);
     if (h->host_state) (void)hipHostFree(h->host_state);
+    for (hipEvent_t ev : h->events) (void)hipEventDestroy(ev);
     delete h;
     return GP_OK_TOL;
 }
@@ -410,9 +424,11 @@ int gp_l1_solve(gp_handle h, gp_dtype kdtype, const void* K, int64_t n, int64_t 
     else { launch_to_f64<float>(s, y, y64, n); launch_to_f64<float>(s, x0, x, p); }
     if (x0) launch_proj(s, st, PM_INIT_X0, p, x, nullptr, nullptr, nullptr, 0, vb);
     // r = K x - y, g = 2 K^T r, f = ||r||^2
+    // d holds h = P(x - alpha g) between the projection and the update
+    const FusedArgs fa_refresh{st, K, n, p, ldk, P.rows, x, nullptr, nullptr, y64, nullptr, q, wpart, P.ldw, spart};
+    const FusedArgs fa_iter{st, K, n, p, ldk, P.rows, d, x, g, nullptr, r, q, wpart, P.ldw, spart};
     auto refresh = [&]() {
-        launch_fused(kdtype, P.cfg, aligned, s, P.G, st, K, n, p, ldk, P.rows, x, y64, nullptr, q, wpart, P.ldw,
-                     spart);
+        launch_fused(kdtype, P.cfg, aligned, s, P.G, fa_refresh);
         launch_update(kdtype, s, st, UM_REFRESH, spart, (int)P.G, wpart, P.ldw, p, n, x, g, d, r, q, upart);
     };
     refresh();
@@ -425,8 +441,11 @@ int gp_l1_solve(gp_handle h, gp_dtype kdtype, const void* K, int64_t n, int64_t 
         const int end = std::min(o.max_iter, it + o.chunk);
         for (; it < end; ++it) {
             launch_proj(s, st, PM_ITER, p, x, g, d, upart, P.GU, vb);
-            launch_fused(kdtype, P.cfg, aligned, s, P.G, st, K, n, p, ldk, P.rows, d, nullptr, r, q, wpart,
-                         P.ldw, spart);
+            hipEvent_t e0 = o.profile ? prof_event(h) : nullptr;
+            if (e0) (void)hipEventRecord(e0, s);
+            launch_fused(kdtype, P.cfg, aligned, s, P.G, fa_iter);
+            hipEvent_t e1 = e0 ? prof_event(h) : nullptr;
+            if (e1) (void)hipEventRecord(e1, s);
             launch_update(kdtype, s, st, UM_ITER, spart, (int)P.G, wpart, P.ldw, p, n, x, g, d, r, q, upart);
             if (o.refresh_every > 0 && (it + 1) % o.refresh_every == 0 && it + 1 < o.max_iter) refresh();
         }
@@ -446,6 +465,7 @@ int gp_l1_solve(gp_handle h, gp_dtype kdtype, const void* K, int64_t n, int64_t 
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(h, e, "final sync");
     fill_result(*h->host_state, res);
+    if (o.profile) res->t_fused_ms = prof_collect(h, &res->n_fused);
     if (res->status < 0) return fail(h, res->status, "solve ended with a non-finite value");
     return res->status;
 }
@@ -462,5 +482,6 @@ void fill_result(const GPState& s, gp_result* res) {
     res->rel_change = s.rel;
     res->lambda_est = s.gmax / 2.0;
     res->l1norm = s.l1;
+    res->proj_passes = s.michelot_total;
 }
 }  // namespace gpl1

@@ -4,8 +4,8 @@
 //
 // Determinism: every reduction below combines values in a fixed order that
 // does not depend on scheduling, so two runs on the same inputs give
-// bit-identical scalars.  The xor butterfly leaves the same value in every
-// lane because IEEE addition is commutative.
+// bit-identical scalars.  The symmetric lane pairings leave the same value in
+// every lane because IEEE addition is commutative.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -92,25 +92,67 @@ __device__ __forceinline__ void load_kvec(const TK* rowp, int64_t col, int64_t p
 // ---------------------------------------------------------------------------
 // Reductions
 // ---------------------------------------------------------------------------
+// Wave reductions with DPP lane permutes (VALU, no LDS round trip):
+// quad_perm xor 1 and xor 2, row_half_mirror and row_mirror leave the sum of
+// each 16-lane row in all of its lanes; the four row sums are then read with
+// v_readlane and added in a fixed order, so every lane holds the same total.
+// Requires all 64 lanes active.
+constexpr int DPP_XOR1 = 0xB1;          // quad_perm [1,0,3,2]
+constexpr int DPP_XOR2 = 0x4E;          // quad_perm [2,3,0,1]
+constexpr int DPP_HALF_MIRROR = 0x141;  // lane i <-> 7-i within 8
+constexpr int DPP_MIRROR = 0x140;       // lane i <-> 15-i within 16
+
+template <int CTRL>
+__device__ __forceinline__ int dpp_i(int v) {
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+    const int lo = dpp_i<CTRL>(__double2loint(v));
+    const int hi = dpp_i<CTRL>(__double2hiint(v));
+    return __hiloint2double(hi, lo);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float v) {
+    return __int_as_float(dpp_i<CTRL>(__float_as_int(v)));
+}
+__device__ __forceinline__ double readlane_d(double v, int lane) {
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), lane),
+                            __builtin_amdgcn_readlane(__double2loint(v), lane));
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int m = 1; m < WAVE; m <<= 1) v += __shfl_xor(v, m, WAVE);
-    return v;
+    v += dpp_d<DPP_XOR1>(v);
+    v += dpp_d<DPP_XOR2>(v);
+    v += dpp_d<DPP_HALF_MIRROR>(v);
+    v += dpp_d<DPP_MIRROR>(v);
+    return (readlane_d(v, 0) + readlane_d(v, 16)) + (readlane_d(v, 32) + readlane_d(v, 48));
 }
 __device__ __forceinline__ float wave_sum(float v) {
-#pragma unroll
-    for (int m = 1; m < WAVE; m <<= 1) v += __shfl_xor(v, m, WAVE);
-    return v;
+    v += dpp_f<DPP_XOR1>(v);
+    v += dpp_f<DPP_XOR2>(v);
+    v += dpp_f<DPP_HALF_MIRROR>(v);
+    v += dpp_f<DPP_MIRROR>(v);
+    const float a = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 0));
+    const float b = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 16));
+    const float c = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 32));
+    const float d = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 48));
+    return (a + b) + (c + d);
 }
 __device__ __forceinline__ int wave_sum(int v) {
-#pragma unroll
-    for (int m = 1; m < WAVE; m <<= 1) v += __shfl_xor(v, m, WAVE);
-    return v;
+    v += dpp_i<DPP_XOR1>(v);
+    v += dpp_i<DPP_XOR2>(v);
+    v += dpp_i<DPP_HALF_MIRROR>(v);
+    v += dpp_i<DPP_MIRROR>(v);
+    return (__builtin_amdgcn_readlane(v, 0) + __builtin_amdgcn_readlane(v, 16)) +
+           (__builtin_amdgcn_readlane(v, 32) + __builtin_amdgcn_readlane(v, 48));
 }
 __device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-    for (int m = 1; m < WAVE; m <<= 1) v = fmax(v, __shfl_xor(v, m, WAVE));
-    return v;
+    v = fmax(v, dpp_d<DPP_XOR1>(v));
+    v = fmax(v, dpp_d<DPP_XOR2>(v));
+    v = fmax(v, dpp_d<DPP_HALF_MIRROR>(v));
+    v = fmax(v, dpp_d<DPP_MIRROR>(v));
+    return fmax(fmax(readlane_d(v, 0), readlane_d(v, 16)), fmax(readlane_d(v, 32), readlane_d(v, 48)));
 }
 
 // Workgroup sum of one double per thread.  `lds` holds T/64 doubles.  Every
@@ -139,6 +181,40 @@ __device__ __forceinline__ double block_max(double v, double* lds) {
 #pragma unroll
     for (int i = 1; i < T / WAVE; ++i) s = fmax(s, lds[i]);
     return s;
+}
+
+// NS sums and NM maxima in one pass (one LDS exchange).  `lds` holds
+// (NS + NM) * T/64 doubles.  Every thread receives the same values.
+template <int T, int NS, int NM>
+__device__ __forceinline__ void block_reduce(double (&s)[NS], double (&mx)[NM], double* lds) {
+    constexpr int NWV = T / WAVE;
+    const int lane = threadIdx.x & (WAVE - 1), wid = threadIdx.x / WAVE;
+#pragma unroll
+    for (int i = 0; i < NS; ++i) s[i] = wave_sum(s[i]);
+#pragma unroll
+    for (int i = 0; i < NM; ++i) mx[i] = wave_max(mx[i]);
+    __syncthreads();
+    if (lane == 0) {
+#pragma unroll
+        for (int i = 0; i < NS; ++i) lds[i * NWV + wid] = s[i];
+#pragma unroll
+        for (int i = 0; i < NM; ++i) lds[(NS + i) * NWV + wid] = mx[i];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NS; ++i) {
+        double a = 0.0;
+#pragma unroll
+        for (int w = 0; w < NWV; ++w) a += lds[i * NWV + w];
+        s[i] = a;
+    }
+#pragma unroll
+    for (int i = 0; i < NM; ++i) {
+        double a = lds[(NS + i) * NWV];
+#pragma unroll
+        for (int w = 1; w < NWV; ++w) a = fmax(a, lds[(NS + i) * NWV + w]);
+        mx[i] = a;
+    }
 }
 
 // Sum of (count, value) pairs in one pass (two LDS slots per wave).

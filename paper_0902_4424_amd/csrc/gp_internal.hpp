@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <string>
+#include <vector>
 
 #include "gp_l1.h"
 #include "gp_state.hpp"
@@ -14,6 +15,8 @@ struct gp_handle_s {
     size_t ws_bytes = 0;
     gpl1::GPState* host_state = nullptr; // pinned copy of a state for status reads
     void* extra = nullptr;               // batched-solver resources
+    std::vector<hipEvent_t> events;      // profiling: start/stop pairs of fused launches
+    int ev_used = 0;
 };
 
 namespace gpl1 {
@@ -34,5 +37,8 @@ int ensure_workspace(gp_handle h, size_t bytes);
 void fill_result(const GPState& s, gp_result* res);
 void destroy_extra(gp_handle h);
 const char* status_name(int s);
+// Profiling helpers: record an event pair around a launch; sum at the end.
+hipEvent_t prof_event(gp_handle h);
+double prof_collect(gp_handle h, int* pairs);
 
 }  // namespace gpl1

@@ -1,16 +1,18 @@
 // Kernels of one GPSS iteration on MI355X.  Per iteration three launches:
 //
 //   k_proj   (1 workgroup)  : steplength rule (Algorithm 2), v = x - alpha g,
-//                             threshold search for P_Omega, d = P(v) - x and
-//                             the dots g'd, d'd (Algorithm 1, projection and
-//                             direction).
-//   k_fused  (G workgroups) : one read of K serves both products: every
-//                             workgroup owns a slab of rows, forms q_i = K_i d
-//                             for its rows and, while that slab of K is still
-//                             in registers, adds K_i^T q_i into a private
-//                             p-vector.  Output: q (n) and G partial vectors of
-//                             w = K^T K d.
-//   k_update (many)         : closed-form Armijo backtracking from
+//                             threshold search for P_Omega, h = P(v)
+//                             (Algorithm 1, projection).
+//   k_fused  (G workgroups) : d = h - x (Algorithm 1, direction), then one
+//                             read of K serves both products: every workgroup
+//                             owns a slab of rows, forms q_i = K_i d for its
+//                             rows and, while that slab of K is still in
+//                             registers, adds K_i^T q_i into a private
+//                             p-vector.  Output: q (n), G partial vectors of
+//                             w = K^T K d, and per-workgroup partial dots g'd,
+//                             d'd, ||d||_inf over a slice of the columns.
+//   k_update (many)         : stationarity test (d = 0 or g'd >= 0),
+//                             closed-form Armijo backtracking from
 //                             (f, g'd, r'q, q'q), x += lam d, r += lam q,
 //                             g += 2 lam w (the new gradient 2 K^T r), and the
 //                             dots d'w, w'w that Algorithm 2 needs next.
@@ -19,6 +21,8 @@
 // and q = Kd, so every backtracking trial is a scalar formula, and
 // grad f(x + lam d) = g + 2 lam K^T K d, so the new gradient needs K^T q only.
 #pragma once
+
+#include <type_traits>
 
 #include "gp_device.hpp"
 #include "gp_state.hpp"
@@ -30,8 +34,26 @@ enum UpdMode : int32_t { UM_ITER = 0, UM_REFRESH = 1 };
 
 constexpr int PROJ_T = 1024;
 constexpr int UPD_T = 256;
-constexpr int UPD_COLS = 64;   // columns per p-part workgroup of k_update
+constexpr int UPD_COLS = 32;   // columns per p-part workgroup of k_update
 constexpr int UPD_ROWS = 256;  // rows per n-part workgroup of k_update
+constexpr int SPART = 8;       // doubles per fused-kernel workgroup in spart:
+                               // t't, t'r, g'd, d'd, ||d||_inf
+
+// ---------------------------------------------------------------------------
+// The state is staged through LDS: one coalesced load by the workgroup
+// instead of a chain of dependent global loads by one thread.
+// ---------------------------------------------------------------------------
+static_assert(sizeof(GPState) % 4 == 0, "state is copied as 32-bit words");
+constexpr int STATE_WORDS = (int)(sizeof(GPState) / 4);
+
+__device__ __forceinline__ void state_load(GPState& dst, const GPState* src) {
+    for (int i = threadIdx.x; i < STATE_WORDS; i += blockDim.x)
+        reinterpret_cast<uint32_t*>(&dst)[i] = reinterpret_cast<const uint32_t*>(src)[i];
+}
+__device__ __forceinline__ void state_store(GPState* dst, const GPState& src) {
+    for (int i = threadIdx.x; i < STATE_WORDS; i += blockDim.x)
+        reinterpret_cast<uint32_t*>(dst)[i] = reinterpret_cast<const uint32_t*>(&src)[i];
+}
 
 // ---------------------------------------------------------------------------
 // scalar logic (thread 0 of a workgroup)
@@ -101,14 +123,16 @@ __device__ __forceinline__ void ss_update(GPState* st, int k, double ss, double 
 // k_proj: projection onto the l1 ball by a parallel threshold search.
 //
 // With b_i = |v_i| - m (m = max|v|), the threshold t = mu - m solves
-// sum max(b_i - t, 0) = rho.  Starting from a lower bound t_0 <= t
-// (t_0 = max(-rho, (sum b - rho)/p): mu >= m - rho because the largest entry
-// of P(v) is at most rho, and mu >= the mean-based bound because all entries
-// could be active), each pass takes A = {b_i > t} and sets
-// t = (sum_A b - rho)/|A|.  The sets shrink monotonically and the pass whose
-// set is unchanged gives the exact threshold (Michelot's method).  Every pass
-// is one workgroup reduction of (count, sum) over values held in registers.
-// VPT = values per thread kept in registers; VPT = 0 streams them from vbuf.
+// phi(t) = sum max(b_i - t, 0) = rho.  phi is convex, piecewise linear and
+// decreasing, and a Newton step from any t,
+//     A = {i : b_i > t},  t <- (sum_A b_i - rho) / |A|,
+// lands at or left of the root (the tangent of a convex function lies below
+// it).  From the left the same step is Michelot's: the sets A shrink
+// monotonically and the pass whose set does not change gives the exact
+// threshold.  So the search may start anywhere with t < 0: in the iteration
+// it starts from the previous iteration's threshold, which usually leaves
+// one or two passes.  Every pass is one workgroup reduction of (count, sum)
+// over values held in registers (VPT per thread; VPT = 0 streams from vbuf).
 // ---------------------------------------------------------------------------
 template <int VPT>
 __global__ __launch_bounds__(PROJ_T) void k_proj(GPState* __restrict__ st, int mode, int64_t p,
@@ -118,114 +142,133 @@ __global__ __launch_bounds__(PROJ_T) void k_proj(GPState* __restrict__ st, int m
                                                  double* __restrict__ vbuf) {
     constexpr int T = PROJ_T;
     constexpr int NV = VPT > 0 ? VPT : 1;
-    __shared__ double lds[2 * (T / WAVE)];
-    __shared__ double sh_alpha;
+    __shared__ double lds[3 * (T / WAVE)];
+    __shared__ double sh_alpha, sh_mu;
+    __shared__ GPState S;
     const int tid = threadIdx.x;
-    if (st->done || st->stop_req) {
+    state_load(S, st);
+    __syncthreads();
+    if (S.done || S.stop_req) {
         if (tid == 0) st->live = 0;
         return;
     }
+    // x (and g) stay in registers for the whole kernel; v = x - alpha g is
+    // recomputed where needed.  g is not read in the modes that have none.
+    const bool use_g = mode == PM_ITER || mode == PM_ALPHA0;
 
     // -- steplength (Algorithm 2) from the partial dots of the last update --
     if (mode == PM_ITER) {
-        const int need_ss = st->ss_pending;          // uniform read before any write
-        double dw = 0.0, ww = 0.0;
+        const int need_ss = S.ss_pending;
+        double dots[2] = {0.0, 0.0};
+        double none[1] = {0.0};
         if (need_ss) {
-            for (int i = tid; i < GU; i += T) { dw += upart[4 * i]; ww += upart[4 * i + 1]; }
-            dw = block_sum<T>(dw, lds);
-            ww = block_sum<T>(ww, lds);
+            for (int i = tid; i < GU; i += T) { dots[0] += upart[4 * i]; dots[1] += upart[4 * i + 1]; }
+            block_reduce<T, 2, 1>(dots, none, lds);
         }
         if (tid == 0) {
-            commit_pending(st);
+            commit_pending(&S);
             if (need_ss) {
                 // s = lam d, z = 2 lam w (w = K^T K d): s's = lam^2 d'd,
                 // s'z = 2 lam^2 d'w, z'z = 4 lam^2 w'w (equation (5))
-                const double l2 = st->lam * st->lam;
-                ss_update(st, st->k, l2 * st->dd, 2.0 * l2 * dw, 4.0 * l2 * ww);
-                st->ss_pending = 0;
+                const double l2 = S.lam * S.lam;
+                ss_update(&S, S.k, l2 * S.dd, 2.0 * l2 * dots[0], 4.0 * l2 * dots[1]);
+                S.ss_pending = 0;
             }
-            sh_alpha = st->alpha;
+            sh_alpha = S.alpha;
+            sh_mu = S.mu;
         }
     } else if (tid == 0) {
-        commit_pending(st);
+        commit_pending(&S);
         sh_alpha = mode == PM_ALPHA0 ? 1.0 : 0.0;
+        sh_mu = 0.0;
     }
     __syncthreads();
     const double alpha = sh_alpha;
-    const double rho = st->prm.rho;
+    const double mu_prev = sh_mu;
+    const double rho = S.prm.rho;
 
     // -- v = x - alpha g ---------------------------------------------------
-    double v[NV];
-    double S = 0.0, m = 0.0;
-    auto vload = [&](int64_t j) -> double {
-        if (mode == PM_ITER || mode == PM_ALPHA0) return x[j] - alpha * g[j];
-        return x[j];
-    };
+    // Register slot e holds element j = 2*((e/2)*T + tid) + (e&1): each
+    // thread owns pairs of neighbours, read with 16-byte loads.
+    double vr[NV];
+    double Sm_s[1] = {0.0}, Sm_m[1] = {0.0};
     if (VPT > 0) {
 #pragma unroll
+        for (int e = 0; e < NV; e += 2) {
+            const int j = 2 * ((e / 2) * T + tid);   // p < 2^31: 32-bit offsets
+            if (NV > 1 && j + 1 < p) {
+                const double2 x2 = *reinterpret_cast<const double2*>(x + j);
+                double2 g2 = make_double2(0.0, 0.0);
+                if (use_g) g2 = *reinterpret_cast<const double2*>(g + j);
+                vr[e] = x2.x - alpha * g2.x;
+                vr[e + 1] = x2.y - alpha * g2.y;
+            } else {
+                vr[e] = j < p ? (use_g ? x[j] - alpha * g[j] : x[j]) : 0.0;
+                if (NV > 1) vr[e + 1] = 0.0;
+            }
+        }
+#pragma unroll
         for (int e = 0; e < NV; ++e) {
-            const int64_t j = (int64_t)e * T + tid;
-            v[e] = j < p ? vload(j) : 0.0;
-            S += fabs(v[e]);
-            m = fmax(m, fabs(v[e]));
+            const double a = fabs(vr[e]);
+            Sm_s[0] += a;
+            Sm_m[0] = fmax(Sm_m[0], a);
         }
     } else {
         for (int64_t j = tid; j < p; j += T) {
-            const double vj = vload(j);
+            const double vj = use_g ? x[j] - alpha * g[j] : x[j];
             vbuf[j] = vj;
-            S += fabs(vj);
-            m = fmax(m, fabs(vj));
+            Sm_s[0] += fabs(vj);
+            Sm_m[0] = fmax(Sm_m[0], fabs(vj));
         }
     }
-    S = block_sum<T>(S, lds);
-    m = block_max<T>(m, lds);
-    if (!isfinite(S)) {
-        if (tid == 0) { st->status = ST_NONFINITE; st->done = 1; st->live = 0; }
+    block_reduce<T, 1, 1>(Sm_s, Sm_m, lds);
+    const double Sv = Sm_s[0], m = Sm_m[0];
+    if (!isfinite(Sv)) {
+        if (tid == 0) { S.status = ST_NONFINITE; S.done = 1; S.live = 0; }
+        __syncthreads();
+        state_store(st, S);
         return;
     }
 
     // -- threshold --------------------------------------------------------
-    const bool inside = S <= rho;
+    const bool inside = Sv <= rho;
     double t = 0.0;     // mu - m
     int passes = 0;
     if (!inside && rho > 0.0) {
-        double sb = 0.0;
-        if (VPT > 0) {
-#pragma unroll
-            for (int e = 0; e < NV; ++e) {
-                const int64_t j = (int64_t)e * T + tid;
-                if (j < p) sb += fabs(v[e]) - m;
-            }
-        } else {
-            for (int64_t j = tid; j < p; j += T) sb += fabs(vbuf[j]) - m;
-        }
-        sb = block_sum<T>(sb, lds);
-        t = fmax(-rho, (sb - rho) / (double)p);
+        // start: the previous threshold if it lies below m, else the lower
+        // bound max(-rho, mean bound); any start with t < 0 is valid
+        const double tw = mu_prev - m;
+        t = (mode == PM_ITER && mu_prev > 0.0 && tw < 0.0) ? fmax(-rho, tw)
+                                                           : fmax(-rho, (Sv - rho) / (double)p - m);
+        if (!(t < 0.0)) t = -rho;
         int cprev = -1;
+        bool first = true;
         for (;;) {
             int c = 0;
-            double s = 0.0;
+            double sum = 0.0;
             if (VPT > 0) {
 #pragma unroll
                 for (int e = 0; e < NV; ++e) {
-                    const int64_t j = (int64_t)e * T + tid;
-                    const double b = fabs(v[e]) - m;
-                    if (j < p && b > t) { ++c; s += b; }
+                    const int j = 2 * ((e / 2) * T + tid) + (e & 1);
+                    const double b = fabs(vr[e]) - m;
+                    if (j < p && b > t) { ++c; sum += b; }
                 }
             } else {
                 for (int64_t j = tid; j < p; j += T) {
                     const double b = fabs(vbuf[j]) - m;
-                    if (b > t) { ++c; s += b; }
+                    if (b > t) { ++c; sum += b; }
                 }
             }
-            block_sum2<T>(c, s, lds);
+            block_sum2<T>(c, sum, lds);
             ++passes;
-            // c >= 1: the largest entry has b = 0 > t.  Keeping t monotone
-            // makes the sets nested in floating point too, so c never grows
-            // and the loop ends after at most p + 1 passes.
+            // c >= 1: the largest entry has b = 0 > t.  After the first
+            // (Newton) step t is kept monotone, so the sets are nested in
+            // floating point too and the loop ends within p + 1 passes.
             if (c == cprev || passes >= (1 << 20)) break;
             cprev = c;
-            t = fmax(t, (s - rho) / (double)c);
+            const double tn = (sum - rho) / (double)c;
+            t = first ? tn : fmax(t, tn);
+            first = false;
         }
     }
     // h_i = sgn(v_i) max(b_i - t, 0);  rho == 0 gives h = 0
@@ -238,43 +281,34 @@ __global__ __launch_bounds__(PROJ_T) void k_proj(GPState* __restrict__ st, int m
 
     // -- outputs ------------------------------------------------------------
     if (mode == PM_ITER) {
-        double gd = 0.0, dd = 0.0, dmax = 0.0;
-        auto emit = [&](int64_t j, double vj) {
-            const double dj = hval(vj) - x[j];
-            dout[j] = dj;
-            gd += g[j] * dj;
-            dd += dj * dj;
-            dmax = fmax(dmax, fabs(dj));
-        };
+        // h = P(x - alpha g); the direction d = h - x and its dots are formed
+        // by the multi-workgroup kernels that read h next
         if (VPT > 0) {
 #pragma unroll
-            for (int e = 0; e < NV; ++e) {
-                const int64_t j = (int64_t)e * T + tid;
-                if (j < p) emit(j, v[e]);
+            for (int e = 0; e < NV; e += 2) {
+                const int j = 2 * ((e / 2) * T + tid);
+                if (NV > 1 && j + 1 < p) {
+                    *reinterpret_cast<double2*>(dout + j) = make_double2(hval(vr[e]), hval(vr[e + 1]));
+                } else if (j < p) {
+                    dout[j] = hval(vr[e]);
+                }
             }
         } else {
-            for (int64_t j = tid; j < p; j += T) emit(j, vbuf[j]);
+            for (int64_t j = tid; j < p; j += T) dout[j] = hval(vbuf[j]);
         }
-        gd = block_sum<T>(gd, lds);
-        dd = block_sum<T>(dd, lds);
-        dmax = block_max<T>(dmax, lds);
         if (tid == 0) {
-            st->gd = gd;
-            st->dd = dd;
-            st->dmax = dmax;
-            st->mu = inside ? 0.0 : m + t;
-            st->michelot_iters = passes;
-            // h == x, or no descent left at working precision: stationary
-            if (dmax == 0.0 || !(gd < 0.0)) { st->status = ST_STATIONARY; st->done = 1; st->live = 0; }
-            else st->live = 1;
+            S.mu = inside ? 0.0 : m + t;
+            S.michelot_iters = passes;
+            S.michelot_total += passes;
+            S.live = 1;
         }
     } else if (mode == PM_ALPHA0) {
         double hmax = 0.0;
         if (VPT > 0) {
 #pragma unroll
             for (int e = 0; e < NV; ++e) {
-                const int64_t j = (int64_t)e * T + tid;
-                if (j < p) hmax = fmax(hmax, fabs(hval(v[e])));
+                const int j = 2 * ((e / 2) * T + tid) + (e & 1);
+                if (j < p) hmax = fmax(hmax, fabs(hval(vr[e])));
             }
         } else {
             for (int64_t j = tid; j < p; j += T) hmax = fmax(hmax, fabs(hval(vbuf[j])));
@@ -282,27 +316,29 @@ __global__ __launch_bounds__(PROJ_T) void k_proj(GPState* __restrict__ st, int m
         hmax = block_max<T>(hmax, lds);
         if (tid == 0) {
             // alpha_0 = max{alpha_min, min{1/||P(x0 - grad f(x0))||_inf, alpha_max}}
-            st->alpha = hmax > 0.0 ? clamp_alpha(1.0 / hmax, st->prm) : st->prm.amax;
-            st->live = 1;
+            S.alpha = hmax > 0.0 ? clamp_alpha(1.0 / hmax, S.prm) : S.prm.amax;
+            S.live = 1;
         }
     } else {   // PM_INIT_X0 (in place on x) and PM_PLAIN (into dout)
         double* out = mode == PM_INIT_X0 ? x : dout;
         if (VPT > 0) {
 #pragma unroll
             for (int e = 0; e < NV; ++e) {
-                const int64_t j = (int64_t)e * T + tid;
-                if (j < p) out[j] = hval(v[e]);
+                const int j = 2 * ((e / 2) * T + tid) + (e & 1);
+                if (j < p) out[j] = hval(vr[e]);
             }
         } else {
             for (int64_t j = tid; j < p; j += T) out[j] = hval(vbuf[j]);
         }
         if (tid == 0) {
-            st->mu = inside ? 0.0 : (rho > 0.0 ? m + t : m);
-            st->michelot_iters = passes;
-            if (mode == PM_INIT_X0) st->projected = inside ? 0 : 1;
-            st->live = 1;
+            S.mu = inside ? 0.0 : (rho > 0.0 ? m + t : m);
+            S.michelot_iters = passes;
+            if (mode == PM_INIT_X0) S.projected = inside ? 0 : 1;
+            S.live = 1;
         }
     }
+    __syncthreads();
+    state_store(st, S);
 }
 
 // ---------------------------------------------------------------------------
@@ -379,10 +415,14 @@ struct FusedBlock {
     }
 };
 
+// The vector multiplied is u = v - vsub (vsub may be NULL): in an iteration
+// v = h and vsub = x give the direction d; on a refresh v = x.  With g given,
+// workgroup b also returns g'd, d'd and ||d||_inf over its column slice.
 template <typename TK, typename ACC, int T, int CPT, int RB, bool ALIGNED>
 __global__ __launch_bounds__(T) void k_fused(const GPState* __restrict__ st, const TK* __restrict__ K,
                                                 int64_t n, int64_t p, int64_t ldk, int64_t rows_per_wg,
-                                                const double* __restrict__ v, const double* __restrict__ ysub,
+                                                const double* __restrict__ v, const double* __restrict__ vsub,
+                                                const double* __restrict__ g, const double* __restrict__ ysub,
                                                 const double* __restrict__ rvec, double* __restrict__ tout,
                                                 ACC* __restrict__ wpart, int64_t ldw,
                                                 double* __restrict__ spart) {
@@ -390,8 +430,15 @@ __global__ __launch_bounds__(T) void k_fused(const GPState* __restrict__ st, con
     constexpr int VEC = FB::VEC;
     constexpr int NW = FB::NW;
     __shared__ double red[2][RB][NW];
+    __shared__ double lds3[3 * NW];
     if (!st->live) return;
     const int tid = threadIdx.x;
+
+    const int64_t r0 = (int64_t)blockIdx.x * rows_per_wg;
+    const int64_t r1 = r0 + rows_per_wg < n ? r0 + rows_per_wg : n;
+    KVec<TK> A[RB][CPT], B[RB][CPT];
+    // start streaming K before the vector loads so their latencies overlap
+    if (r0 < r1) FB::template load<ALIGNED>(A, K, ldk, p, r0, r1);
 
     ACC dv[CPT][VEC], w[CPT][VEC];
 #pragma unroll
@@ -399,16 +446,13 @@ __global__ __launch_bounds__(T) void k_fused(const GPState* __restrict__ st, con
         const int64_t col = ((int64_t)c * T + tid) * VEC;
 #pragma unroll
         for (int e = 0; e < VEC; ++e) {
-            dv[c][e] = col + e < p ? (ACC)v[col + e] : (ACC)0;
+            const int64_t j = col + e;
+            dv[c][e] = j < p ? (ACC)(vsub ? v[j] - vsub[j] : v[j]) : (ACC)0;
             w[c][e] = 0;
         }
     }
-    const int64_t r0 = (int64_t)blockIdx.x * rows_per_wg;
-    const int64_t r1 = r0 + rows_per_wg < n ? r0 + rows_per_wg : n;
     double tt = 0.0, tr = 0.0;
-    KVec<TK> A[RB][CPT], B[RB][CPT];
     int bi = 0;
-    if (r0 < r1) FB::template load<ALIGNED>(A, K, ldk, p, r0, r1);
     for (int64_t row = r0; row < r1; row += 2 * RB) {
         if (row + RB < r1) FB::template load<ALIGNED>(B, K, ldk, p, row + RB, r1);
         FB::process(A, dv, w, red, bi, row, r1, ysub, rvec, tout, tt, tr);
@@ -417,6 +461,20 @@ __global__ __launch_bounds__(T) void k_fused(const GPState* __restrict__ st, con
         if (row + 2 * RB < r1) FB::template load<ALIGNED>(A, K, ldk, p, row + 2 * RB, r1);
         FB::process(B, dv, w, red, bi, row + RB, r1, ysub, rvec, tout, tt, tr);
         bi ^= 1;
+    }
+    // direction dots over this workgroup's column slice
+    double dsum[2] = {0.0, 0.0}, dmx[1] = {0.0};
+    if (g) {
+        const int64_t cs = (p + gridDim.x - 1) / gridDim.x;
+        const int64_t c0 = (int64_t)blockIdx.x * cs;
+        const int64_t c1 = c0 + cs < p ? c0 + cs : p;
+        for (int64_t j = c0 + tid; j < c1; j += T) {
+            const double dj = v[j] - vsub[j];
+            dsum[0] += g[j] * dj;
+            dsum[1] += dj * dj;
+            dmx[0] = fmax(dmx[0], fabs(dj));
+        }
+        block_reduce<T, 2, 1>(dsum, dmx, lds3);
     }
     ACC* wrow = wpart + (int64_t)blockIdx.x * ldw;
 #pragma unroll
@@ -428,8 +486,12 @@ __global__ __launch_bounds__(T) void k_fused(const GPState* __restrict__ st, con
         }
     }
     if (tid == 0) {
-        spart[2 * blockIdx.x] = tt;
-        spart[2 * blockIdx.x + 1] = tr;
+        double* sp = spart + (int64_t)SPART * blockIdx.x;
+        sp[0] = tt;
+        sp[1] = tr;
+        sp[2] = dsum[0];
+        sp[3] = dsum[1];
+        sp[4] = dmx[0];
     }
 }
 
@@ -442,7 +504,7 @@ __global__ __launch_bounds__(UPD_T) void k_update(GPState* __restrict__ st, int 
                                                   const double* __restrict__ spart, int GF,
                                                   const ACC* __restrict__ wpart, int64_t ldw, int64_t p,
                                                   int64_t n, int nbp, double* __restrict__ x,
-                                                  double* __restrict__ g, const double* __restrict__ d,
+                                                  double* __restrict__ g, const double* __restrict__ h,
                                                   double* __restrict__ r, const double* __restrict__ tq,
                                                   double* __restrict__ upart) {
     constexpr int T = UPD_T;
@@ -451,19 +513,41 @@ __global__ __launch_bounds__(UPD_T) void k_update(GPState* __restrict__ st, int 
     constexpr int NG = T / CQ;                  // partial groups
     __shared__ double red[NG][UPD_COLS];
     __shared__ double sh[4];
-    if (!st->live) return;
+    __shared__ GPState S;
     const int tid = threadIdx.x, lane = tid & (WAVE - 1);
+    state_load(S, st);
+    __syncthreads();
+    if (!S.live) return;
 
-    // (q'q, r'q) or (r'r) from the fused kernel's partials, fixed order
+    // (q'q, r'q, g'd, d'd, ||d||_inf) or (r'r) from the fused kernel's
+    // partials, fixed order
+    __shared__ double sh5[5];
     if (tid < WAVE) {
-        double a = 0.0, b = 0.0;
-        for (int i = lane; i < GF; i += WAVE) { a += spart[2 * i]; b += spart[2 * i + 1]; }
+        double a = 0.0, b = 0.0, c = 0.0, e = 0.0, mx = 0.0;
+        for (int i = lane; i < GF; i += WAVE) {
+            const double* sp = spart + (int64_t)SPART * i;
+            a += sp[0]; b += sp[1]; c += sp[2]; e += sp[3]; mx = fmax(mx, sp[4]);
+        }
         a = wave_sum(a);
         b = wave_sum(b);
-        if (lane == 0) { sh[0] = a; sh[1] = b; }
+        c = wave_sum(c);
+        e = wave_sum(e);
+        mx = wave_max(mx);
+        if (lane == 0) { sh5[0] = a; sh5[1] = b; sh5[2] = c; sh5[3] = e; sh5[4] = mx; }
     }
     __syncthreads();
-    const double qq = sh[0], rq = sh[1];
+    const double qq = sh5[0], rq = sh5[1], gd = sh5[2], dd = sh5[3], dmax = sh5[4];
+    if (mode == UM_ITER && (dmax == 0.0 || !(gd < 0.0))) {
+        // h == x, or no descent left at working precision: stationary
+        if (blockIdx.x == 0 && tid == 0) {
+            st->gd = gd;
+            st->dd = dd;
+            st->dmax = dmax;
+            st->status = ST_STATIONARY;
+            st->stop_req = 1;
+        }
+        return;
+    }
 
     double lam = 1.0;
     int nb = 0;
@@ -471,13 +555,12 @@ __global__ __launch_bounds__(UPD_T) void k_update(GPState* __restrict__ st, int 
     if (mode == UM_ITER) {
         // Armijo with memory M: f(x + lam d) <= f_max + beta lam g'd, where
         // f(x + lam d) - f = lam (2 r'q + lam q'q) exactly for this f.
-        const GPParams& P = st->prm;
-        const double f = st->f;
+        const GPParams& P = S.prm;
+        const double f = S.f;
         double fmax = f;
-        const int nh = st->nhist < P.M ? st->nhist : P.M;
-        for (int i = 0; i < nh; ++i) fmax = fmax > st->fhist[(st->hpos - i + MAX_M) % MAX_M]
-                                              ? fmax : st->fhist[(st->hpos - i + MAX_M) % MAX_M];
-        const double gd = st->gd;
+        const int nh = S.nhist < P.M ? S.nhist : P.M;
+        for (int i = 0; i < nh; ++i) fmax = fmax > S.fhist[(S.hpos - i + MAX_M) % MAX_M]
+                                              ? fmax : S.fhist[(S.hpos - i + MAX_M) % MAX_M];
         for (;;) {
             const double inc = lam * (2.0 * rq + lam * qq);
             if (inc <= (fmax - f) + P.beta * lam * gd) break;
@@ -497,29 +580,43 @@ __global__ __launch_bounds__(UPD_T) void k_update(GPState* __restrict__ st, int 
         double acc[VU];
 #pragma unroll
         for (int e = 0; e < VU; ++e) acc[e] = 0.0;
-        for (int gi = grp; gi < GF; gi += NG) {
-            const ACC* src = wpart + (int64_t)gi * ldw + c0 + cq * VU;
-            if constexpr (VU == 4) {
-                const float4 w4 = *reinterpret_cast<const float4*>(src);
-                acc[0] += w4.x; acc[1] += w4.y; acc[2] += w4.z; acc[3] += w4.w;
-            } else {
-                const double2 w2 = *reinterpret_cast<const double2*>(src);
-                acc[0] += w2.x; acc[1] += w2.y;
+        const ACC* src = wpart + c0 + cq * VU;
+        using V16 = typename std::conditional<VU == 4, float4, double2>::type;
+        int gi = grp;
+        // eight partial vectors in flight per thread, summed in index order
+        for (; gi + 7 * NG < GF; gi += 8 * NG) {
+            V16 w8[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) w8[u] = *reinterpret_cast<const V16*>(src + (int64_t)(gi + u * NG) * ldw);
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const ACC* pw = reinterpret_cast<const ACC*>(&w8[u]);
+#pragma unroll
+                for (int e = 0; e < VU; ++e) acc[e] += (double)pw[e];
             }
+        }
+        for (; gi < GF; gi += NG) {
+            const V16 w1 = *reinterpret_cast<const V16*>(src + (int64_t)gi * ldw);
+            const ACC* pw = reinterpret_cast<const ACC*>(&w1);
+#pragma unroll
+            for (int e = 0; e < VU; ++e) acc[e] += (double)pw[e];
         }
 #pragma unroll
         for (int e = 0; e < VU; ++e) red[grp][cq * VU + e] = acc[e];
         __syncthreads();
         double dw = 0.0, ww = 0.0;
-        if (tid < UPD_COLS) {
+        if (tid < WAVE) {
             double w = 0.0;
+            if (tid < UPD_COLS) {
 #pragma unroll
-            for (int i = 0; i < NG; ++i) w += red[i][tid];
+                for (int i = 0; i < NG; ++i) w += red[i][tid];
+            }
             const int64_t j = c0 + tid;
-            if (j < p) {
+            if (tid < UPD_COLS && j < p) {
                 if (mode == UM_ITER) {
-                    const double dj = d[j];
-                    x[j] += lam * dj;
+                    const double xj = x[j];
+                    const double dj = h[j] - xj;
+                    x[j] = xj + lam * dj;
                     g[j] += 2.0 * lam * w;
                     dw = dj * w;
                     ww = w * w;
@@ -549,15 +646,18 @@ __global__ __launch_bounds__(UPD_T) void k_update(GPState* __restrict__ st, int 
     }
 
     if (blockIdx.x == 0 && tid == 0) {
-        const GPParams& P = st->prm;
+        const GPParams& P = S.prm;
         if (mode == UM_ITER) {
-            const double f = st->f;
+            const double f = S.f;
             const double fn = f + lam * (2.0 * rq + lam * qq);
             st->lam = lam;
+            st->gd = gd;
+            st->dd = dd;
+            st->dmax = dmax;
             st->nb = nb;
-            st->backtracks += nb;
+            st->backtracks = S.backtracks + nb;
             st->f_new = fn;
-            st->k_new = st->k + 1;
+            st->k_new = S.k + 1;
             st->pending = 1;
             st->ss_pending = 1;
             const double rel = (f - fn) / f;
@@ -565,10 +665,10 @@ __global__ __launch_bounds__(UPD_T) void k_update(GPState* __restrict__ st, int 
             if (!isfinite(fn)) { st->status = ST_NONFINITE; st->stop_req = 1; }
             else if (P.f_target >= 0.0 && fn <= P.f_target) { st->status = ST_TARGET; st->stop_req = 1; }
             else if (P.tol > 0.0 && rel < P.tol) { st->status = ST_OK_TOL; st->stop_req = 1; }
-            else if (st->k + 1 >= P.max_iter) { st->status = ST_MAX_ITER; st->stop_req = 1; }
+            else if (S.k + 1 >= P.max_iter) { st->status = ST_MAX_ITER; st->stop_req = 1; }
         } else {
             st->f_new = qq;              // sum of t_i^2 = ||K x - y||^2
-            if (!st->pending) st->k_new = st->k;
+            if (!S.pending) st->k_new = S.k;
             st->pending = 1;
             if (!isfinite(qq)) { st->status = ST_NONFINITE; st->stop_req = 1; }
         }

@@ -54,6 +54,7 @@ struct GPState {
     int32_t status, done, projected;
     int32_t live, stop_req;
     int32_t michelot_iters;    // diagnostics: passes of the last threshold search
+    int32_t michelot_total;    // diagnostics: passes summed over the iterations
     // final results
     double l1, gmax;
 };

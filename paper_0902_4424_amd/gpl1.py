@@ -31,14 +31,17 @@ class GPOpts(C.Structure):
                 ("max_iter", C.c_int32), ("f_target", C.c_double),
                 ("refresh_every", C.c_int32), ("backtrack_cap", C.c_int32),
                 ("chunk", C.c_int32), ("fused_cfg", C.c_int32),
-                ("fused_grid", C.c_int32)]
+                ("fused_grid", C.c_int32), ("profile", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 class GPResult(C.Structure):
     _fields_ = [("status", C.c_int32), ("iters", C.c_int32),
                 ("backtracks", C.c_int32), ("projected_x0", C.c_int32),
                 ("f", C.c_double), ("rel_change", C.c_double),
-                ("lambda_est", C.c_double), ("l1norm", C.c_double)]
+                ("lambda_est", C.c_double), ("l1norm", C.c_double),
+                ("t_fused_ms", C.c_double), ("n_fused", C.c_int32),
+                ("proj_passes", C.c_int32)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_}
@@ -215,7 +218,7 @@ class Handle:
         if x0 is not None and (x0.dtype != vdt or x0.numel() != p or not x0.is_contiguous()):
             raise ValueError(f"x0 must be contiguous {vdt} of length {p}")
         out = torch.empty(p, dtype=vdt, device=K.device) if out is None else out
-        o = opts if opts is not None else default_opts(**kw)
+        o = opts if opts is not None else default_opts(**_tuned(kdt, n, p, kw))
         res = GPResult()
         rc = self.lib.gp_l1_solve(self.h, kdt, _ptr(K), n, p, ldk, _ptr(y), float(rho),
                                   _ptr(x0), float(tol), _ptr(out), C.byref(o),
@@ -280,6 +283,24 @@ class Handle:
                                               res, _stream(stream))
         self._raise(rc)
         return outs, [r.as_dict() for r in res]
+
+
+_DT_NAME = {GP_F64: "f64", GP_F32: "f32", GP_BF16: "bf16"}
+
+
+def _tuned(kdt, n, p, kw):
+    """Add the autotuned kernel shape for this problem shape (tuned.json),
+    unless the caller chose one."""
+    if "fused_cfg" in kw or "fused_grid" in kw:
+        return kw
+    from . import tune
+    t = tune.lookup(_DT_NAME[kdt], n, p)
+    if not t:
+        return kw
+    kw = dict(kw)
+    kw["fused_cfg"] = int(t["fused_cfg"])
+    kw["fused_grid"] = int(t["fused_grid"])
+    return kw
 
 
 _default_handles = {}

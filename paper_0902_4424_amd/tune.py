@@ -1,0 +1,109 @@
+"""Tile autotuner for the fused K / K^T kernel.
+
+For each problem shape (K dtype, n, p) it times the solver's fused kernel
+(HIP events around every launch, `profile` option) and the whole iteration
+over the candidate kernel shapes (threads, column chunks per thread, rows
+per block) and grid sizes (row slabs), and records the fastest pair in
+tuned.json next to this file.  The binding reads that table and passes the
+pair through gp_opts.fused_cfg / fused_grid unless the caller sets them.
+
+    python -m paper_0902_4424_amd.tune f32:4096x16384 f64:256x1024 ...
+"""
+import json
+import os
+import sys
+import time
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+TABLE = os.path.join(PKG, "tuned.json")
+
+# (threads, chunks per thread) of the library's configurations 1..6; a
+# configuration covers T * CPT * (16 / element size) columns
+CFG_COVER = {1: (256, 1), 2: (256, 2), 3: (256, 4), 4: (512, 4), 5: (512, 8), 6: (1024, 8)}
+ESIZE = {"f64": 8, "f32": 4, "bf16": 2}
+GRIDS = (32, 64, 128, 192, 256, 320, 384, 512)
+
+
+def key(dtype, n, p):
+    return f"{dtype}:{n}x{p}"
+
+
+def load_table():
+    try:
+        with open(TABLE) as fh:
+            return json.load(fh)
+    except (OSError, ValueError):
+        return {}
+
+
+def lookup(dtype, n, p):
+    return load_table().get(key(dtype, n, p))
+
+
+def candidates(dtype, n, p):
+    vec = 16 // ESIZE[dtype]
+    out = []
+    for c, (T, cpt) in CFG_COVER.items():
+        if T * cpt * vec >= p and T * cpt * vec < 4 * max(p, 1):
+            for g in GRIDS:
+                if g <= n:
+                    out.append((c, g))
+    return out
+
+
+def tune_shape(H, dtype, n, p, iters=40, reps=3, log=print):
+    import numpy as np
+    import torch
+    from . import gpl1, instances
+    inst = instances.gaussian_instance(n, p, max(1, n // 20), dtype=dtype, seed=12345)
+    if dtype == "bf16":
+        K = torch.from_numpy(inst.K_store.view(np.int16)).cuda()
+    else:
+        K = torch.from_numpy(inst.K_store).cuda()
+    y = torch.from_numpy(inst.y_store).cuda()
+    best = None
+    for cfg, grid in candidates(dtype, n, p):
+        opts = gpl1.default_opts(max_iter=iters, profile=1, fused_cfg=cfg, fused_grid=grid)
+        H.solve(K, y, inst.rho, tol=0.0, opts=opts)          # warm
+        torch.cuda.synchronize()
+        fused, it_us = [], []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            _, res = H.solve(K, y, inst.rho, tol=0.0, opts=opts)
+            dt = time.perf_counter() - t0
+            fused.append(res["t_fused_ms"] * 1e3 / max(res["n_fused"], 1))
+            it_us.append(dt * 1e6 / max(res["iters"], 1))
+        f_us, i_us = min(fused), min(it_us)
+        log(f"  {key(dtype, n, p)} cfg={cfg} grid={grid}: fused {f_us:8.2f} us  iteration {i_us:8.2f} us")
+        if best is None or i_us < best["iter_us"]:
+            best = {"fused_cfg": cfg, "fused_grid": grid, "fused_us": round(f_us, 3),
+                    "iter_us": round(i_us, 3)}
+    return best
+
+
+def main(argv):
+    import torch
+    from . import gpl1
+    if not torch.cuda.is_available():
+        print("tune: needs a GPU", file=sys.stderr)
+        return 2
+    shapes = []
+    for a in argv:
+        dt, nm = a.split(":")
+        n, p = (int(v) for v in nm.split("x"))
+        shapes.append((dt, n, p))
+    table = load_table()
+    H = gpl1.Handle(0)
+    for dt, n, p in shapes:
+        print(f"tuning {key(dt, n, p)}", flush=True)
+        best = tune_shape(H, dt, n, p, log=lambda m: print(m, flush=True))
+        if best:
+            table[key(dt, n, p)] = best
+            print(f"  -> {best}", flush=True)
+    with open(TABLE, "w") as fh:
+        json.dump(table, fh, indent=1, sort_keys=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main(sys.argv[1:]))
