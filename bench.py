@@ -75,6 +75,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-gap", action="store_true", help="skip the time-to-gap leg")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first run one plain 256 MiB device-to-device copy (a reference "
+                         "kernel of known traffic for hardware-counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this solver runs on one GPU; --gpus {args.gpus} is not supported "
@@ -97,6 +100,14 @@ def main():
     torch.cuda.synchronize()
     H = gpl1.Handle(0)
     opts = gpl1.default_opts(max_iter=ITERS, refresh_every=REFRESH, profile=1)
+    if args.calibrate_copy:
+        src = torch.ones(64 << 20, dtype=torch.float32, device=dev)   # 256 MiB
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("calibration copy: 256 MiB read + 256 MiB written")
+        del src, dst
 
     for i in range(args.warmup):
         H.solve(K, y, inst.rho, tol=0.0, opts=opts)

@@ -76,10 +76,10 @@ typedef struct {
     int32_t refresh_every;/* recompute r = Kx - y, g = 2K^T r every R iters (0 = never) */
     int32_t backtrack_cap;/* max reductions of the line-search step            */
     int32_t chunk;        /* iterations enqueued between host status polls     */
-    int32_t fused_cfg;    /* tuning: fused K/K^T kernel shape, 1..6 (0 = automatic) */
+    int32_t fused_cfg;    /* tuning: fused K/K^T kernel shape, 1..10 (0 = automatic) */
     int32_t fused_grid;   /* tuning: workgroups (row slabs) of that kernel (0 = automatic) */
     int32_t profile;      /* 1: time every fused K/K^T launch with HIP events (result.t_fused_ms) */
-    int32_t reserved;
+    int32_t fused_interleave; /* tuning: 1 = row blocks dealt round-robin to workgroups, 0 = slabs */
 } gp_opts;
 
 typedef struct {

@@ -71,10 +71,12 @@ hipEvent_t prof_event(gp_handle h) {
     return h->events[h->ev_used++];
 }
 
-double prof_collect(gp_handle h, int* pairs) {
+// Sum the first `live` event pairs (launches enqueued after the solve stopped
+// exit at once and are not counted).
+double prof_collect(gp_handle h, int live, int* pairs) {
     double ms = 0.0;
     int np = 0;
-    for (int i = 0; i + 1 < h->ev_used; i += 2) {
+    for (int i = 0; i + 1 < h->ev_used && np < live; i += 2) {
         float t = 0.f;
         if (hipEventElapsedTime(&t, h->events[i], h->events[i + 1]) == hipSuccess) { ms += t; ++np; }
     }
@@ -121,9 +123,12 @@ int check_opts(gp_handle h, const gp_opts& o) {
 // ---------------------------------------------------------------------------
 // (threads, column chunks per thread, rows per block); columns covered by one
 // workgroup = T * CPT * VEC.
-struct FusedCfg { int T, CPT, RB; };
+// (threads, column chunks per thread, rows per block, register buffers);
+// columns covered by one workgroup = T * CPT * VEC.
+struct FusedCfg { int T, CPT, RB, NB; };
 static const FusedCfg kFusedCfgs[] = {
-    {256, 1, 4}, {256, 2, 4}, {256, 4, 2}, {512, 4, 2}, {512, 8, 1}, {1024, 8, 1},
+    {256, 1, 4, 2}, {256, 2, 4, 2}, {256, 4, 2, 2}, {512, 4, 2, 2}, {512, 8, 1, 2}, {1024, 8, 1, 2},
+    {256, 4, 1, 3}, {512, 4, 1, 3}, {512, 8, 1, 3}, {1024, 4, 1, 3},
 };
 constexpr int kNumFusedCfgs = sizeof(kFusedCfgs) / sizeof(kFusedCfgs[0]);
 
@@ -136,7 +141,7 @@ int pick_fused_cfg(gp_dtype dt, int64_t p, int want) {
         const FusedCfg& c = kFusedCfgs[want - 1];
         return (int64_t)c.T * c.CPT * vec >= p ? want - 1 : -1;
     }
-    for (int i = 0; i < kNumFusedCfgs; ++i) {
+    for (int i = 0; i < 6; ++i) {
         const FusedCfg& c = kFusedCfgs[i];
         if ((int64_t)c.T * c.CPT * vec >= p) return i;
     }
@@ -157,31 +162,36 @@ int64_t pick_fused_grid(int64_t n, int64_t p, gp_dtype dt, int want) {
 struct FusedArgs {
     const GPState* st; const void* K; int64_t n, p, ldk, rows;
     const double *v, *vsub, *g, *ysub, *rvec; double* tout; void* wpart; int64_t ldw; double* spart;
+    int interleave;
 };
 
-template <typename TK, typename ACC, int T, int CPT, int RB>
+template <typename TK, typename ACC, int T, int CPT, int RB, int NB>
 void launch_fused_t(bool aligned, hipStream_t s, int64_t G, const FusedArgs& a) {
     if (aligned)
-        hipLaunchKernelGGL((k_fused<TK, ACC, T, CPT, RB, true>), dim3((unsigned)G), dim3(T), 0, s, a.st,
+        hipLaunchKernelGGL((k_fused<TK, ACC, T, CPT, RB, NB, true>), dim3((unsigned)G), dim3(T), 0, s, a.st,
                            (const TK*)a.K, a.n, a.p, a.ldk, a.rows, a.v, a.vsub, a.g, a.ysub, a.rvec, a.tout,
-                           (ACC*)a.wpart, a.ldw, a.spart);
+                           (ACC*)a.wpart, a.ldw, a.spart, a.interleave);
     else
-        hipLaunchKernelGGL((k_fused<TK, ACC, T, CPT, RB, false>), dim3((unsigned)G), dim3(T), 0, s, a.st,
+        hipLaunchKernelGGL((k_fused<TK, ACC, T, CPT, RB, NB, false>), dim3((unsigned)G), dim3(T), 0, s, a.st,
                            (const TK*)a.K, a.n, a.p, a.ldk, a.rows, a.v, a.vsub, a.g, a.ysub, a.rvec, a.tout,
-                           (ACC*)a.wpart, a.ldw, a.spart);
+                           (ACC*)a.wpart, a.ldw, a.spart, a.interleave);
 }
 
 template <typename TK, typename ACC>
 void launch_fused_dt(int cfg, bool aligned, hipStream_t s, int64_t G, const FusedArgs& a) {
-#define GPL1_FUSED_CASE(i, T, C, R) \
-    case i: launch_fused_t<TK, ACC, T, C, R>(aligned, s, G, a); break;
+#define GPL1_FUSED_CASE(i, T, C, R, B) \
+    case i: launch_fused_t<TK, ACC, T, C, R, B>(aligned, s, G, a); break;
     switch (cfg) {
-        GPL1_FUSED_CASE(0, 256, 1, 4)
-        GPL1_FUSED_CASE(1, 256, 2, 4)
-        GPL1_FUSED_CASE(2, 256, 4, 2)
-        GPL1_FUSED_CASE(3, 512, 4, 2)
-        GPL1_FUSED_CASE(4, 512, 8, 1)
-        GPL1_FUSED_CASE(5, 1024, 8, 1)
+        GPL1_FUSED_CASE(0, 256, 1, 4, 2)
+        GPL1_FUSED_CASE(1, 256, 2, 4, 2)
+        GPL1_FUSED_CASE(2, 256, 4, 2, 2)
+        GPL1_FUSED_CASE(3, 512, 4, 2, 2)
+        GPL1_FUSED_CASE(4, 512, 8, 1, 2)
+        GPL1_FUSED_CASE(5, 1024, 8, 1, 2)
+        GPL1_FUSED_CASE(6, 256, 4, 1, 3)
+        GPL1_FUSED_CASE(7, 512, 4, 1, 3)
+        GPL1_FUSED_CASE(8, 512, 8, 1, 3)
+        GPL1_FUSED_CASE(9, 1024, 4, 1, 3)
     }
 #undef GPL1_FUSED_CASE
 }
@@ -425,8 +435,9 @@ int gp_l1_solve(gp_handle h, gp_dtype kdtype, const void* K, int64_t n, int64_t 
     if (x0) launch_proj(s, st, PM_INIT_X0, p, x, nullptr, nullptr, nullptr, 0, vb);
     // r = K x - y, g = 2 K^T r, f = ||r||^2
     // d holds h = P(x - alpha g) between the projection and the update
-    const FusedArgs fa_refresh{st, K, n, p, ldk, P.rows, x, nullptr, nullptr, y64, nullptr, q, wpart, P.ldw, spart};
-    const FusedArgs fa_iter{st, K, n, p, ldk, P.rows, d, x, g, nullptr, r, q, wpart, P.ldw, spart};
+    const int il = o.fused_interleave;
+    const FusedArgs fa_refresh{st, K, n, p, ldk, P.rows, x, nullptr, nullptr, y64, nullptr, q, wpart, P.ldw, spart, il};
+    const FusedArgs fa_iter{st, K, n, p, ldk, P.rows, d, x, g, nullptr, r, q, wpart, P.ldw, spart, il};
     auto refresh = [&]() {
         launch_fused(kdtype, P.cfg, aligned, s, P.G, fa_refresh);
         launch_update(kdtype, s, st, UM_REFRESH, spart, (int)P.G, wpart, P.ldw, p, n, x, g, d, r, q, upart);
@@ -465,7 +476,12 @@ int gp_l1_solve(gp_handle h, gp_dtype kdtype, const void* K, int64_t n, int64_t 
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(h, e, "final sync");
     fill_result(*h->host_state, res);
-    if (o.profile) res->t_fused_ms = prof_collect(h, &res->n_fused);
+    if (o.profile) {
+        // fused launches that did work: one per accepted update, plus the one
+        // whose direction was found stationary or failed the line search
+        const int live = res->iters + ((res->status == GP_STATIONARY || res->status == GP_BACKTRACK_LIMIT) ? 1 : 0);
+        res->t_fused_ms = prof_collect(h, live, &res->n_fused);
+    }
     if (res->status < 0) return fail(h, res->status, "solve ended with a non-finite value");
     return res->status;
 }

@@ -39,6 +39,6 @@ void destroy_extra(gp_handle h);
 const char* status_name(int s);
 // Profiling helpers: record an event pair around a launch; sum at the end.
 hipEvent_t prof_event(gp_handle h);
-double prof_collect(gp_handle h, int* pairs);
+double prof_collect(gp_handle h, int live, int* pairs);
 
 }  // namespace gpl1

@@ -371,11 +371,14 @@ struct FusedBlock {
         }
     }
 
+    // Reduce one block of RB rows and fold it into w.  Row values live in
+    // LDS (stage: y_i and r_i staged in, t_i buffered out) so that no global
+    // access sits on the per-row path: vmcnt is in order, and waiting for a
+    // scalar load would also wait for the prefetched rows of K.
     __device__ __forceinline__ static void process(const KVec<TK> (&buf)[RB][CPT], const ACC (&dv)[CPT][VEC],
                                                    ACC (&w)[CPT][VEC], double (*red)[RB][NW], int bi,
-                                                   int64_t row0, int64_t r1, const double* ysub,
-                                                   const double* rvec, double* tout, double& tt,
-                                                   double& tr) {
+                                                   int64_t row0, int64_t r1, int kl, const double* s_y,
+                                                   const double* s_r, double* s_t, double& tt, double& tr) {
         const int lane = threadIdx.x & (WAVE - 1), wid = threadIdx.x / WAVE;
         double part[RB];
 #pragma unroll
@@ -399,11 +402,11 @@ struct FusedBlock {
                 double t = 0.0;
 #pragma unroll
                 for (int i = 0; i < NW; ++i) t += red[bi][r][i];
-                if (ysub) t -= ysub[row];
+                t -= s_y[kl + r];
                 if (threadIdx.x == 0) {
-                    tout[row] = t;
+                    s_t[kl + r] = t;
                     tt += t * t;
-                    if (rvec) tr += t * rvec[row];
+                    tr += t * s_r[kl + r];
                 }
                 const ACC ta = (ACC)t;
 #pragma unroll
@@ -418,27 +421,38 @@ struct FusedBlock {
 // The vector multiplied is u = v - vsub (vsub may be NULL): in an iteration
 // v = h and vsub = x give the direction d; on a refresh v = x.  With g given,
 // workgroup b also returns g'd, d'd and ||d||_inf over its column slice.
-template <typename TK, typename ACC, int T, int CPT, int RB, bool ALIGNED>
+template <typename TK, typename ACC, int T, int CPT, int RB, int NB, bool ALIGNED>
 __global__ __launch_bounds__(T) void k_fused(const GPState* __restrict__ st, const TK* __restrict__ K,
                                                 int64_t n, int64_t p, int64_t ldk, int64_t rows_per_wg,
                                                 const double* __restrict__ v, const double* __restrict__ vsub,
                                                 const double* __restrict__ g, const double* __restrict__ ysub,
                                                 const double* __restrict__ rvec, double* __restrict__ tout,
                                                 ACC* __restrict__ wpart, int64_t ldw,
-                                                double* __restrict__ spart) {
+                                                double* __restrict__ spart, int interleave) {
     using FB = FusedBlock<TK, ACC, T, CPT, RB>;
     constexpr int VEC = FB::VEC;
     constexpr int NW = FB::NW;
+    constexpr int FCH = 256;    // rows staged per chunk (a multiple of RB)
+    static_assert(FCH % RB == 0, "row blocks must not straddle a chunk");
     __shared__ double red[2][RB][NW];
     __shared__ double lds3[3 * NW];
+    __shared__ double s_y[FCH], s_r[FCH], s_t[FCH];
     if (!st->live) return;
     const int tid = threadIdx.x;
 
+    // Row blocks of this workgroup: a contiguous slab [r0, r1), or, with
+    // `interleave`, blocks b, b + G, b + 2G, ... so that at any moment the
+    // whole grid streams one compact window of K.
     const int64_t r0 = (int64_t)blockIdx.x * rows_per_wg;
-    const int64_t r1 = r0 + rows_per_wg < n ? r0 + rows_per_wg : n;
-    KVec<TK> A[RB][CPT], B[RB][CPT];
+    const int64_t first = interleave ? (int64_t)blockIdx.x * RB : r0;
+    const int64_t step = interleave ? (int64_t)gridDim.x * RB : RB;
+    const int64_t lim = interleave ? n : (r0 + rows_per_wg < n ? r0 + rows_per_wg : n);
+    // NB register buffers of RB rows each: NB - 1 row blocks are in flight
+    // while one is reduced
+    KVec<TK> A[RB][CPT], B[RB][CPT], C[NB > 2 ? RB : 1][CPT];
     // start streaming K before the vector loads so their latencies overlap
-    if (r0 < r1) FB::template load<ALIGNED>(A, K, ldk, p, r0, r1);
+    if (first < lim) FB::template load<ALIGNED>(A, K, ldk, p, first, lim);
+    if (NB > 2 && first + step < lim) FB::template load<ALIGNED>(B, K, ldk, p, first + step, lim);
 
     ACC dv[CPT][VEC], w[CPT][VEC];
 #pragma unroll
@@ -453,14 +467,68 @@ __global__ __launch_bounds__(T) void k_fused(const GPState* __restrict__ st, con
     }
     double tt = 0.0, tr = 0.0;
     int bi = 0;
-    for (int64_t row = r0; row < r1; row += 2 * RB) {
-        if (row + RB < r1) FB::template load<ALIGNED>(B, K, ldk, p, row + RB, r1);
-        FB::process(A, dv, w, red, bi, row, r1, ysub, rvec, tout, tt, tr);
+    // Staging of y_i, r_i and the outputs t_i, CH rows at a time.  `kl` is
+    // the index of a row block within the current chunk; a chunk boundary
+    // flushes t and loads the next chunk (one wait per CH rows).
+    int64_t chunk_first = -1;   // first row block (in units of step) of the staged chunk
+    int kl = 0;
+    auto stage = [&](int64_t blk) {
+        // rows of row-block index bb: first + bb*step + r, r < RB
+        __syncthreads();
+        if (chunk_first >= 0) {
+            for (int i = tid; i < FCH; i += T) {
+                const int64_t bb = chunk_first + i / RB;
+                const int64_t row = first + bb * step + i % RB;
+                if (row < lim && i < kl) tout[row] = s_t[i];
+            }
+        }
+        chunk_first = blk;
+        for (int i = tid; i < FCH; i += T) {
+            const int64_t bb = blk + i / RB;
+            const int64_t row = first + bb * step + i % RB;
+            const bool ok = row < lim;
+            s_y[i] = (ok && ysub) ? ysub[row] : 0.0;
+            s_r[i] = (ok && rvec) ? rvec[row] : 0.0;
+        }
+        kl = 0;
+        __syncthreads();
+    };
+    int64_t blk = 0;    // row-block counter
+    auto run = [&](const KVec<TK> (&buf)[RB][CPT], int64_t row) {
+        if (kl == FCH || chunk_first < 0) stage(blk);
+        FB::process(buf, dv, w, red, bi, row, lim, kl, s_y, s_r, s_t, tt, tr);
         bi ^= 1;
-        if (row + RB >= r1) break;
-        if (row + 2 * RB < r1) FB::template load<ALIGNED>(A, K, ldk, p, row + 2 * RB, r1);
-        FB::process(B, dv, w, red, bi, row + RB, r1, ysub, rvec, tout, tt, tr);
-        bi ^= 1;
+        kl += RB;
+        ++blk;
+    };
+    if constexpr (NB > 2) {
+        for (int64_t row = first; row < lim; row += 3 * step) {
+            if (row + 2 * step < lim) FB::template load<ALIGNED>(C, K, ldk, p, row + 2 * step, lim);
+            run(A, row);
+            if (row + step >= lim) break;
+            if (row + 3 * step < lim) FB::template load<ALIGNED>(A, K, ldk, p, row + 3 * step, lim);
+            run(B, row + step);
+            if (row + 2 * step >= lim) break;
+            if (row + 4 * step < lim) FB::template load<ALIGNED>(B, K, ldk, p, row + 4 * step, lim);
+            run(C, row + 2 * step);
+        }
+    } else {
+        for (int64_t row = first; row < lim; row += 2 * step) {
+            if (row + step < lim) FB::template load<ALIGNED>(B, K, ldk, p, row + step, lim);
+            run(A, row);
+            if (row + step >= lim) break;
+            if (row + 2 * step < lim) FB::template load<ALIGNED>(A, K, ldk, p, row + 2 * step, lim);
+            run(B, row + step);
+        }
+    }
+    // flush the last chunk of outputs
+    __syncthreads();
+    if (chunk_first >= 0) {
+        for (int i = tid; i < FCH; i += T) {
+            const int64_t bb = chunk_first + i / RB;
+            const int64_t row = first + bb * step + i % RB;
+            if (row < lim && i < kl) tout[row] = s_t[i];
+        }
     }
     // direction dots over this workgroup's column slice
     double dsum[2] = {0.0, 0.0}, dmx[1] = {0.0};

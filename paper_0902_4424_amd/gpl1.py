@@ -32,7 +32,7 @@ class GPOpts(C.Structure):
                 ("refresh_every", C.c_int32), ("backtrack_cap", C.c_int32),
                 ("chunk", C.c_int32), ("fused_cfg", C.c_int32),
                 ("fused_grid", C.c_int32), ("profile", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("fused_interleave", C.c_int32)]
 
 
 class GPResult(C.Structure):
@@ -300,6 +300,7 @@ def _tuned(kdt, n, p, kw):
     kw = dict(kw)
     kw["fused_cfg"] = int(t["fused_cfg"])
     kw["fused_grid"] = int(t["fused_grid"])
+    kw["fused_interleave"] = int(t.get("fused_interleave", 0))
     return kw
 
 

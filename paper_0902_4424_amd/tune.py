@@ -17,11 +17,13 @@ import time
 PKG = os.path.dirname(os.path.abspath(__file__))
 TABLE = os.path.join(PKG, "tuned.json")
 
-# (threads, chunks per thread) of the library's configurations 1..6; a
-# configuration covers T * CPT * (16 / element size) columns
-CFG_COVER = {1: (256, 1), 2: (256, 2), 3: (256, 4), 4: (512, 4), 5: (512, 8), 6: (1024, 8)}
+# (threads, chunks per thread) of the library's configurations 1..10; a
+# configuration covers T * CPT * (16 / element size) columns.  Shape 6 spills
+# registers and is tried only when nothing else covers p.
+CFG_COVER = {1: (256, 1), 2: (256, 2), 3: (256, 4), 4: (512, 4), 5: (512, 8), 6: (1024, 8),
+             7: (256, 4), 8: (512, 4), 9: (512, 8), 10: (1024, 4)}
 ESIZE = {"f64": 8, "f32": 4, "bf16": 2}
-GRIDS = (32, 64, 128, 192, 256, 320, 384, 512)
+GRIDS = (64, 128, 192, 256, 384, 512)
 
 
 def key(dtype, n, p):
@@ -43,11 +45,15 @@ def lookup(dtype, n, p):
 def candidates(dtype, n, p):
     vec = 16 // ESIZE[dtype]
     out = []
+    covering = [c for c, (T, cpt) in CFG_COVER.items() if T * cpt * vec >= p]
     for c, (T, cpt) in CFG_COVER.items():
+        if c == 6 and len(covering) > 1:
+            continue
         if T * cpt * vec >= p and T * cpt * vec < 4 * max(p, 1):
             for g in GRIDS:
                 if g <= n:
-                    out.append((c, g))
+                    for il in (0, 1):
+                        out.append((c, g, il))
     return out
 
 
@@ -62,8 +68,9 @@ def tune_shape(H, dtype, n, p, iters=40, reps=3, log=print):
         K = torch.from_numpy(inst.K_store).cuda()
     y = torch.from_numpy(inst.y_store).cuda()
     best = None
-    for cfg, grid in candidates(dtype, n, p):
-        opts = gpl1.default_opts(max_iter=iters, profile=1, fused_cfg=cfg, fused_grid=grid)
+    for cfg, grid, il in candidates(dtype, n, p):
+        opts = gpl1.default_opts(max_iter=iters, profile=1, fused_cfg=cfg, fused_grid=grid,
+                                 fused_interleave=il)
         H.solve(K, y, inst.rho, tol=0.0, opts=opts)          # warm
         torch.cuda.synchronize()
         fused, it_us = [], []
@@ -74,10 +81,11 @@ def tune_shape(H, dtype, n, p, iters=40, reps=3, log=print):
             fused.append(res["t_fused_ms"] * 1e3 / max(res["n_fused"], 1))
             it_us.append(dt * 1e6 / max(res["iters"], 1))
         f_us, i_us = min(fused), min(it_us)
-        log(f"  {key(dtype, n, p)} cfg={cfg} grid={grid}: fused {f_us:8.2f} us  iteration {i_us:8.2f} us")
+        log(f"  {key(dtype, n, p)} cfg={cfg} grid={grid} interleave={il}: fused {f_us:8.2f} us  "
+            f"iteration {i_us:8.2f} us")
         if best is None or i_us < best["iter_us"]:
-            best = {"fused_cfg": cfg, "fused_grid": grid, "fused_us": round(f_us, 3),
-                    "iter_us": round(i_us, 3)}
+            best = {"fused_cfg": cfg, "fused_grid": grid, "fused_interleave": il,
+                    "fused_us": round(f_us, 3), "iter_us": round(i_us, 3)}
     return best
 
 
