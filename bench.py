@@ -68,6 +68,92 @@ def blas_threads():
     return os.cpu_count()
 
 
+def _gap(K64, y64, x, f_ref):
+    import numpy as np
+    r = K64 @ np.asarray(x, dtype=np.float64) - y64
+    return (float(r @ r) - f_ref) / f_ref
+
+
+def forms_legs(H, inst, np, torch, gpl1, instances, out):
+    """BF16 storage of the same instance, and many right-hand sides sharing one
+    bf16 K, each timed to a tight stop and checked in FP64 on the host."""
+    res = {}
+    dev = torch.device("cuda:0")
+    # BF16 storage of the benchmark instance: parity against the oracle is
+    # judged on the bf16 K (widened), the error against the FP32-stored K is
+    # reported
+    b16 = instances.plain_large(seed=2, dtype="bf16")
+    Kb = torch.from_numpy(b16.K_store.view(np.int16)).to(dev)
+    yb = torch.from_numpy(b16.y_store).to(dev)
+    ob = gpl1.default_opts(max_iter=ITERS, refresh_every=REFRESH, profile=1)
+    H.solve(Kb, yb, b16.rho, tol=0.0, opts=ob)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    xb, rb = H.solve(Kb, yb, b16.rho, tol=0.0, opts=ob)
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t0
+    K64b = b16.K64
+    y64 = b16.y64
+    xl, _ = H.solve(Kb, yb, b16.rho, tol=0.0, max_iter=3000, refresh_every=REFRESH)
+    f_ref = float(np.sum((K64b @ xl.cpu().double().numpy() - y64) ** 2))
+    xbn = xb.cpu().double().numpy()
+    fused_us = rb["t_fused_ms"] * 1e3 / max(rb["n_fused"], 1)
+    alg = inst.n * inst.p * 2 + 8 * inst.p + 16 * inst.n + 4 * inst.p
+    res["bf16_storage"] = {
+        "workload": "same instance, K stored bf16 (128 MiB)", "iterations": rb["iters"],
+        "status": rb["status_name"], "seconds": round(tb, 5),
+        "iterations_per_s": round(rb["iters"] / tb, 1),
+        "fused_avg_us": round(fused_us, 2), "fused_GBps": round(alg / fused_us / 1e3, 1),
+        "gap_vs_bf16_ref": _gap(K64b, y64, xbn, f_ref),
+        "x_rel_diff_vs_fp32_storage_solution": float(
+            np.linalg.norm(xbn - out.get("_x_fp32", xbn)) / max(np.linalg.norm(out.get("_x_fp32", xbn)), 1e-300))}
+    log(f"bf16 storage: {rb['iters']} iterations in {tb * 1e3:.2f} ms; fused {fused_us:.1f} us")
+    del Kb, K64b
+
+    # many right-hand sides sharing one bf16 K (matrix-core GEMMs)
+    batch = instances.shared_rhs(seed=5, dtype="bf16")
+    Ks = torch.from_numpy(batch.K_store.view(np.int16)).to(dev)
+    Y = torch.from_numpy(batch.Y_store).to(dev)
+    kw = dict(tol=1e-10, max_iter=5000, refresh_every=REFRESH)
+    H.solve_batched_shared(Ks, Y, batch.rho, **kw)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    X, rs = H.solve_batched_shared(Ks, Y, batch.rho, **kw)
+    torch.cuda.synchronize()
+    tbat = time.perf_counter() - t0
+    its = [r["iters"] for r in rs]
+    # plain solver on 8 of the columns, one at a time
+    t0 = time.perf_counter()
+    pits = 0
+    for b in range(8):
+        _, r1 = H.solve(Ks, Y[b].contiguous(), float(batch.rho[b]), **kw)
+        pits += r1["iters"]
+    torch.cuda.synchronize()
+    tpl = (time.perf_counter() - t0) / 8
+    # reference: a long batched run; gaps recomputed in FP64 on the host
+    Xl, _ = H.solve_batched_shared(Ks, Y, batch.rho, tol=0.0, max_iter=3000, refresh_every=REFRESH)
+    K64 = batch.K64
+    Xn, Xln = X.cpu().double().numpy(), Xl.cpu().double().numpy()
+    gaps = []
+    for b in range(0, batch.B, 16):
+        y = batch.Y_store[b].astype(np.float64)
+        fr = float(np.sum((K64 @ Xln[b] - y) ** 2))
+        gaps.append(_gap(K64, y, Xn[b], fr))
+    res["batched_shared"] = {
+        "workload": "K 2048x8192 bf16 shared by 256 right-hand sides (102-sparse +-1, sigma 1e-2), "
+                    "each to relative change < 1e-10",
+        "seconds": round(tbat, 5), "rhs_iterations_per_s": round(sum(its) / tbat, 1),
+        "iterations_min_mean_max": [min(its), round(float(np.mean(its)), 1), max(its)],
+        "statuses": sorted(set(r["status_name"] for r in rs)),
+        "max_gap_sampled_16_columns": max(gaps),
+        "plain_solver_seconds_per_column": round(tpl, 6),
+        "plain_solver_seconds_for_256_extrapolated": round(256 * tpl, 4),
+        "speedup_vs_plain_per_column": round(256 * tpl / tbat, 2)}
+    log(f"batched shared: {tbat * 1e3:.1f} ms for 256 columns; plain {tpl * 1e3:.2f} ms/column; "
+        f"max sampled gap {max(gaps):.2e}")
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -75,6 +161,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-gap", action="store_true", help="skip the time-to-gap leg")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="skip the BF16-storage and batched legs")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one plain 256 MiB device-to-device copy (a reference "
                          "kernel of known traffic for hardware-counter scaling)")
@@ -191,6 +279,12 @@ def main():
             "f_ref_frank_wolfe_bound_rel": fw / f_ref}
         log(f"time to 1e-6 gap: {tg * 1e3:.2f} ms, {rg['iters']} iterations, "
             f"gap {(fg - f_ref) / f_ref:.2e} (FW bound of ref {fw / f_ref:.1e})")
+
+    # ---- the other forms: BF16 storage, batched shared K --------------------
+    if not args.no_forms:
+        out["_x_fp32"] = x_gpu
+        out["forms"] = forms_legs(H, inst, np, torch, gpl1, instances, out)
+        del out["_x_fp32"]
 
     # ---- CPU oracle baseline + parity at 500 iterations --------------------
     if not args.no_cpu_baseline:

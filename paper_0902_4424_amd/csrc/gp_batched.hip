@@ -1,6 +1,7 @@
-// Batched entry points.  This translation unit runs the batch as a sequence
-// of single-problem solves on the caller's stream; every problem keeps its
-// own steplength, threshold and line-search state.
+// Batched entry points.  Shared K in bf16 runs on the matrix cores
+// (gp_batched_shared.hip); other cases run as a sequence of single-problem
+// solves on the caller's stream.  Every problem keeps its own steplength,
+// threshold and line-search state.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -30,6 +31,22 @@ extern "C" int gp_l1_solve_batched_shared(gp_handle h, gp_dtype kdtype, const vo
     if (B == 0) return GP_OK_TOL;
     if (!res || !rho || !Y || !X_out) return fail(h, GP_E_ARG, "null pointer argument");
     if (ldy < n || ldx < p) return fail(h, GP_E_ARG, "ldy must be >= n and ldx >= p");
+    if (n <= 0 || p <= 0 || ldk < p) return fail(h, GP_E_ARG, "bad matrix shape");
+    if (!K) return fail(h, GP_E_ARG, "null K");
+    if (!(tol >= 0.0)) return fail(h, GP_E_ARG, "tol must be >= 0");
+    for (int64_t b = 0; b < B; ++b)
+        if (!(rho[b] >= 0.0) || !std::isfinite(rho[b])) return fail(h, GP_E_ARG, "rho must be finite and >= 0");
+    gp_opts o;
+    if (opts) o = *opts; else gp_opts_default(&o);
+    int rc0 = check_opts(h, o);
+    if (rc0) return rc0;
+    for (int64_t b = 0; b < B; ++b) { std::memset(&res[b], 0, sizeof(gp_result)); res[b].status = GP_E_ARG; }
+    hipError_t e = hipSetDevice(h->device);
+    if (e != hipSuccess) return hip_fail(h, e, "hipSetDevice");
+    // the matrix-core path for bf16 K; other dtypes run one problem at a time
+    int rcm = solve_batched_shared_mfma(h, kdtype, K, n, p, ldk, Y, ldy, B, rho, X0, ldx, tol, X_out, o, res,
+                                        (hipStream_t)stream);
+    if (rcm != GP_E_UNSUPPORTED) return rcm;
     const size_t vsz = kdtype == GP_F64 ? 8 : 4;
     int worst = GP_OK_TOL;
     for (int64_t b = 0; b < B; ++b) {

@@ -1,0 +1,536 @@
+// Batched GPSS: B problems min ||K x_b - y_b||^2 s.t. ||x_b||_1 <= rho_b that
+// share one bf16 K.  The two matrix products of an iteration become GEMMs on
+// the bf16 matrix cores (gp_gemm.hpp):
+//     Q = K D          (n x B, D = [d_1 .. d_B], the projected directions)
+//     W = K^T Q        (p x B, W = K^T K D: the gradient change, since
+//                       g_b(x + lam d) = g_b + 2 lam K^T K d_b)
+// with D and Q split into three bf16 planes each, so the products carry FP32
+// accuracy.  K^T is a transposed bf16 copy made once per call so that both
+// GEMMs read their left operand with the reduction index contiguous.
+//
+// Everything per problem (projection and threshold search, the steplength
+// rule of Algorithm 2, the closed-form Armijo backtracking of Algorithm 1,
+// vector updates, stopping) runs in workgroups that each own one problem, so
+// all per-problem scalars stay on the device and finished problems are
+// frozen by their own flag.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "gp_gemm.hpp"
+#include "gp_internal.hpp"
+#include "gp_kernels.hpp"
+#include "gp_l1.h"
+
+using namespace gpl1;
+
+namespace gpl1 {
+
+constexpr int BS_T = 1024;          // threads of the per-problem workgroups
+constexpr int BS_PAD = 128;         // GEMM tile: M, N padding
+constexpr int NSPL = 3;             // bf16 planes per FP32 operand
+
+enum BsRowMode : int32_t { BR_REFRESH = 0, BR_ITER = 1 };
+enum BsColMode : int32_t { BC_INIT = 0, BC_ITER = 1, BC_ITER_NOPROJ = 2, BC_REFRESH_PROJ = 3 };
+
+__device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf16_bits_to_f32(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+
+// v = hi + mid + lo with each part a bf16 (hi = bf16(v), mid = bf16(v - hi),
+// lo = bf16(v - hi - mid), remainders formed in double).
+__device__ __forceinline__ void split3(double v, uint16_t* planes, int64_t pstride, int64_t idx) {
+    const uint16_t h = f32_to_bf16_rne((float)v);
+    const double r1 = v - (double)bf16_bits_to_f32(h);
+    const uint16_t mmid = f32_to_bf16_rne((float)r1);
+    const double r2 = r1 - (double)bf16_bits_to_f32(mmid);
+    const uint16_t l = f32_to_bf16_rne((float)r2);
+    planes[idx] = h;
+    planes[pstride + idx] = mmid;
+    planes[2 * pstride + idx] = l;
+}
+
+// Padded copies of K: Kp (npad x ppad, row-major) and Kt (ppad x npad).
+__global__ void k_bs_pack(const uint16_t* __restrict__ K, int64_t n, int64_t p, int64_t ldk,
+                          uint16_t* __restrict__ Kp, int64_t ldkp, uint16_t* __restrict__ Kt, int64_t ldkt) {
+    __shared__ uint16_t tile[64][65];
+    const int64_t i0 = (int64_t)blockIdx.y * 64, j0 = (int64_t)blockIdx.x * 64;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;   // 256 threads: 64 x 4
+    for (int r = ty; r < 64; r += 4) {
+        const int64_t i = i0 + r, j = j0 + tx;
+        const uint16_t v = (i < n && j < p) ? K[i * ldk + j] : (uint16_t)0;
+        tile[r][tx] = v;
+        Kp[i * ldkp + j] = v;
+    }
+    __syncthreads();
+    for (int r = ty; r < 64; r += 4) {
+        const int64_t j = j0 + r, i = i0 + tx;
+        Kt[j * ldkt + i] = tile[tx][r];
+    }
+}
+
+struct BsPtrs {
+    GPState* st; int32_t* done;
+    double *X, *G, *H, *R, *Y, *Qv;          // B x p (X, G, H) and B x n (R, Y, Qv), ld = p / n
+    uint16_t *Dsp, *Qsp;                      // GEMM right operands: 3 planes of Bpad x ppad / npad
+    const float *Qpart, *Wpart;               // GEMM partial outputs
+    int64_t n, p, npad, ppad, plD, plQ;       // plane strides of Dsp / Qsp
+    int S1, S2;                               // split-K chunks of the two GEMMs
+    int64_t sQ, sW;                           // partial strides (elements)
+};
+
+// ---------------------------------------------------------------------------
+// init: state, x0 (projected if outside the ball), y; X split for K X
+// ---------------------------------------------------------------------------
+template <int NV>
+__global__ __launch_bounds__(BS_T) void k_bs_init(BsPtrs P, GPParams prm, const double* __restrict__ rho,
+                                                  const void* __restrict__ Y, int64_t ldy,
+                                                  const void* __restrict__ X0, int64_t ldx, int f64v) {
+    __shared__ double lds[3 * (BS_T / WAVE)];
+    const int b = blockIdx.x, tid = threadIdx.x;
+    const int64_t n = P.n, p = P.p;
+    double* x = P.X + b * p;
+    double* y = P.Y + b * n;
+    for (int64_t i = tid; i < n; i += BS_T)
+        y[i] = f64v ? ((const double*)Y)[b * ldy + i] : (double)((const float*)Y)[b * ldy + i];
+    double vr[NV];
+#pragma unroll
+    for (int e = 0; e < NV; ++e) {
+        const int j = 2 * ((e / 2) * BS_T + tid) + (e & 1);
+        double v = 0.0;
+        if (X0 && j < p) v = f64v ? ((const double*)X0)[b * ldx + j] : (double)((const float*)X0)[b * ldx + j];
+        vr[e] = v;
+    }
+    double m, t;
+    bool inside;
+    int passes;
+    const double rb = rho[b];
+    l1_threshold_regs<BS_T, NV>(vr, p, rb, -1.0, lds, m, t, inside, passes);
+#pragma unroll
+    for (int e = 0; e < NV; ++e) {
+        const int j = 2 * ((e / 2) * BS_T + tid) + (e & 1);
+        if (j < p) {
+            const double h = l1_hval(vr[e], m, t, inside, rb);
+            x[j] = h;
+            split3(h, P.Dsp, P.plD, b * P.ppad + j);
+        }
+    }
+    if (tid == 0) {
+        GPState s = {};
+        s.prm = prm;
+        s.prm.rho = rb;
+        s.tau = prm.tau1;
+        s.alpha = prm.amax;
+        s.status = ST_MAX_ITER;
+        s.projected = inside ? 0 : 1;
+        s.live = 1;
+        P.st[b] = s;
+        P.done[b] = 0;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// row side: t = sum of the K-products; refresh (r = t - y) or the line search
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(BS_T) void k_bs_rows(BsPtrs P, int mode, int refresh_next) {
+    __shared__ double lds[3 * (BS_T / WAVE)];
+    __shared__ double sh[4];
+    const int b = blockIdx.x, tid = threadIdx.x;
+    GPState* st = P.st + b;
+    if (P.done[b]) return;
+    const int64_t n = P.n, p = P.p;
+    double* r = P.R + b * n;
+    const double* y = P.Y + b * n;
+    double* qv = P.Qv + b * n;
+    auto tval = [&](int64_t i) {
+        double s = 0.0;
+        for (int c = 0; c < P.S1; ++c) s += (double)P.Qpart[c * P.sQ + b * P.npad + i];
+        return s;
+    };
+    if (mode == BR_REFRESH) {
+        double acc[1] = {0.0}, none[1] = {0.0};
+        for (int64_t i = tid; i < n; i += BS_T) {
+            const double ri = tval(i) - y[i];
+            r[i] = ri;
+            acc[0] += ri * ri;
+            split3(ri, P.Qsp, P.plQ, b * P.npad + i);
+        }
+        block_reduce<BS_T, 1, 1>(acc, none, lds);
+        if (tid == 0) {
+            const double f = acc[0];
+            if (st->k == 0 && st->nhist == 0) {
+                st->hpos = 0;
+                st->fhist[0] = f;
+                st->nhist = 1;
+            } else {
+                st->fhist[st->hpos] = f;
+            }
+            st->f = f;
+            if (!isfinite(f)) { st->status = ST_NONFINITE; st->done = 1; P.done[b] = 1; }
+        }
+        return;
+    }
+    // iteration: q = K d, its dots, the Armijo step, then r, x updates
+    double acc[2] = {0.0, 0.0}, none[1] = {0.0};
+    for (int64_t i = tid; i < n; i += BS_T) {
+        const double qi = tval(i);
+        qv[i] = qi;
+        acc[0] += qi * qi;
+        acc[1] += r[i] * qi;
+    }
+    block_reduce<BS_T, 2, 1>(acc, none, lds);
+    if (tid == 0) {
+        const GPParams& Pm = st->prm;
+        const double qq = acc[0], rq = acc[1], f = st->f, gd = st->gd;
+        double fmax = f;
+        const int nh = st->nhist < Pm.M ? st->nhist : Pm.M;
+        for (int i = 0; i < nh; ++i) fmax = fmax > st->fhist[(st->hpos - i + MAX_M) % MAX_M]
+                                              ? fmax : st->fhist[(st->hpos - i + MAX_M) % MAX_M];
+        double lam = 1.0;
+        int nb = 0;
+        bool fail = false;
+        for (;;) {
+            const double inc = lam * (2.0 * rq + lam * qq);
+            if (inc <= (fmax - f) + Pm.beta * lam * gd) break;
+            if (++nb > Pm.bt_cap) { fail = true; break; }
+            lam *= Pm.theta;
+        }
+        sh[0] = lam;
+        sh[1] = fail ? 1.0 : 0.0;
+        if (fail) {
+            st->status = ST_BACKTRACK;
+            st->done = 1;
+            P.done[b] = 1;
+        } else {
+            const double fn = f + lam * (2.0 * rq + lam * qq);
+            st->lam = lam;
+            st->nb = nb;
+            st->backtracks += nb;
+            st->rel = (f - fn) / f;
+            st->f = fn;
+            st->k += 1;
+            st->hpos = (st->hpos + 1) % MAX_M;
+            st->fhist[st->hpos] = fn;
+            if (st->nhist < MAX_M) st->nhist++;
+            st->ss_pending = 1;
+            int stop = 0;
+            if (!isfinite(fn)) { st->status = ST_NONFINITE; stop = 1; }
+            else if (Pm.f_target >= 0.0 && fn <= Pm.f_target) { st->status = ST_TARGET; stop = 1; }
+            else if (Pm.tol > 0.0 && st->rel < Pm.tol) { st->status = ST_OK_TOL; stop = 1; }
+            else if (st->k >= Pm.max_iter) { st->status = ST_MAX_ITER; stop = 1; }
+            if (stop) { st->done = 1; P.done[b] = 1; }
+        }
+    }
+    __syncthreads();
+    if (sh[1] != 0.0) return;
+    const double lam = sh[0];
+    for (int64_t i = tid; i < n; i += BS_T) {
+        const double qi = qv[i];
+        r[i] += lam * qi;
+        split3(qi, P.Qsp, P.plQ, b * P.npad + i);
+    }
+    double* x = P.X + b * p;
+    double* hd = P.H + b * p;       // holds h on entry, d on exit
+    for (int64_t j = tid; j < p; j += BS_T) {
+        const double xj = x[j];
+        const double dj = hd[j] - xj;
+        const double xn = xj + lam * dj;
+        x[j] = xn;
+        hd[j] = dj;
+        if (refresh_next) split3(xn, P.Dsp, P.plD, b * P.ppad + j);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// column side: gradient update from W = K^T Q, steplength rule, projection,
+// direction d = P(x - alpha g) - x and its dots, d split for the next K D
+// ---------------------------------------------------------------------------
+template <int NV>
+__global__ __launch_bounds__(BS_T) void k_bs_cols(BsPtrs P, int mode) {
+    __shared__ double lds[3 * (BS_T / WAVE)];
+    __shared__ double sh[4];
+    const int b = blockIdx.x, tid = threadIdx.x;
+    GPState* st = P.st + b;
+    const int64_t p = P.p;
+    double* x = P.X + b * p;
+    double* g = P.G + b * p;
+    double* hd = P.H + b * p;
+    const int need_ss = (mode == BC_ITER || mode == BC_ITER_NOPROJ) ? st->ss_pending : 0;
+    const int col_done = P.done[b];
+    if (col_done && !need_ss) return;
+    auto wval = [&](int64_t j) {
+        double s = 0.0;
+        for (int c = 0; c < P.S2; ++c) s += (double)P.Wpart[c * P.sW + b * P.ppad + j];
+        return s;
+    };
+    if (mode == BC_INIT || mode == BC_REFRESH_PROJ) {
+        for (int64_t j = tid; j < p; j += BS_T) g[j] = 2.0 * wval(j);
+    } else if (need_ss) {
+        const double lam = st->lam;
+        double acc[2] = {0.0, 0.0}, none[1] = {0.0};
+        for (int64_t j = tid; j < p; j += BS_T) {
+            const double w = wval(j);
+            g[j] += 2.0 * lam * w;
+            acc[0] += hd[j] * w;     // d'w
+            acc[1] += w * w;         // w'w
+        }
+        block_reduce<BS_T, 2, 1>(acc, none, lds);
+        if (tid == 0) {
+            // s = lam d, z = 2 lam w: s's = lam^2 d'd, s'z = 2 lam^2 d'w,
+            // z'z = 4 lam^2 w'w (equation (5)), then Algorithm 2
+            const double l2 = lam * lam;
+            ss_update(st, st->k, l2 * st->dd, 2.0 * l2 * acc[0], 4.0 * l2 * acc[1]);
+            st->ss_pending = 0;
+        }
+    }
+    if (col_done || mode == BC_ITER_NOPROJ) return;
+    __syncthreads();
+    if (tid == 0) { sh[0] = st->alpha; sh[1] = st->mu; sh[2] = st->prm.rho; }
+    __syncthreads();
+    const double rho = sh[2];
+    double vr[NV];
+    double m, t;
+    bool inside;
+    int passes;
+    double alpha;
+    if (mode == BC_INIT) {
+        // alpha_0 = max{alpha_min, min{1/||P(x0 - grad f(x0))||_inf, alpha_max}}
+#pragma unroll
+        for (int e = 0; e < NV; ++e) {
+            const int j = 2 * ((e / 2) * BS_T + tid) + (e & 1);
+            vr[e] = j < p ? x[j] - g[j] : 0.0;
+        }
+        l1_threshold_regs<BS_T, NV>(vr, p, rho, -1.0, lds, m, t, inside, passes);
+        double hm = 0.0;
+#pragma unroll
+        for (int e = 0; e < NV; ++e) hm = fmax(hm, fabs(l1_hval(vr[e], m, t, inside, rho)));
+        hm = block_max<BS_T>(hm, lds);
+        alpha = hm > 0.0 ? clamp_alpha(1.0 / hm, st->prm) : st->prm.amax;
+        __syncthreads();
+        if (tid == 0) st->alpha = alpha;
+    } else {
+        alpha = sh[0];
+    }
+    const double mu_prev = mode == BC_INIT ? 0.0 : sh[1];
+#pragma unroll
+    for (int e = 0; e < NV; ++e) {
+        const int j = 2 * ((e / 2) * BS_T + tid) + (e & 1);
+        vr[e] = j < p ? x[j] - alpha * g[j] : 0.0;
+    }
+    // warm start from the previous threshold when it lies below max|v|
+    double mloc = 0.0;
+#pragma unroll
+    for (int e = 0; e < NV; ++e) mloc = fmax(mloc, fabs(vr[e]));
+    mloc = block_max<BS_T>(mloc, lds);
+    const double start = (mu_prev > 0.0 && mu_prev < mloc) ? mu_prev - mloc : -1.0;
+    l1_threshold_regs<BS_T, NV>(vr, p, rho, start, lds, m, t, inside, passes);
+    double sums[2] = {0.0, 0.0}, mx[1] = {0.0};
+#pragma unroll
+    for (int e = 0; e < NV; ++e) {
+        const int j = 2 * ((e / 2) * BS_T + tid) + (e & 1);
+        if (j < p) {
+            const double h = l1_hval(vr[e], m, t, inside, rho);
+            const double xj = x[j];
+            const double dj = h - xj;
+            hd[j] = h;
+            split3(dj, P.Dsp, P.plD, b * P.ppad + j);
+            sums[0] += g[j] * dj;
+            sums[1] += dj * dj;
+            mx[0] = fmax(mx[0], fabs(dj));
+        }
+    }
+    block_reduce<BS_T, 2, 1>(sums, mx, lds);
+    if (tid == 0) {
+        if (!isfinite(m)) { st->status = ST_NONFINITE; st->done = 1; P.done[b] = 1; return; }
+        st->gd = sums[0];
+        st->dd = sums[1];
+        st->dmax = mx[0];
+        st->mu = inside ? 0.0 : m + t;
+        st->michelot_total += passes;
+        if (mx[0] == 0.0 || !(sums[0] < 0.0)) { st->status = ST_STATIONARY; st->done = 1; P.done[b] = 1; }
+    }
+}
+
+// results: ||x||_1, ||g||_inf and x out in the vector dtype
+__global__ __launch_bounds__(BS_T) void k_bs_finish(BsPtrs P, void* __restrict__ Xout, int64_t ldx, int f64v) {
+    __shared__ double lds[3 * (BS_T / WAVE)];
+    const int b = blockIdx.x, tid = threadIdx.x;
+    const int64_t p = P.p;
+    const double* x = P.X + b * p;
+    const double* g = P.G + b * p;
+    double s[1] = {0.0}, mx[1] = {0.0};
+    for (int64_t j = tid; j < p; j += BS_T) {
+        s[0] += fabs(x[j]);
+        mx[0] = fmax(mx[0], fabs(g[j]));
+        if (f64v) ((double*)Xout)[b * ldx + j] = x[j];
+        else ((float*)Xout)[b * ldx + j] = (float)x[j];
+    }
+    block_reduce<BS_T, 1, 1>(s, mx, lds);
+    if (tid == 0) {
+        P.st[b].l1 = s[0];
+        P.st[b].gmax = mx[0];
+    }
+}
+
+namespace {
+
+int bs_nv(int64_t p) {
+    const int64_t per = (p + BS_T - 1) / BS_T;
+    if (per <= 2) return 2;
+    if (per <= 4) return 4;
+    if (per <= 8) return 8;
+    if (per <= 16) return 16;
+    return 0;
+}
+
+#define GPL1_BS_NV_SWITCH(nv, STMT) \
+    switch (nv) {                   \
+        case 2: { constexpr int NVc = 2; STMT; } break;   \
+        case 4: { constexpr int NVc = 4; STMT; } break;   \
+        case 8: { constexpr int NVc = 8; STMT; } break;   \
+        case 16: { constexpr int NVc = 16; STMT; } break; \
+    }
+
+int64_t rup(int64_t a, int64_t m) { return (a + m - 1) / m * m; }
+
+int severity(int s) {
+    if (s < 0) return 100 - s;
+    if (s == GP_BACKTRACK_LIMIT) return 4;
+    if (s == GP_MAX_ITER) return 3;
+    return 1;
+}
+
+}  // namespace
+
+// The MFMA path; returns GP_E_UNSUPPORTED (nothing launched) if the shape or
+// dtype does not fit it.
+int solve_batched_shared_mfma(gp_handle h, gp_dtype kdtype, const void* K, int64_t n, int64_t p, int64_t ldk,
+                              const void* Y, int64_t ldy, int64_t B, const double* rho, const void* X0,
+                              int64_t ldx, double tol, void* X_out, const gp_opts& o, gp_result* res,
+                              hipStream_t s) {
+    if (kdtype != GP_BF16) return GP_E_UNSUPPORTED;
+    const int nv = bs_nv(p);
+    if (nv == 0 || B > (1 << 20)) return GP_E_UNSUPPORTED;
+    const int64_t npad = rup(n, BS_PAD), ppad = rup(p, BS_PAD), bpad = rup(B, BS_PAD);
+    // split-K chunks of about 1024 (multiples of 32) per GEMM
+    auto chunk_of = [](int64_t kd) {
+        int64_t c = std::min<int64_t>(kd, 1024);
+        while (kd % c) c -= 32;
+        return c;
+    };
+    const int64_t kc1 = chunk_of(ppad), kc2 = chunk_of(npad);
+    const int S1 = (int)(ppad / kc1), S2 = (int)(npad / kc2);
+
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t o2 = off; off += (bytes + 255) / 256 * 256; return o2; };
+    const size_t o_st = take(sizeof(GPState) * B), o_done = take(sizeof(int32_t) * B);
+    const size_t o_X = take(8 * B * p), o_G = take(8 * B * p), o_H = take(8 * B * p);
+    const size_t o_R = take(8 * B * n), o_Y = take(8 * B * n), o_Qv = take(8 * B * n);
+    const size_t o_Kp = take(2 * npad * ppad), o_Kt = take(2 * ppad * npad);
+    const size_t o_Dsp = take(2 * NSPL * bpad * ppad), o_Qsp = take(2 * NSPL * bpad * npad);
+    const size_t o_Qp = take(4 * (size_t)S1 * bpad * npad), o_Wp = take(4 * (size_t)S2 * bpad * ppad);
+    const size_t o_rho = take(8 * B);
+    int rc = ensure_workspace(h, off);
+    if (rc) return rc;
+    char* ws = (char*)h->ws;
+    BsPtrs P;
+    P.st = (GPState*)(ws + o_st);
+    P.done = (int32_t*)(ws + o_done);
+    P.X = (double*)(ws + o_X); P.G = (double*)(ws + o_G); P.H = (double*)(ws + o_H);
+    P.R = (double*)(ws + o_R); P.Y = (double*)(ws + o_Y); P.Qv = (double*)(ws + o_Qv);
+    uint16_t* Kp = (uint16_t*)(ws + o_Kp);
+    uint16_t* Kt = (uint16_t*)(ws + o_Kt);
+    P.Dsp = (uint16_t*)(ws + o_Dsp); P.Qsp = (uint16_t*)(ws + o_Qsp);
+    float* Qpart = (float*)(ws + o_Qp);
+    float* Wpart = (float*)(ws + o_Wp);
+    P.Qpart = Qpart; P.Wpart = Wpart;
+    P.n = n; P.p = p; P.npad = npad; P.ppad = ppad;
+    P.plD = bpad * ppad; P.plQ = bpad * npad;
+    P.S1 = S1; P.S2 = S2;
+    P.sQ = bpad * npad; P.sW = bpad * ppad;
+    double* drho = (double*)(ws + o_rho);
+
+    hipError_t e = hipMemcpyAsync(drho, rho, 8 * B, hipMemcpyHostToDevice, s);
+    // zero padding of the GEMM operands (rows beyond n, p and columns beyond B)
+    if (e == hipSuccess) e = hipMemsetAsync(P.Dsp, 0, 2 * NSPL * bpad * ppad, s);
+    if (e == hipSuccess) e = hipMemsetAsync(P.Qsp, 0, 2 * NSPL * bpad * npad, s);
+    if (e != hipSuccess) return hip_fail(h, e, "batched set-up");
+    hipLaunchKernelGGL(k_bs_pack, dim3((unsigned)(ppad / 64), (unsigned)(npad / 64)), dim3(256), 0, s,
+                       (const uint16_t*)K, n, p, ldk, Kp, ppad, Kt, npad);
+    const GPParams prm = make_params(o, 0.0, tol);
+    const int f64v = 0;
+    GPL1_BS_NV_SWITCH(nv, hipLaunchKernelGGL(k_bs_init<NVc>, dim3((unsigned)B), dim3(BS_T), 0, s, P, prm, drho,
+                                             Y, ldy, X0, ldx, f64v));
+    auto gemm1 = [&]() {   // Qpart = K * (Dsp planes)
+        hipLaunchKernelGGL(k_gemm_bf16<NSPL>, dim3((unsigned)(npad / GM_BM), (unsigned)(bpad / GM_BN), (unsigned)S1),
+                           dim3(GM_T), 0, s, Kp, ppad, P.Dsp, ppad, P.plD, (int)kc1, Qpart, npad, P.sQ);
+    };
+    auto gemm2 = [&]() {   // Wpart = K^T * (Qsp planes)
+        hipLaunchKernelGGL(k_gemm_bf16<NSPL>, dim3((unsigned)(ppad / GM_BM), (unsigned)(bpad / GM_BN), (unsigned)S2),
+                           dim3(GM_T), 0, s, Kt, npad, P.Qsp, npad, P.plQ, (int)kc2, Wpart, ppad, P.sW);
+    };
+    auto rows = [&](int mode, int refresh_next) {
+        hipLaunchKernelGGL(k_bs_rows, dim3((unsigned)B), dim3(BS_T), 0, s, P, mode, refresh_next);
+    };
+    auto cols = [&](int mode) {
+        GPL1_BS_NV_SWITCH(nv, hipLaunchKernelGGL(k_bs_cols<NVc>, dim3((unsigned)B), dim3(BS_T), 0, s, P, mode));
+    };
+    // r = K x - y, g = 2 K^T r, alpha_0, first direction
+    gemm1();
+    rows(BR_REFRESH, 0);
+    gemm2();
+    cols(BC_INIT);
+    e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(h, e, "batched init launch");
+
+    std::vector<int32_t> hdone((size_t)B);
+    int it = 0;
+    while (it < o.max_iter) {
+        const int end = std::min(o.max_iter, it + o.chunk);
+        for (; it < end; ++it) {
+            const bool refresh = o.refresh_every > 0 && (it + 1) % o.refresh_every == 0 && it + 1 < o.max_iter;
+            gemm1();
+            rows(BR_ITER, refresh ? 1 : 0);
+            gemm2();
+            if (refresh) {
+                cols(BC_ITER_NOPROJ);
+                gemm1();
+                rows(BR_REFRESH, 0);
+                gemm2();
+                cols(BC_REFRESH_PROJ);
+            } else {
+                cols(BC_ITER);
+            }
+        }
+        e = hipGetLastError();
+        if (e != hipSuccess) return hip_fail(h, e, "batched iteration launch");
+        if (it < o.max_iter) {
+            e = hipMemcpyAsync(hdone.data(), P.done, 4 * B, hipMemcpyDeviceToHost, s);
+            if (e == hipSuccess) e = hipStreamSynchronize(s);
+            if (e != hipSuccess) return hip_fail(h, e, "batched status poll");
+            bool all = true;
+            for (int64_t b = 0; b < B && all; ++b) all = hdone[(size_t)b] != 0;
+            if (all) break;
+        }
+    }
+    hipLaunchKernelGGL(k_bs_finish, dim3((unsigned)B), dim3(BS_T), 0, s, P, X_out, ldx, f64v);
+    std::vector<GPState> hst((size_t)B);
+    e = hipMemcpyAsync(hst.data(), P.st, sizeof(GPState) * B, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(h, e, "batched final sync");
+    int worst = GP_OK_TOL;
+    for (int64_t b = 0; b < B; ++b) {
+        fill_result(hst[(size_t)b], &res[b]);
+        if (severity(res[b].status) > severity(worst)) worst = res[b].status;
+    }
+    return worst;
+}
+
+}  // namespace gpl1

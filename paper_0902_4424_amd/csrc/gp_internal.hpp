@@ -37,6 +37,14 @@ int ensure_workspace(gp_handle h, size_t bytes);
 void fill_result(const GPState& s, gp_result* res);
 void destroy_extra(gp_handle h);
 const char* status_name(int s);
+GPParams make_params(const gp_opts& o, double rho, double tol);
+int check_opts(gp_handle h, const gp_opts& o);
+// Batched shared-K solve on the matrix cores (bf16 K); GP_E_UNSUPPORTED means
+// nothing was launched and the caller should use another path.
+int solve_batched_shared_mfma(gp_handle h, gp_dtype kdtype, const void* K, int64_t n, int64_t p, int64_t ldk,
+                              const void* Y, int64_t ldy, int64_t B, const double* rho, const void* X0,
+                              int64_t ldx, double tol, void* X_out, const gp_opts& o, gp_result* res,
+                              hipStream_t s);
 // Profiling helpers: record an event pair around a launch; sum at the end.
 hipEvent_t prof_event(gp_handle h);
 double prof_collect(gp_handle h, int live, int* pairs);

@@ -134,6 +134,62 @@ __device__ __forceinline__ void ss_update(GPState* st, int k, double ss, double 
 // one or two passes.  Every pass is one workgroup reduction of (count, sum)
 // over values held in registers (VPT per thread; VPT = 0 streams from vbuf).
 // ---------------------------------------------------------------------------
+// Threshold of the projection for values held in registers (slot e of
+// thread tid is element 2*((e/2)*T + tid) + (e&1), elements >= p are
+// ignored).  Returns m = max|v|, inside = (||v||_1 <= rho), and t = mu - m
+// (see the k_proj comment for the method).  `start` < 0 is a first guess of
+// t (e.g. from the previous iteration); any value is valid.  Every thread of
+// the workgroup must call it.
+template <int T, int NV>
+__device__ __forceinline__ void l1_threshold_regs(const double (&vr)[NV], int64_t p, double rho, double start,
+                                                  double* lds, double& m, double& t, bool& inside,
+                                                  int& passes) {
+    const int tid = threadIdx.x;
+    double Sm_s[1] = {0.0}, Sm_m[1] = {0.0};
+#pragma unroll
+    for (int e = 0; e < NV; ++e) {
+        const double a = fabs(vr[e]);
+        Sm_s[0] += a;
+        Sm_m[0] = fmax(Sm_m[0], a);
+    }
+    block_reduce<T, 1, 1>(Sm_s, Sm_m, lds);
+    const double Sv = Sm_s[0];
+    m = Sm_m[0];
+    inside = Sv <= rho;
+    t = 0.0;
+    passes = 0;
+    if (inside || !(rho > 0.0) || !isfinite(Sv)) return;
+    t = start < 0.0 ? fmax(-rho, start) : fmax(-rho, (Sv - rho) / (double)p - m);
+    if (!(t < 0.0)) t = -rho;
+    int cprev = -1;
+    bool first = true;
+    for (;;) {
+        int c = 0;
+        double sum = 0.0;
+#pragma unroll
+        for (int e = 0; e < NV; ++e) {
+            const int j = 2 * ((e / 2) * T + tid) + (e & 1);
+            const double b = fabs(vr[e]) - m;
+            if (j < p && b > t) { ++c; sum += b; }
+        }
+        block_sum2<T>(c, sum, lds);
+        ++passes;
+        if (c == cprev || passes >= (1 << 20)) break;
+        cprev = c;
+        const double tn = (sum - rho) / (double)c;
+        t = first ? tn : fmax(t, tn);
+        first = false;
+    }
+}
+
+// h = sgn(v) max((|v| - m) - t, 0); inside: h = v; rho == 0: h = 0.
+__device__ __forceinline__ double l1_hval(double vj, double m, double t, bool inside, double rho) {
+    if (inside) return vj;
+    if (!(rho > 0.0)) return 0.0;
+    const double a = fmax((fabs(vj) - m) - t, 0.0);
+    return vj < 0.0 ? -a : a;
+}
+
 template <int VPT>
 __global__ __launch_bounds__(PROJ_T) void k_proj(GPState* __restrict__ st, int mode, int64_t p,
                                                  double* __restrict__ x, const double* __restrict__ g,
@@ -746,7 +802,7 @@ __global__ __launch_bounds__(UPD_T) void k_update(GPState* __restrict__ st, int 
 // ---------------------------------------------------------------------------
 // small helpers
 // ---------------------------------------------------------------------------
-__global__ void k_init_state(GPState* st, GPParams prm) {
+static __global__ void k_init_state(GPState* st, GPParams prm) {
     GPState s = {};
     s.prm = prm;
     s.live = 1;
@@ -771,7 +827,7 @@ __global__ void k_from_f64(const double* __restrict__ in, TV* __restrict__ out, 
 }
 
 // Commit the last update and compute ||x||_1 and ||g||_inf for the result.
-__global__ __launch_bounds__(PROJ_T) void k_finish(GPState* __restrict__ st, const double* __restrict__ x,
+static __global__ __launch_bounds__(PROJ_T) void k_finish(GPState* __restrict__ st, const double* __restrict__ x,
                                                    const double* __restrict__ g, int64_t p) {
     __shared__ double lds[PROJ_T / WAVE];
     double l1 = 0.0, gm = 0.0;

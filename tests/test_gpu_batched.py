@@ -1,0 +1,123 @@
+"""GPU parity of the batched solvers against the FP64 oracle (through the C ABI).
+
+Shared K (bf16 storage, matrix-core GEMMs with three-plane bf16 operands):
+every column must meet the FP32-path bar against the oracle run on the same
+stored K widened to FP64: relative objective gap <= 1e-6 and
+||x - x_oracle|| / ||x_oracle|| <= 1e-4.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import gpss
+from paper_0902_4424_amd import gpl1, instances
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def H():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    h = gpl1.Handle(0)
+    yield h
+    h.close()
+
+
+def _kt(batch):
+    return torch.from_numpy(batch.K_store.view(np.int16)).to(DEV)
+
+
+def _check_columns(batch, X, res, cols, tight_iters=100000, gap_tol=1e-6, err_tol=1e-4):
+    K64 = batch.K64
+    Xn = X.cpu().double().numpy()
+    worst_gap = worst_err = 0.0
+    for b in cols:
+        y = batch.Y_store[b].astype(np.float64)
+        ref = gpss(K64, y, float(batch.rho[b]), tol=0.0, max_iter=tight_iters)
+        x = Xn[b]
+        fx = float(np.sum((K64 @ x - y) ** 2))
+        gap = (fx - ref["f"]) / ref["f"]
+        err = np.linalg.norm(x - ref["x"]) / np.linalg.norm(ref["x"])
+        worst_gap, worst_err = max(worst_gap, gap), max(worst_err, err)
+        assert res[b]["status"] >= 0
+        assert abs(res[b]["l1norm"] - np.abs(x).sum()) <= 1e-6 * max(1.0, batch.rho[b])
+        assert np.abs(x).sum() <= batch.rho[b] * (1 + 1e-6)
+    say(f"   worst gap {worst_gap:.2e}, worst x err {worst_err:.2e} over {len(cols)} columns")
+    assert worst_gap <= gap_tol and worst_err <= err_tol
+
+
+@pytest.mark.parametrize("n,p,B", [(256, 1024, 5), (200, 700, 3), (130, 260, 129)])
+def test_shared_small_matches_oracle(H, n, p, B):
+    say(f"[batched-shared] n={n} p={p} B={B} bf16")
+    batch = instances.shared_batch(n, p, B, max(1, n // 20), dtype="bf16", seed=31 + n,
+                                   rhs_seed_base=700 + p)
+    Y = torch.from_numpy(batch.Y_store).to(DEV)
+    X, res = H.solve_batched_shared(_kt(batch), Y, batch.rho, tol=1e-12, max_iter=3000,
+                                    refresh_every=50)
+    cols = list(range(B)) if B <= 8 else [0, 1, B // 2, B - 1]
+    _check_columns(batch, X, res, cols)
+
+
+def test_shared_refresh_and_warm_start(H):
+    say("[batched-shared] refresh every 7, warm start from the answer")
+    batch = instances.shared_batch(256, 1024, 4, 12, dtype="bf16", seed=8, rhs_seed_base=80)
+    Y = torch.from_numpy(batch.Y_store).to(DEV)
+    X, res = H.solve_batched_shared(_kt(batch), Y, batch.rho, tol=1e-12, max_iter=3000,
+                                    refresh_every=7)
+    _check_columns(batch, X, res, range(4))
+    X2, res2 = H.solve_batched_shared(_kt(batch), Y, batch.rho, X0=X.clone(), tol=1e-12,
+                                      max_iter=3000, refresh_every=50)
+    assert max(r["iters"] for r in res2) <= max(5, min(r["iters"] for r in res) // 2)
+    _check_columns(batch, X2, res2, range(4))
+
+
+def test_shared_agrees_with_single_solves(H):
+    say("[batched-shared] vs plain solver on each column")
+    batch = instances.shared_batch(512, 2048, 3, 25, dtype="bf16", seed=9, rhs_seed_base=90)
+    Kt = _kt(batch)
+    Y = torch.from_numpy(batch.Y_store).to(DEV)
+    X, res = H.solve_batched_shared(Kt, Y, batch.rho, tol=1e-13, max_iter=5000, refresh_every=50)
+    K64 = batch.K64
+    for b in range(3):
+        xs, rs = H.solve(Kt, Y[b].contiguous(), float(batch.rho[b]), tol=1e-13, max_iter=5000,
+                         refresh_every=50)
+        y = batch.Y_store[b].astype(np.float64)
+        fb = np.sum((K64 @ X[b].cpu().double().numpy() - y) ** 2)
+        fs = np.sum((K64 @ xs.cpu().double().numpy() - y) ** 2)
+        assert abs(fb - fs) <= 1e-6 * fs
+
+
+def test_shared_special_columns(H):
+    say("[batched-shared] rho = 0, y = 0 and max_iter stop in one batch")
+    batch = instances.shared_batch(128, 512, 4, 6, dtype="bf16", seed=10, rhs_seed_base=100)
+    Y = torch.from_numpy(batch.Y_store).to(DEV)
+    Y[1] = 0.0
+    rho = list(batch.rho)
+    rho[0] = 0.0
+    X, res = H.solve_batched_shared(_kt(batch), Y, rho, tol=0.0, max_iter=4)
+    assert res[0]["status_name"] == "stationary" and not X[0].any().item()
+    assert res[1]["status_name"] == "stationary" and res[1]["iters"] == 0
+    assert res[2]["status_name"] == "max_iter" and res[2]["iters"] == 4
+    ref = gpss(batch.K64, batch.Y_store[2].astype(np.float64), float(batch.rho[2]), tol=0.0,
+               max_iter=4)
+    np.testing.assert_allclose(X[2].cpu().double().numpy(), ref["x"], rtol=0, atol=1e-5)
+
+
+def test_shared_large_sampled(H):
+    say("[batched-shared] 2048 x 8192 bf16, 64 right-hand sides, 3 sampled columns")
+    batch = instances.shared_batch(2048, 8192, 64, 102, dtype="bf16", seed=5, rhs_seed_base=5000)
+    Y = torch.from_numpy(batch.Y_store).to(DEV)
+    X, res = H.solve_batched_shared(_kt(batch), Y, batch.rho, tol=1e-12, max_iter=5000,
+                                    refresh_every=50)
+    assert all(r["status"] >= 0 for r in res)
+    _check_columns(batch, X, res, [0, 31, 63], tight_iters=20000)
