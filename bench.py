@@ -151,6 +151,49 @@ def forms_legs(H, inst, np, torch, gpl1, instances, out):
         "speedup_vs_plain_per_column": round(256 * tpl / tbat, 2)}
     log(f"batched shared: {tbat * 1e3:.1f} ms for 256 columns; plain {tpl * 1e3:.2f} ms/column; "
         f"max sampled gap {max(gaps):.2e}")
+    del Ks, Y, X, Xl, K64
+
+    # 512 independent problems of uneven size in one lockstep batch
+    t0 = time.time()
+    insts = instances.uneven_batch(512, dtype="bf16", seed=4)
+    probs = [(torch.from_numpy(i.K_store.view(np.int16)).to(dev), torch.from_numpy(i.y_store).to(dev),
+              i.rho) for i in insts]
+    log(f"uneven batch generated in {time.time() - t0:.1f}s")
+    kv = dict(tol=1e-10, max_iter=5000, refresh_every=REFRESH)
+    H.solve_batched_var(probs, **kv)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    Xv, rv = H.solve_batched_var(probs, **kv)
+    torch.cuda.synchronize()
+    tvar = time.perf_counter() - t0
+    sample = list(range(0, 512, 32))
+    t0 = time.perf_counter()
+    for i in sample:
+        H.solve(probs[i][0], probs[i][1], probs[i][2], **kv)
+    torch.cuda.synchronize()
+    tseq = (time.perf_counter() - t0) / len(sample)
+    vgaps = []
+    for i in sample[:6]:
+        inst = insts[i]
+        xl, _ = H.solve(probs[i][0], probs[i][1], probs[i][2], tol=0.0, max_iter=3000,
+                        refresh_every=REFRESH)
+        fr = float(np.sum((inst.K64 @ xl.cpu().double().numpy() - inst.y64) ** 2))
+        vgaps.append(_gap(inst.K64, inst.y64, Xv[i].cpu().double().numpy(), fr))
+    vits = [r["iters"] for r in rv]
+    kbytes = sum(2 * i.n * i.p for i in insts)
+    res["batched_uneven"] = {
+        "workload": "512 problems, n uniform in [128,1024], p = 4n, K bf16 (%.2f GB), each to "
+                    "relative change < 1e-10" % (kbytes / 1e9),
+        "seconds": round(tvar, 5), "problem_iterations_per_s": round(sum(vits) / tvar, 1),
+        "iterations_min_mean_max": [min(vits), round(float(np.mean(vits)), 1), max(vits)],
+        "statuses": sorted(set(r["status_name"] for r in rv)),
+        "max_gap_sampled_6": max(vgaps),
+        "plain_solver_seconds_per_problem": round(tseq, 6),
+        "plain_solver_seconds_for_512_extrapolated": round(512 * tseq, 4),
+        "speedup_vs_plain_per_problem": round(512 * tseq / tvar, 2),
+        "K_GB_per_sweep": round(kbytes / 1e9, 3),
+        "sweep_GBps_lower_bound": round(kbytes * max(vits) / tvar / 1e9, 1)}
+    log(f"batched uneven: {tvar * 1e3:.1f} ms for 512 problems; plain {tseq * 1e3:.2f} ms/problem")
     return res
 
 

@@ -66,6 +66,26 @@ extern "C" int gp_l1_solve_batched_var(gp_handle h, gp_dtype kdtype, const gp_in
     if (B < 0) return fail(h, GP_E_ARG, "B must be >= 0");
     if (B == 0) return GP_OK_TOL;
     if (!inst || !res) return fail(h, GP_E_ARG, "null pointer argument");
+    if (kdtype != GP_F64 && kdtype != GP_F32 && kdtype != GP_BF16) return fail(h, GP_E_ARG, "bad dtype");
+    if (!(tol >= 0.0)) return fail(h, GP_E_ARG, "tol must be >= 0");
+    for (int64_t b = 0; b < B; ++b) {
+        const gp_instance& I = inst[b];
+        if (I.n <= 0 || I.p <= 0 || I.ldk < I.p || !I.K || !I.y || !I.x_out)
+            return fail(h, GP_E_ARG, "instance " + std::to_string(b) + ": bad shape or null pointer");
+        if (!(I.rho >= 0.0) || !std::isfinite(I.rho))
+            return fail(h, GP_E_ARG, "instance " + std::to_string(b) + ": rho must be finite and >= 0");
+        if (I.n > ((int64_t)1 << 31) || I.p > ((int64_t)1 << 31))
+            return fail(h, GP_E_UNSUPPORTED, "instance too large");
+    }
+    gp_opts o;
+    if (opts) o = *opts; else gp_opts_default(&o);
+    int rc0 = check_opts(h, o);
+    if (rc0) return rc0;
+    for (int64_t b = 0; b < B; ++b) { std::memset(&res[b], 0, sizeof(gp_result)); res[b].status = GP_E_ARG; }
+    hipError_t e = hipSetDevice(h->device);
+    if (e != hipSuccess) return hip_fail(h, e, "hipSetDevice");
+    int rcl = solve_batched_var_lockstep(h, kdtype, inst, B, tol, o, res, (hipStream_t)stream);
+    if (rcl != GP_E_UNSUPPORTED) return rcl;
     int worst = GP_OK_TOL;
     for (int64_t b = 0; b < B; ++b) {
         const gp_instance& I = inst[b];

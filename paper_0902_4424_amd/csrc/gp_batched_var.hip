@@ -1,0 +1,457 @@
+// Batched GPSS over independent problems of different sizes.
+//
+// All problems advance in lockstep, three launches per sweep:
+//   k_bv_fused  : a work list of (problem, slab of rows) items; each item
+//                 runs the fused pass of the plain solver (q = K d for its
+//                 rows and a partial p-vector of K^T q from the same read of
+//                 K), so the HBM stream is spread over thousands of
+//                 workgroups whatever the mix of sizes;
+//   k_bv_update : one workgroup per problem: closed-form Armijo backtracking
+//                 (Algorithm 1), x, r, g updates, the dots of equation (5)
+//                 and the steplength rule of Algorithm 2;
+//   k_bv_proj   : one workgroup per problem: projection onto the l1 ball
+//                 (threshold search in registers), direction d = P(v) - x
+//                 and its dots, stationarity.
+// A problem that has stopped is skipped by all three (its own flag).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "gp_internal.hpp"
+#include "gp_kernels.hpp"
+#include "gp_l1.h"
+
+using namespace gpl1;
+
+namespace gpl1 {
+
+constexpr int BV_T = 1024;   // per-problem workgroups
+constexpr int BV_FT = 256;   // fused-pass workgroups
+constexpr int BV_ROWS = 32;  // rows per work item
+
+struct VarInst {
+    const void* K;
+    const void* yin;
+    const void* x0in;
+    void* xout;
+    int64_t n, p, ldk;
+    double rho;
+    double *x, *g, *d, *r, *q, *y;   // FP64 per-problem vectors
+    int64_t item0, nitems, ldw;      // work items (slabs) and partial stride
+    float* wpart;                    // nitems x ldw partial vectors (float accumulation)
+    double* wpart64;                 // same for FP64 K
+    double* spart;                   // nitems x SPART partial dots
+    int32_t aligned;
+    int32_t pad_;
+};
+
+struct VarItem { int32_t inst, slab; };
+
+template <int NV>
+__global__ __launch_bounds__(BV_T) void k_bv_init(const VarInst* __restrict__ I, GPState* __restrict__ st,
+                                                  GPParams prm, int f64v) {
+    __shared__ double lds[3 * (BV_T / WAVE)];
+    const int b = blockIdx.x, tid = threadIdx.x;
+    const VarInst D = I[b];
+    for (int64_t i = tid; i < D.n; i += BV_T)
+        D.y[i] = f64v ? ((const double*)D.yin)[i] : (double)((const float*)D.yin)[i];
+    double vr[NV];
+#pragma unroll
+    for (int e = 0; e < NV; ++e) {
+        const int j = 2 * ((e / 2) * BV_T + tid) + (e & 1);
+        double v = 0.0;
+        if (D.x0in && j < D.p) v = f64v ? ((const double*)D.x0in)[j] : (double)((const float*)D.x0in)[j];
+        vr[e] = v;
+    }
+    double m, t;
+    bool inside;
+    int passes;
+    l1_threshold_regs<BV_T, NV>(vr, D.p, D.rho, -1.0, lds, m, t, inside, passes);
+#pragma unroll
+    for (int e = 0; e < NV; ++e) {
+        const int j = 2 * ((e / 2) * BV_T + tid) + (e & 1);
+        if (j < D.p) D.x[j] = l1_hval(vr[e], m, t, inside, D.rho);
+    }
+    if (tid == 0) {
+        GPState s = {};
+        s.prm = prm;
+        s.prm.rho = D.rho;
+        s.tau = prm.tau1;
+        s.alpha = prm.amax;
+        s.status = ST_MAX_ITER;
+        s.projected = inside ? 0 : 1;
+        s.live = 1;
+        st[b] = s;
+    }
+}
+
+// fused pass on one work item; v = x (refresh, with y subtracted) or d
+template <typename TK, typename ACC, int CPT>
+__global__ __launch_bounds__(BV_FT) void k_bv_fused(const VarInst* __restrict__ I, const VarItem* __restrict__ items,
+                                                    const GPState* __restrict__ st, int refresh) {
+    const VarItem it = items[blockIdx.x];
+    if (st[it.inst].done) return;
+    const VarInst D = I[it.inst];
+    ACC* wp;
+    if constexpr (sizeof(ACC) == 8) wp = (ACC*)D.wpart64;
+    else wp = (ACC*)D.wpart;
+    ACC* wrow = wp + (int64_t)it.slab * D.ldw;
+    double* sp = D.spart + (int64_t)SPART * it.slab;
+    const double* v = refresh ? D.x : D.d;
+    if (D.aligned)
+        fused_body<TK, ACC, BV_FT, CPT, 1, 2, true>((const TK*)D.K, D.n, D.p, D.ldk, BV_ROWS, v, nullptr, nullptr,
+                                                     refresh ? D.y : nullptr, refresh ? nullptr : D.r, D.q, wrow,
+                                                     D.ldw, sp, 0, it.slab, D.nitems);
+    else
+        fused_body<TK, ACC, BV_FT, CPT, 1, 2, false>((const TK*)D.K, D.n, D.p, D.ldk, BV_ROWS, v, nullptr, nullptr,
+                                                      refresh ? D.y : nullptr, refresh ? nullptr : D.r, D.q, wrow,
+                                                      D.ldw, sp, 0, it.slab, D.nitems);
+}
+
+// line search, updates, steplength rule (iteration) or r, g, f (refresh)
+template <typename ACC>
+__global__ __launch_bounds__(BV_T) void k_bv_update(const VarInst* __restrict__ I, GPState* __restrict__ st_all,
+                                                    int refresh) {
+    __shared__ double lds[3 * (BV_T / WAVE)];
+    __shared__ double sh[4];
+    const int b = blockIdx.x, tid = threadIdx.x;
+    GPState* st = st_all + b;
+    if (st->done) return;
+    const VarInst D = I[b];
+    const ACC* wp;
+    if constexpr (sizeof(ACC) == 8) wp = (const ACC*)D.wpart64;
+    else wp = (const ACC*)D.wpart;
+    // partial dots of the items, fixed order
+    double a[2] = {0.0, 0.0}, none[1] = {0.0};
+    for (int64_t i = tid; i < D.nitems; i += BV_T) {
+        a[0] += D.spart[SPART * i];
+        a[1] += D.spart[SPART * i + 1];
+    }
+    block_reduce<BV_T, 2, 1>(a, none, lds);
+    const double tt = a[0], tr = a[1];
+    auto wsum = [&](int64_t j) {
+        double s = 0.0;
+        for (int64_t c = 0; c < D.nitems; ++c) s += (double)wp[c * D.ldw + j];
+        return s;
+    };
+    if (refresh) {
+        for (int64_t i = tid; i < D.n; i += BV_T) D.r[i] = D.q[i];
+        for (int64_t j = tid; j < D.p; j += BV_T) D.g[j] = 2.0 * wsum(j);
+        if (tid == 0) {
+            if (st->k == 0 && st->nhist == 0) { st->hpos = 0; st->nhist = 1; }
+            st->fhist[st->hpos] = tt;
+            st->f = tt;
+            if (!isfinite(tt)) { st->status = ST_NONFINITE; st->done = 1; }
+        }
+        return;
+    }
+    if (tid == 0) {
+        const GPParams& P = st->prm;
+        const double qq = tt, rq = tr, f = st->f, gd = st->gd;
+        double fmax = f;
+        const int nh = st->nhist < P.M ? st->nhist : P.M;
+        for (int i = 0; i < nh; ++i) fmax = fmax > st->fhist[(st->hpos - i + MAX_M) % MAX_M]
+                                              ? fmax : st->fhist[(st->hpos - i + MAX_M) % MAX_M];
+        double lam = 1.0;
+        int nb = 0;
+        bool fail = false;
+        for (;;) {
+            const double inc = lam * (2.0 * rq + lam * qq);
+            if (inc <= (fmax - f) + P.beta * lam * gd) break;
+            if (++nb > P.bt_cap) { fail = true; break; }
+            lam *= P.theta;
+        }
+        sh[0] = lam;
+        sh[1] = fail ? 1.0 : 0.0;
+        if (fail) {
+            st->status = ST_BACKTRACK;
+            st->done = 1;
+        } else {
+            const double fn = f + lam * (2.0 * rq + lam * qq);
+            st->lam = lam;
+            st->nb = nb;
+            st->backtracks += nb;
+            st->rel = (f - fn) / f;
+            st->f = fn;
+            st->k += 1;
+            st->hpos = (st->hpos + 1) % MAX_M;
+            st->fhist[st->hpos] = fn;
+            if (st->nhist < MAX_M) st->nhist++;
+        }
+    }
+    __syncthreads();
+    if (sh[1] != 0.0) return;
+    const double lam = sh[0];
+    for (int64_t i = tid; i < D.n; i += BV_T) D.r[i] += lam * D.q[i];
+    double dots[2] = {0.0, 0.0};
+    for (int64_t j = tid; j < D.p; j += BV_T) {
+        const double w = wsum(j);
+        const double dj = D.d[j];
+        D.x[j] += lam * dj;
+        D.g[j] += 2.0 * lam * w;
+        dots[0] += dj * w;
+        dots[1] += w * w;
+    }
+    block_reduce<BV_T, 2, 1>(dots, none, lds);
+    if (tid == 0) {
+        const GPParams& P = st->prm;
+        // s = lam d, z = 2 lam w: equation (5), then Algorithm 2
+        const double l2 = lam * lam;
+        ss_update(st, st->k, l2 * st->dd, 2.0 * l2 * dots[0], 4.0 * l2 * dots[1]);
+        const double fn = st->f;
+        int stop = 0;
+        if (!isfinite(fn)) { st->status = ST_NONFINITE; stop = 1; }
+        else if (P.f_target >= 0.0 && fn <= P.f_target) { st->status = ST_TARGET; stop = 1; }
+        else if (P.tol > 0.0 && st->rel < P.tol) { st->status = ST_OK_TOL; stop = 1; }
+        else if (st->k >= P.max_iter) { st->status = ST_MAX_ITER; stop = 1; }
+        if (stop) st->done = 1;
+    }
+}
+
+// projection (alpha0 first on init), direction and its dots
+template <int NV>
+__global__ __launch_bounds__(BV_T) void k_bv_proj(const VarInst* __restrict__ I, GPState* __restrict__ st_all,
+                                                  int init) {
+    __shared__ double lds[3 * (BV_T / WAVE)];
+    __shared__ double sh[4];
+    const int b = blockIdx.x, tid = threadIdx.x;
+    GPState* st = st_all + b;
+    if (st->done) return;
+    const VarInst D = I[b];
+    const int64_t p = D.p;
+    const double rho = D.rho;
+    double vr[NV];
+    double m, t;
+    bool inside;
+    int passes;
+    if (tid == 0) { sh[0] = st->alpha; sh[1] = st->mu; }
+    __syncthreads();
+    double alpha = sh[0];
+    if (init) {
+#pragma unroll
+        for (int e = 0; e < NV; ++e) {
+            const int j = 2 * ((e / 2) * BV_T + tid) + (e & 1);
+            vr[e] = j < p ? D.x[j] - D.g[j] : 0.0;
+        }
+        l1_threshold_regs<BV_T, NV>(vr, p, rho, -1.0, lds, m, t, inside, passes);
+        double hm = 0.0;
+#pragma unroll
+        for (int e = 0; e < NV; ++e) hm = fmax(hm, fabs(l1_hval(vr[e], m, t, inside, rho)));
+        hm = block_max<BV_T>(hm, lds);
+        alpha = hm > 0.0 ? clamp_alpha(1.0 / hm, st->prm) : st->prm.amax;
+        __syncthreads();
+        if (tid == 0) st->alpha = alpha;
+    }
+    const double mu_prev = init ? 0.0 : sh[1];
+#pragma unroll
+    for (int e = 0; e < NV; ++e) {
+        const int j = 2 * ((e / 2) * BV_T + tid) + (e & 1);
+        vr[e] = j < p ? D.x[j] - alpha * D.g[j] : 0.0;
+    }
+    double mloc = 0.0;
+#pragma unroll
+    for (int e = 0; e < NV; ++e) mloc = fmax(mloc, fabs(vr[e]));
+    mloc = block_max<BV_T>(mloc, lds);
+    const double start = (mu_prev > 0.0 && mu_prev < mloc) ? mu_prev - mloc : -1.0;
+    l1_threshold_regs<BV_T, NV>(vr, p, rho, start, lds, m, t, inside, passes);
+    double sums[2] = {0.0, 0.0}, mx[1] = {0.0};
+#pragma unroll
+    for (int e = 0; e < NV; ++e) {
+        const int j = 2 * ((e / 2) * BV_T + tid) + (e & 1);
+        if (j < p) {
+            const double dj = l1_hval(vr[e], m, t, inside, rho) - D.x[j];
+            D.d[j] = dj;
+            sums[0] += D.g[j] * dj;
+            sums[1] += dj * dj;
+            mx[0] = fmax(mx[0], fabs(dj));
+        }
+    }
+    block_reduce<BV_T, 2, 1>(sums, mx, lds);
+    if (tid == 0) {
+        st->gd = sums[0];
+        st->dd = sums[1];
+        st->dmax = mx[0];
+        st->mu = inside ? 0.0 : m + t;
+        st->michelot_total += passes;
+        if (!isfinite(m)) { st->status = ST_NONFINITE; st->done = 1; }
+        else if (mx[0] == 0.0 || !(sums[0] < 0.0)) { st->status = ST_STATIONARY; st->done = 1; }
+    }
+}
+
+__global__ __launch_bounds__(BV_T) void k_bv_finish(const VarInst* __restrict__ I, GPState* __restrict__ st_all,
+                                                    int f64v) {
+    __shared__ double lds[3 * (BV_T / WAVE)];
+    const int b = blockIdx.x, tid = threadIdx.x;
+    const VarInst D = I[b];
+    double s[1] = {0.0}, mx[1] = {0.0};
+    for (int64_t j = tid; j < D.p; j += BV_T) {
+        s[0] += fabs(D.x[j]);
+        mx[0] = fmax(mx[0], fabs(D.g[j]));
+        if (f64v) ((double*)D.xout)[j] = D.x[j];
+        else ((float*)D.xout)[j] = (float)D.x[j];
+    }
+    block_reduce<BV_T, 1, 1>(s, mx, lds);
+    if (tid == 0) {
+        st_all[b].l1 = s[0];
+        st_all[b].gmax = mx[0];
+    }
+}
+
+namespace {
+int bv_nv(int64_t p) {
+    const int64_t per = (p + BV_T - 1) / BV_T;
+    if (per <= 2) return 2;
+    if (per <= 4) return 4;
+    if (per <= 8) return 8;
+    if (per <= 16) return 16;
+    return 0;
+}
+int severity(int s) {
+    if (s < 0) return 100 - s;
+    if (s == GP_BACKTRACK_LIMIT) return 4;
+    if (s == GP_MAX_ITER) return 3;
+    return 1;
+}
+#define GPL1_BV_NV_SWITCH(nv, STMT) \
+    switch (nv) {                   \
+        case 2: { constexpr int NVc = 2; STMT; } break;   \
+        case 4: { constexpr int NVc = 4; STMT; } break;   \
+        case 8: { constexpr int NVc = 8; STMT; } break;   \
+        case 16: { constexpr int NVc = 16; STMT; } break; \
+    }
+
+template <typename TK, typename ACC>
+void launch_bv_fused(int cpt, hipStream_t s, unsigned nitems, const VarInst* I, const VarItem* items,
+                     const GPState* st, int refresh) {
+    switch (cpt) {
+        case 1: hipLaunchKernelGGL((k_bv_fused<TK, ACC, 1>), dim3(nitems), dim3(BV_FT), 0, s, I, items, st, refresh); break;
+        case 2: hipLaunchKernelGGL((k_bv_fused<TK, ACC, 2>), dim3(nitems), dim3(BV_FT), 0, s, I, items, st, refresh); break;
+        case 4: hipLaunchKernelGGL((k_bv_fused<TK, ACC, 4>), dim3(nitems), dim3(BV_FT), 0, s, I, items, st, refresh); break;
+    }
+}
+}  // namespace
+
+// Returns GP_E_UNSUPPORTED (nothing launched) when the sizes do not fit.
+int solve_batched_var_lockstep(gp_handle h, gp_dtype kdtype, const gp_instance* inst, int64_t B, double tol,
+                               const gp_opts& o, gp_result* res, hipStream_t s) {
+    const int esz = kdtype == GP_F64 ? 8 : kdtype == GP_F32 ? 4 : 2;
+    const int vec = 16 / esz;
+    int64_t maxp = 0;
+    for (int64_t b = 0; b < B; ++b) maxp = std::max(maxp, inst[b].p);
+    int cpt = 0;
+    for (int c : {1, 2, 4})
+        if ((int64_t)BV_FT * c * vec >= maxp) { cpt = c; break; }
+    const int nv = bv_nv(maxp);
+    if (cpt == 0 || nv == 0) return GP_E_UNSUPPORTED;
+    const bool f64v = kdtype == GP_F64;
+
+    // workspace: states, descriptors, items, vectors, partials
+    std::vector<VarInst> hI((size_t)B);
+    std::vector<VarItem> hitems;
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t o2 = off; off += (bytes + 255) / 256 * 256; return o2; };
+    const size_t o_st = take(sizeof(GPState) * B);
+    const size_t o_I = take(sizeof(VarInst) * B);
+    std::vector<size_t> ox((size_t)B), ow((size_t)B), osp((size_t)B);
+    int64_t total_items = 0;
+    for (int64_t b = 0; b < B; ++b) {
+        const gp_instance& S = inst[b];
+        VarInst& D = hI[(size_t)b];
+        D.K = S.K; D.yin = S.y; D.x0in = S.x0; D.xout = S.x_out;
+        D.n = S.n; D.p = S.p; D.ldk = S.ldk; D.rho = S.rho;
+        D.nitems = (S.n + BV_ROWS - 1) / BV_ROWS;
+        D.item0 = total_items;
+        D.ldw = (S.p + 63) / 64 * 64;
+        D.aligned = (S.ldk % vec == 0) && (((uintptr_t)S.K) % 16 == 0);
+        for (int64_t i = 0; i < D.nitems; ++i) hitems.push_back(VarItem{(int32_t)b, (int32_t)i});
+        total_items += D.nitems;
+        ox[(size_t)b] = take(8 * (3 * S.p + 3 * S.n));
+        ow[(size_t)b] = take((size_t)(f64v ? 8 : 4) * D.nitems * D.ldw);
+        osp[(size_t)b] = take(8 * SPART * D.nitems);
+    }
+    const size_t o_items = take(sizeof(VarItem) * hitems.size());
+    int rc = ensure_workspace(h, off);
+    if (rc) return rc;
+    char* ws = (char*)h->ws;
+    for (int64_t b = 0; b < B; ++b) {
+        VarInst& D = hI[(size_t)b];
+        double* base = (double*)(ws + ox[(size_t)b]);
+        D.x = base; D.g = base + D.p; D.d = base + 2 * D.p;
+        D.r = base + 3 * D.p; D.q = D.r + D.n; D.y = D.q + D.n;
+        D.wpart = f64v ? nullptr : (float*)(ws + ow[(size_t)b]);
+        D.wpart64 = f64v ? (double*)(ws + ow[(size_t)b]) : nullptr;
+        D.spart = (double*)(ws + osp[(size_t)b]);
+    }
+    // longest rows first so that big items start early
+    std::stable_sort(hitems.begin(), hitems.end(), [&](const VarItem& a, const VarItem& c) {
+        return hI[(size_t)a.inst].p > hI[(size_t)c.inst].p;
+    });
+    GPState* st = (GPState*)(ws + o_st);
+    VarInst* dI = (VarInst*)(ws + o_I);
+    VarItem* ditems = (VarItem*)(ws + o_items);
+    hipError_t e = hipMemcpyAsync(dI, hI.data(), sizeof(VarInst) * B, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(ditems, hitems.data(), sizeof(VarItem) * hitems.size(), hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(h, e, "batched-var set-up");
+    const GPParams prm = make_params(o, 0.0, tol);
+    const unsigned nit = (unsigned)hitems.size();
+    auto fused = [&](int refresh) {
+        if (kdtype == GP_F64) launch_bv_fused<double, double>(cpt, s, nit, dI, ditems, st, refresh);
+        else if (kdtype == GP_F32) launch_bv_fused<float, float>(cpt, s, nit, dI, ditems, st, refresh);
+        else launch_bv_fused<bf16_t, float>(cpt, s, nit, dI, ditems, st, refresh);
+    };
+    auto update = [&](int refresh) {
+        if (f64v) hipLaunchKernelGGL(k_bv_update<double>, dim3((unsigned)B), dim3(BV_T), 0, s, dI, st, refresh);
+        else hipLaunchKernelGGL(k_bv_update<float>, dim3((unsigned)B), dim3(BV_T), 0, s, dI, st, refresh);
+    };
+    auto proj = [&](int init) {
+        GPL1_BV_NV_SWITCH(nv, hipLaunchKernelGGL(k_bv_proj<NVc>, dim3((unsigned)B), dim3(BV_T), 0, s, dI, st, init));
+    };
+    GPL1_BV_NV_SWITCH(nv, hipLaunchKernelGGL(k_bv_init<NVc>, dim3((unsigned)B), dim3(BV_T), 0, s, dI, st, prm,
+                                             f64v ? 1 : 0));
+    fused(1);
+    update(1);
+    proj(1);
+    e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(h, e, "batched-var init launch");
+    std::vector<GPState> hst((size_t)B);
+    int it = 0;
+    while (it < o.max_iter) {
+        const int end = std::min(o.max_iter, it + o.chunk);
+        for (; it < end; ++it) {
+            fused(0);
+            update(0);
+            if (o.refresh_every > 0 && (it + 1) % o.refresh_every == 0 && it + 1 < o.max_iter) {
+                fused(1);
+                update(1);
+            }
+            proj(0);
+        }
+        e = hipGetLastError();
+        if (e != hipSuccess) return hip_fail(h, e, "batched-var iteration launch");
+        if (it < o.max_iter) {
+            e = hipMemcpyAsync(hst.data(), st, sizeof(GPState) * B, hipMemcpyDeviceToHost, s);
+            if (e == hipSuccess) e = hipStreamSynchronize(s);
+            if (e != hipSuccess) return hip_fail(h, e, "batched-var status poll");
+            bool all = true;
+            for (int64_t b = 0; b < B && all; ++b) all = hst[(size_t)b].done != 0;
+            if (all) break;
+        }
+    }
+    hipLaunchKernelGGL(k_bv_finish, dim3((unsigned)B), dim3(BV_T), 0, s, dI, st, f64v ? 1 : 0);
+    e = hipMemcpyAsync(hst.data(), st, sizeof(GPState) * B, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(h, e, "batched-var final sync");
+    int worst = GP_OK_TOL;
+    for (int64_t b = 0; b < B; ++b) {
+        fill_result(hst[(size_t)b], &res[b]);
+        if (severity(res[b].status) > severity(worst)) worst = res[b].status;
+    }
+    return worst;
+}
+
+}  // namespace gpl1

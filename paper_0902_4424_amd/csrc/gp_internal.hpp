@@ -45,6 +45,10 @@ int solve_batched_shared_mfma(gp_handle h, gp_dtype kdtype, const void* K, int64
                               const void* Y, int64_t ldy, int64_t B, const double* rho, const void* X0,
                               int64_t ldx, double tol, void* X_out, const gp_opts& o, gp_result* res,
                               hipStream_t s);
+// Independent problems in lockstep; GP_E_UNSUPPORTED means nothing was
+// launched and the caller should solve them one at a time.
+int solve_batched_var_lockstep(gp_handle h, gp_dtype kdtype, const gp_instance* inst, int64_t B, double tol,
+                               const gp_opts& o, gp_result* res, hipStream_t s);
 // Profiling helpers: record an event pair around a launch; sum at the end.
 hipEvent_t prof_event(gp_handle h);
 double prof_collect(gp_handle h, int live, int* pairs);

@@ -477,14 +477,16 @@ struct FusedBlock {
 // The vector multiplied is u = v - vsub (vsub may be NULL): in an iteration
 // v = h and vsub = x give the direction d; on a refresh v = x.  With g given,
 // workgroup b also returns g'd, d'd and ||d||_inf over its column slice.
+// Body of the fused pass for workgroup `wg` of `ngroups` (the slab index and
+// slab count of one problem); `wrow` and `sp` are this workgroup's partial
+// vector and partial dots.
 template <typename TK, typename ACC, int T, int CPT, int RB, int NB, bool ALIGNED>
-__global__ __launch_bounds__(T) void k_fused(const GPState* __restrict__ st, const TK* __restrict__ K,
-                                                int64_t n, int64_t p, int64_t ldk, int64_t rows_per_wg,
-                                                const double* __restrict__ v, const double* __restrict__ vsub,
-                                                const double* __restrict__ g, const double* __restrict__ ysub,
-                                                const double* __restrict__ rvec, double* __restrict__ tout,
-                                                ACC* __restrict__ wpart, int64_t ldw,
-                                                double* __restrict__ spart, int interleave) {
+__device__ __forceinline__ void fused_body(const TK* __restrict__ K, int64_t n, int64_t p, int64_t ldk,
+                                           int64_t rows_per_wg, const double* __restrict__ v,
+                                           const double* __restrict__ vsub, const double* __restrict__ g,
+                                           const double* __restrict__ ysub, const double* __restrict__ rvec,
+                                           double* __restrict__ tout, ACC* __restrict__ wrow, int64_t ldw,
+                                           double* __restrict__ sp, int interleave, int64_t wg, int64_t ngroups) {
     using FB = FusedBlock<TK, ACC, T, CPT, RB>;
     constexpr int VEC = FB::VEC;
     constexpr int NW = FB::NW;
@@ -493,15 +495,14 @@ __global__ __launch_bounds__(T) void k_fused(const GPState* __restrict__ st, con
     __shared__ double red[2][RB][NW];
     __shared__ double lds3[3 * NW];
     __shared__ double s_y[FCH], s_r[FCH], s_t[FCH];
-    if (!st->live) return;
     const int tid = threadIdx.x;
 
     // Row blocks of this workgroup: a contiguous slab [r0, r1), or, with
     // `interleave`, blocks b, b + G, b + 2G, ... so that at any moment the
     // whole grid streams one compact window of K.
-    const int64_t r0 = (int64_t)blockIdx.x * rows_per_wg;
-    const int64_t first = interleave ? (int64_t)blockIdx.x * RB : r0;
-    const int64_t step = interleave ? (int64_t)gridDim.x * RB : RB;
+    const int64_t r0 = wg * rows_per_wg;
+    const int64_t first = interleave ? wg * RB : r0;
+    const int64_t step = interleave ? ngroups * RB : RB;
     const int64_t lim = interleave ? n : (r0 + rows_per_wg < n ? r0 + rows_per_wg : n);
     // NB register buffers of RB rows each: NB - 1 row blocks are in flight
     // while one is reduced
@@ -589,8 +590,8 @@ __global__ __launch_bounds__(T) void k_fused(const GPState* __restrict__ st, con
     // direction dots over this workgroup's column slice
     double dsum[2] = {0.0, 0.0}, dmx[1] = {0.0};
     if (g) {
-        const int64_t cs = (p + gridDim.x - 1) / gridDim.x;
-        const int64_t c0 = (int64_t)blockIdx.x * cs;
+        const int64_t cs = (p + ngroups - 1) / ngroups;
+        const int64_t c0 = wg * cs;
         const int64_t c1 = c0 + cs < p ? c0 + cs : p;
         for (int64_t j = c0 + tid; j < c1; j += T) {
             const double dj = v[j] - vsub[j];
@@ -600,7 +601,6 @@ __global__ __launch_bounds__(T) void k_fused(const GPState* __restrict__ st, con
         }
         block_reduce<T, 2, 1>(dsum, dmx, lds3);
     }
-    ACC* wrow = wpart + (int64_t)blockIdx.x * ldw;
 #pragma unroll
     for (int c = 0; c < CPT; ++c) {
         const int64_t col = ((int64_t)c * T + tid) * VEC;
@@ -610,13 +610,27 @@ __global__ __launch_bounds__(T) void k_fused(const GPState* __restrict__ st, con
         }
     }
     if (tid == 0) {
-        double* sp = spart + (int64_t)SPART * blockIdx.x;
         sp[0] = tt;
         sp[1] = tr;
         sp[2] = dsum[0];
         sp[3] = dsum[1];
         sp[4] = dmx[0];
     }
+}
+
+template <typename TK, typename ACC, int T, int CPT, int RB, int NB, bool ALIGNED>
+__global__ __launch_bounds__(T) void k_fused(const GPState* __restrict__ st, const TK* __restrict__ K,
+                                                int64_t n, int64_t p, int64_t ldk, int64_t rows_per_wg,
+                                                const double* __restrict__ v, const double* __restrict__ vsub,
+                                                const double* __restrict__ g, const double* __restrict__ ysub,
+                                                const double* __restrict__ rvec, double* __restrict__ tout,
+                                                ACC* __restrict__ wpart, int64_t ldw,
+                                                double* __restrict__ spart, int interleave) {
+    if (!st->live) return;
+    fused_body<TK, ACC, T, CPT, RB, NB, ALIGNED>(K, n, p, ldk, rows_per_wg, v, vsub, g, ysub, rvec, tout,
+                                                 wpart + (int64_t)blockIdx.x * ldw, ldw,
+                                                 spart + (int64_t)SPART * blockIdx.x, interleave,
+                                                 (int64_t)blockIdx.x, (int64_t)gridDim.x);
 }
 
 // ---------------------------------------------------------------------------

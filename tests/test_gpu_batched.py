@@ -121,3 +121,75 @@ def test_shared_large_sampled(H):
                                     refresh_every=50)
     assert all(r["status"] >= 0 for r in res)
     _check_columns(batch, X, res, [0, 31, 63], tight_iters=20000)
+
+
+# ---------------------------------------------------------------------------
+# independent problems of different sizes (lockstep batch)
+# ---------------------------------------------------------------------------
+def _var_problems(insts, dtype):
+    probs = []
+    for inst in insts:
+        if dtype == "bf16":
+            K = torch.from_numpy(inst.K_store.view(np.int16)).to(DEV)
+        else:
+            K = torch.from_numpy(inst.K_store).to(DEV)
+        probs.append((K, torch.from_numpy(inst.y_store).to(DEV), inst.rho))
+    return probs
+
+
+def _check_var(insts, X, res, idx, gap_tol, err_tol):
+    worst = [0.0, 0.0]
+    for i in idx:
+        inst = insts[i]
+        ref = gpss(inst.K64, inst.y64, inst.rho, tol=0.0, max_iter=100000)
+        x = X[i].cpu().double().numpy()
+        fx = float(np.sum((inst.K64 @ x - inst.y64) ** 2))
+        gap = (fx - ref["f"]) / ref["f"]
+        err = np.linalg.norm(x - ref["x"]) / np.linalg.norm(ref["x"])
+        worst = [max(worst[0], gap), max(worst[1], err)]
+        assert res[i]["status"] >= 0
+        assert np.abs(x).sum() <= inst.rho * (1 + 1e-6)
+    say(f"   worst gap {worst[0]:.2e}, worst x err {worst[1]:.2e}")
+    assert worst[0] <= gap_tol and worst[1] <= err_tol
+
+
+@pytest.mark.parametrize("dtype", ["bf16", "f32", "f64"])
+def test_var_small_matches_oracle(H, dtype):
+    say(f"[batched-var] 7 uneven problems {dtype}")
+    rng = np.random.default_rng(77)
+    insts = [instances.gaussian_instance(int(n), 4 * int(n), max(1, int(n) // 20), sigma=1e-2,
+                                         dtype=dtype, seed=900 + i)
+             for i, n in enumerate(rng.integers(16, 300, size=7))]
+    X, res = H.solve_batched_var(_var_problems(insts, dtype), tol=1e-13, max_iter=5000,
+                                 refresh_every=0 if dtype == "f64" else 50)
+    tol = (1e-10, 1e-6) if dtype == "f64" else (1e-6, 1e-4)
+    _check_var(insts, X, res, range(7), *tol)
+
+
+def test_var_uneven_sampled(H):
+    say("[batched-var] 64 problems, n in [128, 1024], p = 4n, bf16; 4 sampled")
+    insts = instances.uneven_batch(64, dtype="bf16", seed=4)
+    X, res = H.solve_batched_var(_var_problems(insts, "bf16"), tol=1e-12, max_iter=5000,
+                                 refresh_every=50)
+    assert all(r["status"] >= 0 for r in res)
+    big = int(np.argmax([i.n for i in insts]))
+    _check_var(insts, X, res, [0, 17, 40, big], 1e-6, 1e-4)
+
+
+def test_var_special_and_padded(H):
+    say("[batched-var] rho = 0, y = 0, padded leading dimension, warm start")
+    insts = [instances.gaussian_instance(40, 160, 3, dtype="f32", seed=1000 + i) for i in range(4)]
+    probs = _var_problems(insts, "f32")
+    Kp = torch.zeros(40, 163, dtype=torch.float32, device=DEV)
+    Kp[:, :160] = probs[2][0]
+    probs[2] = (Kp[:, :160], probs[2][1], probs[2][2])
+    probs[0] = (probs[0][0], probs[0][1], 0.0)
+    probs[1] = (probs[1][0], torch.zeros_like(probs[1][1]), probs[1][2])
+    X, res = H.solve_batched_var(probs, tol=1e-13, max_iter=5000, refresh_every=50)
+    assert res[0]["status_name"] == "stationary" and not X[0].any().item()
+    assert res[1]["status_name"] == "stationary" and res[1]["iters"] == 0
+    _check_var(insts, X, res, [2, 3], 1e-6, 1e-4)
+    # warm start from the answer
+    probs3 = [(probs[3][0], probs[3][1], probs[3][2], X[3].clone())]
+    X2, res2 = H.solve_batched_var(probs3, tol=1e-13, max_iter=5000, refresh_every=50)
+    assert res2[0]["iters"] <= max(5, res[3]["iters"] // 2)
