@@ -80,6 +80,8 @@ typedef struct {
     int32_t fused_grid;   /* tuning: workgroups (row slabs) of that kernel (0 = automatic) */
     int32_t profile;      /* 1: time every fused K/K^T launch with HIP events (result.t_fused_ms) */
     int32_t fused_interleave; /* tuning: 1 = row blocks dealt round-robin to workgroups, 0 = slabs */
+    const double* f_targets;  /* batched calls: host array of one f_target per problem (NULL = f_target
+                                 for all); must stay valid for the call; ignored by gp_l1_solve */
 } gp_opts;
 
 typedef struct {
@@ -99,8 +101,8 @@ typedef struct {
 typedef struct gp_handle_s* gp_handle;
 
 /* Fill `o` with the paper's GPSS parameters, max_iter = 100000,
- * f_target = -1 (off), refresh_every = 0, backtrack_cap = 60, chunk = 64,
- * automatic kernel shapes. */
+ * f_target = -1 (off), f_targets = NULL, refresh_every = 0,
+ * backtrack_cap = 60, chunk = 64, automatic kernel shapes. */
 void gp_opts_default(gp_opts* o);
 
 /* Create a handle bound to HIP device `device`; it owns the solver's scratch
@@ -135,7 +137,10 @@ int gp_l1_solve(gp_handle h, gp_dtype kdtype, const void* K, int64_t n,
  * Y: device B x n (ldy >= n), rho: host array of B radii, X0: device B x p
  * (ldx >= p) or NULL, X_out: device B x p (ldx).  Each problem runs its own
  * steplength, threshold and line search; finished problems are frozen.
- * res: host array of B results.  Returns the most severe status. */
+ * res: host array of B results.  Returns the most severe status.
+ * K in GP_BF16 or GP_F32 runs on the bf16 matrix cores (an FP32 K as three
+ * bf16 planes, products to FP32 accuracy) when p <= 16384; other cases run
+ * the single-problem solver once per right-hand side. */
 int gp_l1_solve_batched_shared(gp_handle h, gp_dtype kdtype, const void* K,
                                int64_t n, int64_t p, int64_t ldk,
                                const void* Y, int64_t ldy, int64_t B,
@@ -159,6 +164,58 @@ typedef struct {
 int gp_l1_solve_batched_var(gp_handle h, gp_dtype kdtype,
                             const gp_instance* inst, int64_t B, double tol,
                             const gp_opts* opts, gp_result* res, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Learned warm start: an unrolled soft-thresholding network.
+ *
+ * ISTA (Section 2, item 1) iterates x <- S_lam[x + K^T (y - K x)], i.e. an
+ * affine map followed by soft thresholding.  The network keeps that shape
+ * with learned matrices and per-layer thresholds:
+ *     c = We y,  x_1 = S_{theta_1}(c),  x_t = S_{theta_t}(c + S x_{t-1}),
+ * t = 2..layers; We is p x n, S is p x p, theta has `layers` entries.  The
+ * warm start of a solve is x0 = P_Omega(x_layers) (projection of Algorithm 1),
+ * which lies in the ball as Algorithm 1 requires.
+ *
+ * Weights are kept on the device as FP32 master copies (with Adam moments)
+ * and used as bf16 on the matrix cores; activations enter the products as
+ * three bf16 planes, so weight x activation products carry FP32 accuracy.
+ * Samples are stored one per row: Y is B x n, X is B x p (row-major, FP32).
+ * ------------------------------------------------------------------------ */
+typedef struct gp_lista_s* gp_lista;
+
+/* Create a network for n x p problems with `layers` (1..32) layers on the
+ * handle's device; weights start at zero.  The network owns its memory. */
+int gp_lista_create(gp_handle h, gp_lista* out, int64_t n, int64_t p, int32_t layers);
+int gp_lista_destroy(gp_lista net);
+
+/* ISTA initialisation from K (device, FP32, n x p row-major, ldk):
+ * We = K^T / L, S = I - K^T K / L, theta_t = lam / L for every layer, where
+ * L >= ||K||_2^2 is given by the caller.  Resets the Adam state. */
+int gp_lista_init_from_K(gp_lista net, const float* K, int64_t ldk, double L, double lam, void* stream);
+
+/* Copy weights in or out (device FP32): We p x n, S p x p, theta[layers]. */
+int gp_lista_set_weights(gp_lista net, const float* We, const float* S, const float* theta, void* stream);
+int gp_lista_get_weights(gp_lista net, float* We, float* S, float* theta, void* stream);
+
+/* Forward pass on B samples: Y (device, B x n, ldy) -> X_out (device,
+ * B x p, ldx).  rho: host array of B radii, or NULL for the raw network
+ * output; with rho each row is projected onto its ball. */
+int gp_lista_forward(gp_lista net, const float* Y, int64_t ldy, int64_t B, const double* rho,
+                     float* X_out, int64_t ldx, void* stream);
+
+/* One training step on B samples (Y: B x n, Xstar: B x p, device): loss
+ * (1/(2B)) sum ||x_layers - x*||^2, gradients by reverse accumulation
+ * (derivative of S_theta taken as 0 at the kink), Adam with step lr
+ * (beta1 = 0.9, beta2 = 0.999, eps = 1e-8) on the FP32 masters.
+ * loss_out (host) receives the loss before the update; the call
+ * synchronises the stream. */
+int gp_lista_train_step(gp_lista net, const float* Y, int64_t ldy, const float* Xstar, int64_t ldx,
+                        int64_t B, double lr, double* loss_out, void* stream);
+
+/* Gradients of the loss at the current weights without an update (device
+ * FP32 outputs, same shapes as the weights); loss_out as above. */
+int gp_lista_gradients(gp_lista net, const float* Y, int64_t ldy, const float* Xstar, int64_t ldx, int64_t B,
+                       float* dWe, float* dS, float* dtheta, double* loss_out, void* stream);
 
 #ifdef __cplusplus
 }

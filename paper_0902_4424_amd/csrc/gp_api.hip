@@ -307,6 +307,8 @@ void gp_opts_default(gp_opts* o) {
     o->fused_cfg = 0;
     o->fused_grid = 0;
     o->profile = 0;
+    o->fused_interleave = 0;
+    o->f_targets = nullptr;
 }
 
 int gp_create(gp_handle* out, int device) {

@@ -14,6 +14,13 @@
 using namespace gpl1;
 
 namespace {
+int check_targets(gp_handle h, const gp_opts& o, int64_t B) {
+    if (!o.f_targets) return GP_OK_TOL;
+    for (int64_t b = 0; b < B; ++b)
+        if (std::isnan(o.f_targets[b])) return fail(h, GP_E_ARG, "opts.f_targets holds a NaN");
+    return GP_OK_TOL;
+}
+
 int severity(int s) {            // errors first, then unfinished, then finished
     if (s < 0) return 100 - s;
     if (s == GP_BACKTRACK_LIMIT) return 4;
@@ -40,10 +47,12 @@ extern "C" int gp_l1_solve_batched_shared(gp_handle h, gp_dtype kdtype, const vo
     if (opts) o = *opts; else gp_opts_default(&o);
     int rc0 = check_opts(h, o);
     if (rc0) return rc0;
+    rc0 = check_targets(h, o, B);
+    if (rc0) return rc0;
     for (int64_t b = 0; b < B; ++b) { std::memset(&res[b], 0, sizeof(gp_result)); res[b].status = GP_E_ARG; }
     hipError_t e = hipSetDevice(h->device);
     if (e != hipSuccess) return hip_fail(h, e, "hipSetDevice");
-    // the matrix-core path for bf16 K; other dtypes run one problem at a time
+    // the matrix-core path for bf16 and FP32 K; other cases run one problem at a time
     int rcm = solve_batched_shared_mfma(h, kdtype, K, n, p, ldk, Y, ldy, B, rho, X0, ldx, tol, X_out, o, res,
                                         (hipStream_t)stream);
     if (rcm != GP_E_UNSUPPORTED) return rcm;
@@ -53,7 +62,9 @@ extern "C" int gp_l1_solve_batched_shared(gp_handle h, gp_dtype kdtype, const vo
         const char* yb = (const char*)Y + (size_t)b * ldy * vsz;
         const char* x0b = X0 ? (const char*)X0 + (size_t)b * ldx * vsz : nullptr;
         char* xb = (char*)X_out + (size_t)b * ldx * vsz;
-        int rc = gp_l1_solve(h, kdtype, K, n, p, ldk, yb, rho[b], x0b, tol, xb, opts, &res[b], stream);
+        gp_opts ob = o;
+        if (o.f_targets) ob.f_target = o.f_targets[b];
+        int rc = gp_l1_solve(h, kdtype, K, n, p, ldk, yb, rho[b], x0b, tol, xb, &ob, &res[b], stream);
         if (rc == GP_E_ARG || rc == GP_E_HIP || rc == GP_E_NOMEM || rc == GP_E_UNSUPPORTED) return rc;
         if (severity(rc) > severity(worst)) worst = rc;
     }
@@ -81,6 +92,8 @@ extern "C" int gp_l1_solve_batched_var(gp_handle h, gp_dtype kdtype, const gp_in
     if (opts) o = *opts; else gp_opts_default(&o);
     int rc0 = check_opts(h, o);
     if (rc0) return rc0;
+    rc0 = check_targets(h, o, B);
+    if (rc0) return rc0;
     for (int64_t b = 0; b < B; ++b) { std::memset(&res[b], 0, sizeof(gp_result)); res[b].status = GP_E_ARG; }
     hipError_t e = hipSetDevice(h->device);
     if (e != hipSuccess) return hip_fail(h, e, "hipSetDevice");
@@ -89,7 +102,9 @@ extern "C" int gp_l1_solve_batched_var(gp_handle h, gp_dtype kdtype, const gp_in
     int worst = GP_OK_TOL;
     for (int64_t b = 0; b < B; ++b) {
         const gp_instance& I = inst[b];
-        int rc = gp_l1_solve(h, kdtype, I.K, I.n, I.p, I.ldk, I.y, I.rho, I.x0, tol, I.x_out, opts, &res[b],
+        gp_opts ob = o;
+        if (o.f_targets) ob.f_target = o.f_targets[b];
+        int rc = gp_l1_solve(h, kdtype, I.K, I.n, I.p, I.ldk, I.y, I.rho, I.x0, tol, I.x_out, &ob, &res[b],
                              stream);
         if (rc == GP_E_ARG || rc == GP_E_HIP || rc == GP_E_NOMEM || rc == GP_E_UNSUPPORTED) return rc;
         if (severity(rc) > severity(worst)) worst = rc;

@@ -1,12 +1,16 @@
 // Batched GPSS: B problems min ||K x_b - y_b||^2 s.t. ||x_b||_1 <= rho_b that
-// share one bf16 K.  The two matrix products of an iteration become GEMMs on
-// the bf16 matrix cores (gp_gemm.hpp):
+// share one K (bf16 or FP32).  The two matrix products of an iteration become
+// GEMMs on the bf16 matrix cores (gp_gemm.hpp):
 //     Q = K D          (n x B, D = [d_1 .. d_B], the projected directions)
 //     W = K^T Q        (p x B, W = K^T K D: the gradient change, since
 //                       g_b(x + lam d) = g_b + 2 lam K^T K d_b)
 // with D and Q split into three bf16 planes each, so the products carry FP32
 // accuracy.  K^T is a transposed bf16 copy made once per call so that both
-// GEMMs read their left operand with the reduction index contiguous.
+// GEMMs read their left operand with the reduction index contiguous.  An
+// FP32 K is kept as three bf16 planes Kh + Km + Kl as well; a product is then
+// Kh (Dh + Dm + Dl) + Km (Dh + Dm) + Kl Dh, three GEMMs whose partial sums
+// add up with the split-K partials (the dropped plane products are below
+// 2^-24 of the result).
 //
 // Everything per problem (projection and threshold search, the steplength
 // rule of Algorithm 2, the closed-form Armijo backtracking of Algorithm 1,
@@ -76,6 +80,26 @@ __global__ void k_bs_pack(const uint16_t* __restrict__ K, int64_t n, int64_t p, 
     }
 }
 
+// FP32 K: padded copies as three bf16 planes each (plane strides kps, kts).
+__global__ void k_bs_pack_f32(const float* __restrict__ K, int64_t n, int64_t p, int64_t ldk,
+                              uint16_t* __restrict__ Kp, int64_t ldkp, int64_t kps, uint16_t* __restrict__ Kt,
+                              int64_t ldkt, int64_t kts) {
+    __shared__ float tile[64][65];
+    const int64_t i0 = (int64_t)blockIdx.y * 64, j0 = (int64_t)blockIdx.x * 64;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;   // 256 threads: 64 x 4
+    for (int r = ty; r < 64; r += 4) {
+        const int64_t i = i0 + r, j = j0 + tx;
+        const float v = (i < n && j < p) ? K[i * ldk + j] : 0.f;
+        tile[r][tx] = v;
+        split3((double)v, Kp, kps, i * ldkp + j);
+    }
+    __syncthreads();
+    for (int r = ty; r < 64; r += 4) {
+        const int64_t j = j0 + r, i = i0 + tx;
+        split3((double)tile[tx][r], Kt, kts, j * ldkt + i);
+    }
+}
+
 struct BsPtrs {
     GPState* st; int32_t* done;
     double *X, *G, *H, *R, *Y, *Qv;          // B x p (X, G, H) and B x n (R, Y, Qv), ld = p / n
@@ -91,6 +115,7 @@ struct BsPtrs {
 // ---------------------------------------------------------------------------
 template <int NV>
 __global__ __launch_bounds__(BS_T) void k_bs_init(BsPtrs P, GPParams prm, const double* __restrict__ rho,
+                                                  const double* __restrict__ ftarget,
                                                   const void* __restrict__ Y, int64_t ldy,
                                                   const void* __restrict__ X0, int64_t ldx, int f64v) {
     __shared__ double lds[3 * (BS_T / WAVE)];
@@ -126,6 +151,7 @@ __global__ __launch_bounds__(BS_T) void k_bs_init(BsPtrs P, GPParams prm, const 
         GPState s = {};
         s.prm = prm;
         s.prm.rho = rb;
+        if (ftarget) s.prm.f_target = ftarget[b];
         s.tau = prm.tau1;
         s.alpha = prm.amax;
         s.status = ST_MAX_ITER;
@@ -415,7 +441,8 @@ int solve_batched_shared_mfma(gp_handle h, gp_dtype kdtype, const void* K, int64
                               const void* Y, int64_t ldy, int64_t B, const double* rho, const void* X0,
                               int64_t ldx, double tol, void* X_out, const gp_opts& o, gp_result* res,
                               hipStream_t s) {
-    if (kdtype != GP_BF16) return GP_E_UNSUPPORTED;
+    if (kdtype != GP_BF16 && kdtype != GP_F32) return GP_E_UNSUPPORTED;
+    const int nK = kdtype == GP_F32 ? 3 : 1;   // bf16 planes of K
     const int nv = bs_nv(p);
     if (nv == 0 || B > (1 << 20)) return GP_E_UNSUPPORTED;
     const int64_t npad = rup(n, BS_PAD), ppad = rup(p, BS_PAD), bpad = rup(B, BS_PAD);
@@ -427,16 +454,17 @@ int solve_batched_shared_mfma(gp_handle h, gp_dtype kdtype, const void* K, int64
     };
     const int64_t kc1 = chunk_of(ppad), kc2 = chunk_of(npad);
     const int S1 = (int)(ppad / kc1), S2 = (int)(npad / kc2);
+    const int64_t kpl = npad * ppad;           // elements of one K plane
 
     size_t off = 0;
     auto take = [&](size_t bytes) { size_t o2 = off; off += (bytes + 255) / 256 * 256; return o2; };
     const size_t o_st = take(sizeof(GPState) * B), o_done = take(sizeof(int32_t) * B);
     const size_t o_X = take(8 * B * p), o_G = take(8 * B * p), o_H = take(8 * B * p);
     const size_t o_R = take(8 * B * n), o_Y = take(8 * B * n), o_Qv = take(8 * B * n);
-    const size_t o_Kp = take(2 * npad * ppad), o_Kt = take(2 * ppad * npad);
+    const size_t o_Kp = take(2 * nK * kpl), o_Kt = take(2 * nK * kpl);
     const size_t o_Dsp = take(2 * NSPL * bpad * ppad), o_Qsp = take(2 * NSPL * bpad * npad);
-    const size_t o_Qp = take(4 * (size_t)S1 * bpad * npad), o_Wp = take(4 * (size_t)S2 * bpad * ppad);
-    const size_t o_rho = take(8 * B);
+    const size_t o_Qp = take(4 * (size_t)S1 * nK * bpad * npad), o_Wp = take(4 * (size_t)S2 * nK * bpad * ppad);
+    const size_t o_rho = take(8 * B), o_ft = take(8 * B);
     int rc = ensure_workspace(h, off);
     if (rc) return rc;
     char* ws = (char*)h->ws;
@@ -453,28 +481,47 @@ int solve_batched_shared_mfma(gp_handle h, gp_dtype kdtype, const void* K, int64
     P.Qpart = Qpart; P.Wpart = Wpart;
     P.n = n; P.p = p; P.npad = npad; P.ppad = ppad;
     P.plD = bpad * ppad; P.plQ = bpad * npad;
-    P.S1 = S1; P.S2 = S2;
+    P.S1 = S1 * nK; P.S2 = S2 * nK;          // partial planes: split-K chunks x K planes
     P.sQ = bpad * npad; P.sW = bpad * ppad;
     double* drho = (double*)(ws + o_rho);
+    double* dft = o.f_targets ? (double*)(ws + o_ft) : nullptr;
 
     hipError_t e = hipMemcpyAsync(drho, rho, 8 * B, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && dft) e = hipMemcpyAsync(dft, o.f_targets, 8 * B, hipMemcpyHostToDevice, s);
     // zero padding of the GEMM operands (rows beyond n, p and columns beyond B)
     if (e == hipSuccess) e = hipMemsetAsync(P.Dsp, 0, 2 * NSPL * bpad * ppad, s);
     if (e == hipSuccess) e = hipMemsetAsync(P.Qsp, 0, 2 * NSPL * bpad * npad, s);
     if (e != hipSuccess) return hip_fail(h, e, "batched set-up");
-    hipLaunchKernelGGL(k_bs_pack, dim3((unsigned)(ppad / 64), (unsigned)(npad / 64)), dim3(256), 0, s,
-                       (const uint16_t*)K, n, p, ldk, Kp, ppad, Kt, npad);
+    if (nK == 1)
+        hipLaunchKernelGGL(k_bs_pack, dim3((unsigned)(ppad / 64), (unsigned)(npad / 64)), dim3(256), 0, s,
+                           (const uint16_t*)K, n, p, ldk, Kp, ppad, Kt, npad);
+    else
+        hipLaunchKernelGGL(k_bs_pack_f32, dim3((unsigned)(ppad / 64), (unsigned)(npad / 64)), dim3(256), 0, s,
+                           (const float*)K, n, p, ldk, Kp, ppad, kpl, Kt, npad, kpl);
     const GPParams prm = make_params(o, 0.0, tol);
     const int f64v = 0;
     GPL1_BS_NV_SWITCH(nv, hipLaunchKernelGGL(k_bs_init<NVc>, dim3((unsigned)B), dim3(BS_T), 0, s, P, prm, drho,
-                                             Y, ldy, X0, ldx, f64v));
+                                             dft, Y, ldy, X0, ldx, f64v));
+    // one GEMM per K plane a: A = plane a, right operand = its first 3 - a
+    // planes (all three for a bf16 K), partials after those of plane a - 1
+    auto gemm_planes = [&](const uint16_t* A0, int64_t lda, int64_t M, const uint16_t* Bpl, int64_t ldb,
+                           int64_t plB, int S, int64_t kc, float* Cp, int64_t ldc, int64_t cs) {
+        for (int a = 0; a < nK; ++a) {
+            const dim3 grid((unsigned)(M / GM_BM), (unsigned)(bpad / GM_BN), (unsigned)S);
+            const uint16_t* A = A0 + a * kpl;
+            float* C = Cp + (int64_t)a * S * cs;
+            switch (nK == 1 ? NSPL : NSPL - a) {
+                case 3: hipLaunchKernelGGL(k_gemm_bf16<3>, grid, dim3(GM_T), 0, s, A, lda, Bpl, ldb, plB, (int)kc, C, ldc, cs); break;
+                case 2: hipLaunchKernelGGL(k_gemm_bf16<2>, grid, dim3(GM_T), 0, s, A, lda, Bpl, ldb, plB, (int)kc, C, ldc, cs); break;
+                default: hipLaunchKernelGGL(k_gemm_bf16<1>, grid, dim3(GM_T), 0, s, A, lda, Bpl, ldb, plB, (int)kc, C, ldc, cs); break;
+            }
+        }
+    };
     auto gemm1 = [&]() {   // Qpart = K * (Dsp planes)
-        hipLaunchKernelGGL(k_gemm_bf16<NSPL>, dim3((unsigned)(npad / GM_BM), (unsigned)(bpad / GM_BN), (unsigned)S1),
-                           dim3(GM_T), 0, s, Kp, ppad, P.Dsp, ppad, P.plD, (int)kc1, Qpart, npad, P.sQ);
+        gemm_planes(Kp, ppad, npad, P.Dsp, ppad, P.plD, S1, kc1, Qpart, npad, P.sQ);
     };
     auto gemm2 = [&]() {   // Wpart = K^T * (Qsp planes)
-        hipLaunchKernelGGL(k_gemm_bf16<NSPL>, dim3((unsigned)(ppad / GM_BM), (unsigned)(bpad / GM_BN), (unsigned)S2),
-                           dim3(GM_T), 0, s, Kt, npad, P.Qsp, npad, P.plQ, (int)kc2, Wpart, ppad, P.sW);
+        gemm_planes(Kt, npad, ppad, P.Qsp, npad, P.plQ, S2, kc2, Wpart, ppad, P.sW);
     };
     auto rows = [&](int mode, int refresh_next) {
         hipLaunchKernelGGL(k_bs_rows, dim3((unsigned)B), dim3(BS_T), 0, s, P, mode, refresh_next);

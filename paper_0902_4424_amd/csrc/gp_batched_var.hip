@@ -45,6 +45,7 @@ struct VarInst {
     float* wpart;                    // nitems x ldw partial vectors (float accumulation)
     double* wpart64;                 // same for FP64 K
     double* spart;                   // nitems x SPART partial dots
+    double ftarget;                  // this problem's f_target
     int32_t aligned;
     int32_t pad_;
 };
@@ -80,6 +81,7 @@ __global__ __launch_bounds__(BV_T) void k_bv_init(const VarInst* __restrict__ I,
         GPState s = {};
         s.prm = prm;
         s.prm.rho = D.rho;
+        s.prm.f_target = D.ftarget;
         s.tau = prm.tau1;
         s.alpha = prm.amax;
         s.status = ST_MAX_ITER;
@@ -363,6 +365,7 @@ int solve_batched_var_lockstep(gp_handle h, gp_dtype kdtype, const gp_instance* 
         VarInst& D = hI[(size_t)b];
         D.K = S.K; D.yin = S.y; D.x0in = S.x0; D.xout = S.x_out;
         D.n = S.n; D.p = S.p; D.ldk = S.ldk; D.rho = S.rho;
+        D.ftarget = o.f_targets ? o.f_targets[b] : o.f_target;
         D.nitems = (S.n + BV_ROWS - 1) / BV_ROWS;
         D.item0 = total_items;
         D.ldw = (S.p + 63) / 64 * 64;

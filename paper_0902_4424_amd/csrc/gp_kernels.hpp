@@ -650,7 +650,6 @@ __global__ __launch_bounds__(UPD_T) void k_update(GPState* __restrict__ st, int 
     constexpr int CQ = UPD_COLS / VU;           // column vectors per workgroup
     constexpr int NG = T / CQ;                  // partial groups
     __shared__ double red[NG][UPD_COLS];
-    __shared__ double sh[4];
     __shared__ GPState S;
     const int tid = threadIdx.x, lane = tid & (WAVE - 1);
     state_load(S, st);

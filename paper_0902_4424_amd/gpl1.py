@@ -21,7 +21,9 @@ STATUS = {0: "ok_tol", 1: "stationary", 2: "max_iter", 3: "reached_target",
 
 SYMBOLS = ("gp_opts_default", "gp_create", "gp_destroy", "gp_last_error",
            "gp_l1_project", "gp_l1_solve", "gp_l1_solve_batched_shared",
-           "gp_l1_solve_batched_var")
+           "gp_l1_solve_batched_var", "gp_lista_create", "gp_lista_destroy",
+           "gp_lista_init_from_K", "gp_lista_set_weights", "gp_lista_get_weights",
+           "gp_lista_forward", "gp_lista_train_step", "gp_lista_gradients")
 
 
 class GPOpts(C.Structure):
@@ -32,7 +34,7 @@ class GPOpts(C.Structure):
                 ("refresh_every", C.c_int32), ("backtrack_cap", C.c_int32),
                 ("chunk", C.c_int32), ("fused_cfg", C.c_int32),
                 ("fused_grid", C.c_int32), ("profile", C.c_int32),
-                ("fused_interleave", C.c_int32)]
+                ("fused_interleave", C.c_int32), ("f_targets", C.POINTER(C.c_double))]
 
 
 class GPResult(C.Structure):
@@ -89,6 +91,23 @@ def load():
                                             dbl, C.POINTER(GPOpts),
                                             C.POINTER(GPResult), vp]
     lib.gp_l1_solve_batched_var.restype = i32
+    fp = C.c_void_p
+    lib.gp_lista_create.argtypes = [vp, C.POINTER(vp), i64, i64, C.c_int32]
+    lib.gp_lista_create.restype = i32
+    lib.gp_lista_destroy.argtypes = [vp]
+    lib.gp_lista_destroy.restype = i32
+    lib.gp_lista_init_from_K.argtypes = [vp, fp, i64, dbl, dbl, vp]
+    lib.gp_lista_init_from_K.restype = i32
+    lib.gp_lista_set_weights.argtypes = [vp, fp, fp, fp, vp]
+    lib.gp_lista_set_weights.restype = i32
+    lib.gp_lista_get_weights.argtypes = [vp, fp, fp, fp, vp]
+    lib.gp_lista_get_weights.restype = i32
+    lib.gp_lista_forward.argtypes = [vp, fp, i64, i64, C.POINTER(dbl), fp, i64, vp]
+    lib.gp_lista_forward.restype = i32
+    lib.gp_lista_train_step.argtypes = [vp, fp, i64, fp, i64, i64, dbl, C.POINTER(dbl), vp]
+    lib.gp_lista_train_step.restype = i32
+    lib.gp_lista_gradients.argtypes = [vp, fp, i64, fp, i64, i64, fp, fp, fp, C.POINTER(dbl), vp]
+    lib.gp_lista_gradients.restype = i32
     _lib = lib
     return lib
 
@@ -99,8 +118,21 @@ def default_opts(**kw) -> GPOpts:
     for k, v in kw.items():
         if not hasattr(o, k):
             raise TypeError(f"unknown option {k!r}")
+        if k == "f_targets":
+            if v is None:
+                continue
+            arr = (C.c_double * len(v))(*[float(t) for t in v])
+            o._targets = arr                     # keeps the host array alive with the struct
+            o.f_targets = C.cast(arr, C.POINTER(C.c_double))
+            continue
         setattr(o, k, v)
     return o
+
+
+def _check_targets(o: GPOpts, B: int):
+    t = getattr(o, "_targets", None)
+    if t is not None and len(t) != B:
+        raise ValueError(f"f_targets holds {len(t)} values for {B} problems")
 
 
 class GPError(RuntimeError):
@@ -245,6 +277,7 @@ class Handle:
         if X0 is not None and X0.stride(0) != ldx:
             raise ValueError("X0 and out must share a leading dimension")
         o = opts if opts is not None else default_opts(**kw)
+        _check_targets(o, B)
         res = (GPResult * B)()
         rc = self.lib.gp_l1_solve_batched_shared(
             self.h, kdt, _ptr(K), n, p, K.stride(0), _ptr(Y), Y.stride(0), B, rho_arr,
@@ -278,11 +311,122 @@ class Handle:
                                  x0.data_ptr() if x0 is not None else None,
                                  out.data_ptr(), n, p, K.stride(0), float(rho))
         o = opts if opts is not None else default_opts(**kw)
+        _check_targets(o, B)
         res = (GPResult * B)()
         rc = self.lib.gp_l1_solve_batched_var(self.h, kdt, inst, B, float(tol), C.byref(o),
                                               res, _stream(stream))
         self._raise(rc)
         return outs, [r.as_dict() for r in res]
+
+
+class Lista:
+    """Unrolled soft-thresholding network on the device (learned warm start).
+
+    Weights: We (p x n), S (p x p), theta (layers), FP32 masters with Adam
+    state, used as bf16 on the matrix cores.  Samples are rows: Y (B x n),
+    X (B x p), float32 device tensors."""
+
+    def __init__(self, handle: "Handle", n: int, p: int, layers: int = 8):
+        self.H = handle
+        self.lib = handle.lib
+        self.n, self.p, self.layers = n, p, layers
+        net = C.c_void_p()
+        rc = self.lib.gp_lista_create(handle.h, C.byref(net), n, p, layers)
+        handle._raise(rc)
+        self.net = net
+
+    def close(self):
+        if getattr(self, "net", None):
+            self.lib.gp_lista_destroy(self.net)
+            self.net = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _f32(self, t, shape):
+        torch = _torch()
+        _check_dev(t)
+        if t.dtype != torch.float32 or tuple(t.shape) != tuple(shape) or t.stride(-1) != 1:
+            raise ValueError(f"expected a row-major float32 tensor of shape {shape}")
+        return t
+
+    def init_from_K(self, K, L: float, lam: float, stream=None):
+        """ISTA start: We = K^T/L, S = I - K^T K/L, theta = lam/L (L >= ||K||^2)."""
+        self._f32(K, (self.n, self.p))
+        self.H._raise(self.lib.gp_lista_init_from_K(self.net, _ptr(K), K.stride(0), float(L),
+                                                    float(lam), _stream(stream)))
+
+    def set_weights(self, We, S, theta, stream=None):
+        self._f32(We, (self.p, self.n))
+        self._f32(S, (self.p, self.p))
+        self._f32(theta, (self.layers,))
+        self.H._raise(self.lib.gp_lista_set_weights(self.net, _ptr(We.contiguous()), _ptr(S.contiguous()),
+                                                    _ptr(theta.contiguous()), _stream(stream)))
+
+    def get_weights(self, stream=None):
+        torch = _torch()
+        dev = torch.device("cuda", self.H.device)
+        We = torch.empty(self.p, self.n, dtype=torch.float32, device=dev)
+        S = torch.empty(self.p, self.p, dtype=torch.float32, device=dev)
+        th = torch.empty(self.layers, dtype=torch.float32, device=dev)
+        self.H._raise(self.lib.gp_lista_get_weights(self.net, _ptr(We), _ptr(S), _ptr(th), _stream(stream)))
+        return We, S, th
+
+    def forward(self, Y, rho=None, out=None, stream=None):
+        """Network output for each row of Y; with rho (sequence of B radii)
+        each row is projected onto its l1 ball."""
+        torch = _torch()
+        B = Y.shape[0]
+        self._f32(Y, (B, self.n))
+        out = torch.empty(B, self.p, dtype=torch.float32, device=Y.device) if out is None else out
+        r = (C.c_double * B)(*[float(v) for v in rho]) if rho is not None else None
+        self.H._raise(self.lib.gp_lista_forward(self.net, _ptr(Y), Y.stride(0), B, r, _ptr(out),
+                                                out.stride(0), _stream(stream)))
+        return out
+
+    def train_step(self, Y, Xstar, lr: float, stream=None) -> float:
+        B = Y.shape[0]
+        self._f32(Y, (B, self.n))
+        self._f32(Xstar, (B, self.p))
+        loss = C.c_double(0.0)
+        self.H._raise(self.lib.gp_lista_train_step(self.net, _ptr(Y), Y.stride(0), _ptr(Xstar),
+                                                   Xstar.stride(0), B, float(lr), C.byref(loss),
+                                                   _stream(stream)))
+        return loss.value
+
+    def gradients(self, Y, Xstar, stream=None):
+        torch = _torch()
+        B = Y.shape[0]
+        self._f32(Y, (B, self.n))
+        self._f32(Xstar, (B, self.p))
+        dev = Y.device
+        dWe = torch.empty(self.p, self.n, dtype=torch.float32, device=dev)
+        dS = torch.empty(self.p, self.p, dtype=torch.float32, device=dev)
+        dth = torch.empty(self.layers, dtype=torch.float32, device=dev)
+        loss = C.c_double(0.0)
+        self.H._raise(self.lib.gp_lista_gradients(self.net, _ptr(Y), Y.stride(0), _ptr(Xstar),
+                                                  Xstar.stride(0), B, _ptr(dWe), _ptr(dS), _ptr(dth),
+                                                  C.byref(loss), _stream(stream)))
+        return loss.value, dWe, dS, dth
+
+
+def warm_start(net: Lista, K, Y, rho, margin: float = 1e-9, **solve_kw):
+    """x0 = P_Omega(net(y)) for each row of Y, replaced by 0 wherever it does
+    not beat the zero start by more than rounding: kept only if
+    f(x0) < (1 - margin) f(0), f(0) = ||y||^2.  Both objective values come
+    from the library (a zero-iteration solve reports f at its start)."""
+    torch = _torch()
+    B = Y.shape[0]
+    X0 = net.forward(Y, rho=rho)
+    _, res = net.H.solve_batched_shared(K, Y, rho, X0=X0, tol=0.0, max_iter=0, **solve_kw)
+    _, res0 = net.H.solve_batched_shared(K, Y, rho, tol=0.0, max_iter=0, **solve_kw)
+    keep = torch.tensor([r["f"] < (1.0 - margin) * r0["f"] for r, r0 in zip(res, res0)],
+                        device=Y.device)
+    X0 = torch.where(keep[:, None], X0, torch.zeros_like(X0))
+    return X0, keep
 
 
 _DT_NAME = {GP_F64: "f64", GP_F32: "f32", GP_BF16: "bf16"}

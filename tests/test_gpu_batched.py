@@ -123,6 +123,47 @@ def test_shared_large_sampled(H):
     _check_columns(batch, X, res, [0, 31, 63], tight_iters=20000)
 
 
+@pytest.mark.parametrize("n,p,B", [(256, 1024, 4), (190, 650, 130)])
+def test_shared_f32_matches_oracle(H, n, p, B):
+    say(f"[batched-shared] FP32 K as three bf16 planes n={n} p={p} B={B}")
+    batch = instances.shared_batch(n, p, B, max(1, n // 20), dtype="f32", seed=61 + n,
+                                   rhs_seed_base=610 + p)
+    Kt = torch.from_numpy(batch.K_store).to(DEV)
+    Y = torch.from_numpy(batch.Y_store).to(DEV)
+    X, res = H.solve_batched_shared(Kt, Y, batch.rho, tol=1e-12, max_iter=4000, refresh_every=50)
+    cols = list(range(B)) if B <= 8 else [0, 1, B // 2, B - 1]
+    _check_columns(batch, X, res, cols)
+
+
+def test_shared_per_problem_targets(H):
+    say("[batched-shared] one f_target per problem")
+    batch = instances.shared_batch(200, 800, 6, 10, dtype="f32", seed=71, rhs_seed_base=710)
+    Kt = torch.from_numpy(batch.K_store).to(DEV)
+    Y = torch.from_numpy(batch.Y_store).to(DEV)
+    K64 = batch.K64
+    fref = [gpss(K64, batch.Y_store[b].astype(np.float64), float(batch.rho[b]), tol=0.0,
+                 max_iter=20000)["f"] for b in range(6)]
+    gaps = [1e-2, 1e-4, 1e-6, 1e-3, 1e-5, 1e-6]
+    targets = [f * (1 + g) for f, g in zip(fref, gaps)]
+    X, res = H.solve_batched_shared(Kt, Y, batch.rho, tol=0.0, max_iter=20000, refresh_every=50,
+                                    f_targets=targets)
+    for b in range(6):
+        assert res[b]["status_name"] == "reached_target", res[b]
+        fx = float(np.sum((K64 @ X[b].cpu().double().numpy() - batch.Y_store[b]) ** 2))
+        # the device tracks f in FP64 from FP32-accurate products; x comes back
+        # rounded to FP32, which moves f by a few 1e-7 of itself
+        assert fx <= targets[b] * (1 + 1e-6)
+    its = [r["iters"] for r in res]
+    say(f"   iterations per target gap: {list(zip(gaps, its))}")
+    assert its[0] < its[2] and its[3] < its[1]
+    # the same targets through the uneven-batch entry point
+    probs = [(Kt, Y[b], float(batch.rho[b])) for b in range(6)]
+    Xv, rv = H.solve_batched_var(probs, tol=0.0, max_iter=20000, refresh_every=50, f_targets=targets)
+    assert all(r["status_name"] == "reached_target" for r in rv)
+    with pytest.raises(ValueError):
+        H.solve_batched_shared(Kt, Y, batch.rho, f_targets=targets[:5])
+
+
 # ---------------------------------------------------------------------------
 # independent problems of different sizes (lockstep batch)
 # ---------------------------------------------------------------------------

@@ -1,0 +1,258 @@
+"""GPU parity of the unrolled soft-thresholding network (learned warm start).
+
+The network's products run on the bf16 matrix cores.  Weights are set to
+bf16-representable FP32 values so that the device's bf16 working copies equal
+the masters exactly; the oracle then runs the same network in FP64.
+
+Tolerances, derived from the arithmetic:
+  * forward: activations enter the products as three bf16 planes (about 24
+    bits), products are exact and accumulate in FP32, so outputs agree to a
+    few FP32 rounding steps of the layer sums: 1e-5 of max|x|.
+  * gradients of the weights: the reduction over samples takes one
+    activation as a single bf16 plane (relative rounding 2^-9 = 1.95e-3 per
+    term), so the gradient matrices agree to 1e-2 in Frobenius norm; the
+    threshold gradients and the loss are FP64 sums of FP32 terms: 1e-4.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import lista as olista
+from oracle.projection import project_l1
+from paper_0902_4424_amd import gpl1, instances
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def H():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    h = gpl1.Handle(0)
+    yield h
+    h.close()
+
+
+def _bf(a):
+    """Round to the nearest bf16-representable FP32 value (as FP64)."""
+    a32 = np.ascontiguousarray(np.asarray(a, dtype=np.float32))
+    return instances.bf16_bits_to_f32(instances.f32_to_bf16_bits(a32)).astype(np.float64)
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(np.asarray(a, dtype=np.float32))).to(DEV)
+
+
+def _problem(n, p, B, s, seed, sigma=1e-2):
+    rng = np.random.default_rng(seed)
+    K = rng.standard_normal((n, p)) / np.sqrt(n)
+    X = np.zeros((B, p))
+    for b in range(B):
+        sup = rng.choice(p, size=s, replace=False)
+        X[b, sup] = rng.choice([-1.0, 1.0], size=s)
+    Y = X @ K.T + sigma * rng.standard_normal((B, n))
+    return K, Y.astype(np.float32).astype(np.float64), X
+
+
+def _weights(K, lam, seed, pert=0.3):
+    """ISTA weights with a random perturbation, rounded to bf16 values."""
+    We, S, th = olista.ista_init(K, lam)
+    rng = np.random.default_rng(seed)
+    We = We * (1 + pert * rng.standard_normal(We.shape))
+    S = S + pert * np.abs(S).mean() * rng.standard_normal(S.shape)
+    return _bf(We), _bf(S), th
+
+
+def _net(H, n, p, L, We, S, th):
+    net = gpl1.Lista(H, n, p, L)
+    thv = np.asarray(th, dtype=np.float64)
+    net.set_weights(_dev(We), _dev(S), _dev(np.broadcast_to(thv, (L,)) if thv.ndim == 0 else thv))
+    return net
+
+
+@pytest.mark.parametrize("n,p,L,B", [(70, 150, 4, 37), (200, 1100, 3, 130), (128, 256, 1, 128)])
+def test_forward_matches_oracle(H, n, p, L, B):
+    say(f"[lista] forward n={n} p={p} layers={L} B={B}")
+    K, Y, _ = _problem(n, p, B, max(1, p // 30), seed=n + p)
+    lam = 0.1 * np.abs(K.T @ Y[0]).max()
+    We, S, th = _weights(K, lam, seed=3)
+    ths = _bf(np.full(L, th) * (1 + 0.2 * np.arange(L) / max(L, 1)))
+    net = _net(H, n, p, L, We, S, ths)
+    X = net.forward(_dev(Y)).cpu().double().numpy()
+    ref, _, _ = olista.forward(We, S, ths, Y.T)
+    ref = ref.T
+    scale = np.abs(ref).max()
+    err = np.abs(X - ref).max() / scale
+    frac_on = float((ref != 0).mean())
+    say(f"   max err {err:.2e} of max|x| {scale:.3e}; {frac_on:.2%} nonzero")
+    assert 0.0 < frac_on < 1.0
+    assert err <= 1e-5
+    # the weights read back are the masters that were set
+    We2, S2, th2 = net.get_weights()
+    np.testing.assert_array_equal(We2.cpu().double().numpy(), We)
+    np.testing.assert_array_equal(S2.cpu().double().numpy(), S)
+    np.testing.assert_array_equal(th2.cpu().double().numpy(), ths)
+    net.close()
+
+
+def test_ista_initialisation(H):
+    say("[lista] initialisation from K equals the ISTA weights")
+    n, p, L = 96, 300, 5
+    K, Y, _ = _problem(n, p, 20, 6, seed=11)
+    K32 = K.astype(np.float32).astype(np.float64)
+    Lc = float(np.linalg.norm(K32, 2) ** 2) * 1.01
+    lam = 0.05 * np.abs(K32.T @ Y[0]).max()
+    net = gpl1.Lista(H, n, p, L)
+    net.init_from_K(_dev(K32), Lc, lam)
+    We, S, th = [t.cpu().double().numpy() for t in net.get_weights()]
+    np.testing.assert_allclose(We, K32.T / Lc, rtol=1e-6, atol=0)
+    # S = I - K^T K / L: the Gram matrix is an FP32-accurate product
+    S_ref = np.eye(p) - K32.T @ K32 / Lc
+    assert np.abs(S - S_ref).max() <= 1e-6
+    np.testing.assert_allclose(th, np.full(L, lam / Lc), rtol=1e-7)
+    # with those weights the network runs L steps of ISTA from x = 0 (bf16 weights)
+    Wb, Sb = _bf(We), _bf(S)
+    X = net.forward(_dev(Y)).cpu().double().numpy()
+    x = np.zeros((p, Y.shape[0]))
+    c = Wb @ Y.T
+    for t in range(L):
+        x = np.sign(c + (Sb @ x if t else 0)) * np.maximum(np.abs(c + (Sb @ x if t else 0)) - th[t], 0)
+    err = np.abs(X - x.T).max() / max(np.abs(x).max(), 1e-30)
+    say(f"   ISTA-step equivalence err {err:.2e}")
+    assert err <= 1e-5
+    net.close()
+
+
+@pytest.mark.parametrize("n,p,L,B", [(70, 150, 4, 37), (200, 1100, 3, 130), (64, 128, 1, 5)])
+def test_gradients_match_oracle(H, n, p, L, B):
+    say(f"[lista] gradients n={n} p={p} layers={L} B={B}")
+    K, Y, Xs = _problem(n, p, B, max(1, p // 30), seed=2 * n + p)
+    lam = 0.1 * np.abs(K.T @ Y[0]).max()
+    We, S, th = _weights(K, lam, seed=5)
+    ths = _bf(np.full(L, th))
+    net = _net(H, n, p, L, We, S, ths)
+    Xs32 = Xs.astype(np.float32).astype(np.float64)
+    loss, dWe, dS, dth = net.gradients(_dev(Y), _dev(Xs32))
+    Lr, dWe_r, dS_r, dth_r = olista.backward(We, S, ths, Y.T, Xs32.T)
+    dWe, dS, dth = [t.cpu().double().numpy() for t in (dWe, dS, dth)]
+    eW = np.linalg.norm(dWe - dWe_r) / np.linalg.norm(dWe_r)
+    eS = np.linalg.norm(dS - dS_r) / max(np.linalg.norm(dS_r), 1e-300) if L > 1 else np.abs(dS).max()
+    et = np.abs(dth - dth_r).max() / np.abs(dth_r).max()
+    say(f"   loss {loss:.6e} vs {Lr:.6e}; rel err dWe {eW:.2e} dS {eS:.2e} dtheta {et:.2e}")
+    assert abs(loss - Lr) <= 1e-4 * Lr
+    assert eW <= 1e-2 and et <= 1e-4
+    if L > 1:
+        assert eS <= 1e-2
+    else:
+        assert eS == 0.0
+    net.close()
+
+
+def test_adam_step(H):
+    say("[lista] one training step is Adam's first step on the gradients")
+    n, p, L, B = 64, 192, 3, 50
+    K, Y, Xs = _problem(n, p, B, 6, seed=21)
+    lam = 0.1 * np.abs(K.T @ Y[0]).max()
+    We, S, th = _weights(K, lam, seed=7)
+    ths = _bf(np.full(L, th))
+    net = _net(H, n, p, L, We, S, ths)
+    Yd, Xd = _dev(Y), _dev(Xs)
+    loss0, gW, gS, gt = net.gradients(Yd, Xd)
+    lr = 1e-3
+    loss1 = net.train_step(Yd, Xd, lr)
+    assert loss1 == loss0                          # same weights, deterministic
+    W1, S1, t1 = [t.cpu().double().numpy() for t in net.get_weights()]
+    for w0, w1, g in ((We, W1, gW), (S, S1, gS), (ths, t1, gt)):
+        g = g.cpu().double().numpy()
+        expect = w0 - lr * g / (np.abs(g) + 1e-8)
+        assert np.abs(w1 - expect).max() <= 2e-6 * lr + 1e-6 * np.abs(w0).max()
+    net.close()
+
+
+def test_training_reduces_loss(H):
+    say("[lista] 60 Adam steps on 512 samples lower the loss")
+    n, p, L, B = 128, 512, 4, 512
+    K, Y, Xs = _problem(n, p, B, 8, seed=31)
+    K32 = K.astype(np.float32).astype(np.float64)
+    net = gpl1.Lista(H, n, p, L)
+    lam = 0.05 * np.median(np.abs(K32.T @ Y.T).max(axis=0))
+    net.init_from_K(_dev(K32), float(np.linalg.norm(K32, 2) ** 2) * 1.01, lam)
+    Yd, Xd = _dev(Y), _dev(Xs)
+    losses = [net.train_step(Yd[i * 128:(i + 1) * 128], Xd[i * 128:(i + 1) * 128], 1e-3)
+              for i in range(4) for _ in range(15)]
+    say(f"   loss {losses[0]:.4e} -> {losses[-1]:.4e}")
+    assert all(np.isfinite(losses))
+    assert losses[-1] < 0.5 * losses[0]
+    net.close()
+
+
+def test_projected_output_and_warm_start(H):
+    say("[lista] projected output, fallback to zero, warm-started solves")
+    n, p, L, B = 64, 256, 3, 24
+    K, Y, Xt = _problem(n, p, B, 4, seed=41)
+    K32 = K.astype(np.float32)
+    rho = np.abs(Xt).sum(axis=1) * 0.8
+    net = gpl1.Lista(H, n, p, L)
+    net.init_from_K(_dev(K32), float(np.linalg.norm(K32.astype(np.float64), 2) ** 2) * 1.01,
+                    0.01 * np.abs(K32.T @ Y[0]).max())
+    Yd = _dev(Y)
+    raw = net.forward(Yd).cpu().double().numpy()
+    proj = net.forward(Yd, rho=rho).cpu().double().numpy()
+    for b in range(B):
+        ref = project_l1(raw[b], rho[b])
+        assert np.abs(proj[b] - ref).max() <= 1e-6 * max(1.0, np.abs(ref).max())
+        assert np.abs(proj[b]).sum() <= rho[b] * (1 + 1e-6)
+    # a network with zero weights proposes 0, which is never kept
+    zero = gpl1.Lista(H, n, p, L)
+    Kd = _dev(K32)
+    X0z, keepz = gpl1.warm_start(zero, Kd, Yd, rho)
+    assert not keepz.any().item() and not X0z.any().item()
+    X0, keep = gpl1.warm_start(net, Kd, Yd, rho)
+    keep = keep.cpu().numpy()
+    X0h = X0.cpu().double().numpy()
+    K64 = K32.astype(np.float64)
+    for b in range(B):
+        f0 = np.sum((K64 @ proj[b] - Y[b]) ** 2)
+        fy = np.sum(Y[b] ** 2)
+        if abs(f0 - fy) > 1e-6 * fy:             # away from a tie the host agrees on the choice
+            assert keep[b] == (f0 < fy)
+        np.testing.assert_array_equal(X0h[b], proj[b] if keep[b] else 0.0)
+    assert keep.mean() >= 0.5               # ISTA steps from zero mostly lower f
+    # warm-started solves reach the same solutions as cold ones
+    cold, rc = H.solve_batched_var([(Kd, Yd[b], rho[b]) for b in range(B)], tol=1e-12, max_iter=5000,
+                                   refresh_every=50)
+    warm, rw = H.solve_batched_var([(Kd, Yd[b], rho[b], X0[b]) for b in range(B)], tol=1e-12,
+                                   max_iter=5000, refresh_every=50)
+    for b in range(B):
+        fc = np.sum((K64 @ cold[b].cpu().double().numpy() - Y[b]) ** 2)
+        fw = np.sum((K64 @ warm[b].cpu().double().numpy() - Y[b]) ** 2)
+        assert abs(fw - fc) <= 1e-6 * fc
+    say(f"   mean iterations cold {np.mean([r['iters'] for r in rc]):.1f}, "
+        f"warm {np.mean([r['iters'] for r in rw]):.1f}")
+    zero.close()
+    net.close()
+
+
+def test_argument_errors(H):
+    say("[lista] argument errors")
+    with pytest.raises(gpl1.GPError):
+        gpl1.Lista(H, 10, 20, 0)
+    with pytest.raises(gpl1.GPError):
+        gpl1.Lista(H, 0, 20, 2)
+    net = gpl1.Lista(H, 10, 20, 2)
+    with pytest.raises(ValueError):
+        net.forward(torch.zeros(3, 11, device=DEV))
+    with pytest.raises(gpl1.GPError):
+        net.forward(torch.zeros(2, 10, device=DEV), rho=[1.0, -1.0])
+    with pytest.raises(gpl1.GPError):
+        net.train_step(torch.zeros(2, 10, device=DEV), torch.zeros(2, 20, device=DEV), 0.0)
+    net.close()
