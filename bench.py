@@ -197,6 +197,179 @@ def forms_legs(H, inst, np, torch, gpl1, instances, out):
     return res
 
 
+def learned_leg(H, np, torch, gpl1, instances, ntrain, neval, epochs, batch=256, lr=3e-4,
+                layers=8):
+    """Learned warm start + batched GP refinement on one fixed FP32 K 1024x4096.
+
+    Training pairs (y, x*) come from the batched shared-K solver; the unrolled
+    network is trained by the library's own kernels; on fresh y, three ways of
+    reaching a 1e-6 relative objective gap are timed: the plain solver one
+    problem at a time (timed on a sample), the batched solver from x0 = 0, and
+    the batched solver from the network's projected output."""
+    dev = torch.device("cuda:0")
+    res = {}
+    K32 = instances.warm_start_matrix()
+    n, p = K32.shape
+    K64 = K32.astype(np.float64)
+    Kd = torch.from_numpy(K32).to(dev)
+    t0 = time.time()
+    tr = instances.warm_start_rhs(K32, ntrain, seed=61)
+    ev = instances.warm_start_rhs(K32, neval, seed=62)
+    log(f"learned leg: {ntrain} training and {neval} evaluation right-hand sides drawn "
+        f"({time.time() - t0:.1f}s)")
+    CH = 2048
+    kw = dict(refresh_every=REFRESH)
+
+    # 1. training targets from the batched solver (matrix cores, FP32 K as bf16 planes)
+    Ytr = torch.from_numpy(tr.Y).to(dev)
+    Xstar = torch.empty(ntrain, p, dtype=torch.float32, device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    its = []
+    for b0 in range(0, ntrain, CH):
+        m = min(CH, ntrain - b0)
+        X, r = H.solve_batched_shared(Kd, Ytr[b0:b0 + m], tr.rho[b0:b0 + m], tol=1e-9,
+                                      max_iter=3000, out=Xstar[b0:b0 + m], **kw)
+        its += [q["iters"] for q in r]
+    torch.cuda.synchronize()
+    t_gen = time.perf_counter() - t0
+    log(f"  targets: {ntrain} solves in {t_gen:.2f}s (mean {np.mean(its):.1f} iterations)")
+
+    # 2. training
+    Lk = float(np.linalg.norm(K64, 2) ** 2) * 1.01
+    lam = 0.1 * float(np.median(np.abs(tr.Y[:256].astype(np.float64) @ K64).max(axis=1)))
+    net = gpl1.Lista(H, n, p, layers)
+    net.init_from_K(Kd, Lk, lam)
+    gen = torch.Generator(device="cpu").manual_seed(7)
+    steps = 0
+    losses = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for ep in range(epochs):
+        perm = torch.randperm(ntrain, generator=gen).to(dev)
+        el = []
+        lr_ep = lr * (0.5 ** (ep // max(1, epochs // 3)))
+        for b0 in range(0, ntrain - batch + 1, batch):
+            idx = perm[b0:b0 + batch]
+            el.append(net.train_step(Ytr[idx].contiguous(), Xstar[idx].contiguous(), lr_ep))
+            steps += 1
+        losses.append(float(np.mean(el)))
+        log(f"  epoch {ep}: mean loss {losses[-1]:.4e} (lr {lr_ep:.1e})")
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+
+    # 3. evaluation on fresh right-hand sides
+    del Ytr, Xstar
+    Yev = torch.from_numpy(ev.Y).to(dev)
+    # reference optimum of each problem: a long batched run, f recomputed in FP64 on the host
+    f_ref = np.empty(neval)
+    for b0 in range(0, neval, CH):
+        m = min(CH, neval - b0)
+        Xl, _ = H.solve_batched_shared(Kd, Yev[b0:b0 + m], ev.rho[b0:b0 + m], tol=0.0,
+                                       max_iter=3000, **kw)
+        R = Xl.cpu().double().numpy() @ K64.T - ev.Y[b0:b0 + m].astype(np.float64)
+        f_ref[b0:b0 + m] = np.einsum("ij,ij->i", R, R)
+    targets = f_ref * (1 + 1e-6)
+
+    def host_gaps(X, b0, m):
+        R = X.cpu().double().numpy() @ K64.T - ev.Y[b0:b0 + m].astype(np.float64)
+        return (np.einsum("ij,ij->i", R, R) - f_ref[b0:b0 + m]) / f_ref[b0:b0 + m]
+
+    def batched(warm):
+        its, gaps, reached, x0err, kept = [], [], 0, [], 0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        outs = []
+        for b0 in range(0, neval, CH):
+            m = min(CH, neval - b0)
+            Yc = Yev[b0:b0 + m]
+            # x0 = P_Omega(net(y)); the solver keeps 0 where x0 is no better
+            X0 = net.forward(Yc, rho=ev.rho[b0:b0 + m]) if warm else None
+            X, r = H.solve_batched_shared(Kd, Yc, ev.rho[b0:b0 + m], X0=X0, tol=0.0, x0_fallback=1,
+                                          max_iter=20000, f_targets=targets[b0:b0 + m], **kw)
+            outs.append((b0, m, X, X0, r))
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        for b0, m, X, X0, r in outs:
+            its += [q["iters"] for q in r]
+            kept += sum(q["x0_rejected"] == 0 for q in r) if X0 is not None else 0
+            reached += sum(q["status_name"] == "reached_target" for q in r)
+            gaps += list(host_gaps(X, b0, m))
+            if X0 is not None:
+                ref = X.cpu().double().numpy()
+                x0 = X0.cpu().double().numpy()
+                x0err += list(np.linalg.norm(x0 - ref, axis=1) / np.linalg.norm(ref, axis=1))
+        return t, its, gaps, reached, x0err, kept
+
+    batched(False)                       # warm-up of the code paths
+    batched(True)
+    tc, itc, gc, rc_, _, _ = batched(False)
+    tw, itw, gw, rw, x0err, kept = batched(True)
+    # the network's share of the learned time: projected forward passes alone
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for b0 in range(0, neval, CH):
+        m = min(CH, neval - b0)
+        net.forward(Yev[b0:b0 + m], rho=ev.rho[b0:b0 + m])
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    # generalisation: the raw network output against the solutions, first chunk
+    m0 = min(CH, neval)
+    Xs0, _ = H.solve_batched_shared(Kd, Yev[:m0], ev.rho[:m0], tol=0.0, f_targets=targets[:m0],
+                                    max_iter=20000, **kw)
+    Xr = net.forward(Yev[:m0]).cpu().double().numpy()
+    Xs0 = Xs0.cpu().double().numpy()
+    raw_err = float(np.mean(np.linalg.norm(Xr - Xs0, axis=1) / np.linalg.norm(Xs0, axis=1)))
+    Ytr0 = torch.from_numpy(tr.Y[:m0]).to(dev)
+    Xt0, _ = H.solve_batched_shared(Kd, Ytr0, tr.rho[:m0], tol=1e-9, max_iter=3000, **kw)
+    Xt0 = Xt0.cpu().double().numpy()
+    Xrt = net.forward(Ytr0).cpu().double().numpy()
+    raw_err_train = float(np.mean(np.linalg.norm(Xrt - Xt0, axis=1) / np.linalg.norm(Xt0, axis=1)))
+    # plain solver, one problem at a time, on a sample
+    sample = list(range(0, neval, max(1, neval // 32)))[:32]
+    H.solve(Kd, Yev[0], float(ev.rho[0]), tol=0.0, f_target=float(targets[0]), max_iter=20000, **kw)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pits = []
+    for b in sample:
+        _, r = H.solve(Kd, Yev[b], float(ev.rho[b]), tol=0.0, f_target=float(targets[b]),
+                       max_iter=20000, **kw)
+        pits.append(r["iters"])
+    torch.cuda.synchronize()
+    tp = (time.perf_counter() - t0) / len(sample)
+    t_plain_all = tp * neval
+    res = {
+        "workload": f"fixed Gaussian K {n}x{p} fp32; {layers}-layer unrolled network (bf16 weights "
+                    f"on the matrix cores); {ntrain} training pairs from the batched solver, "
+                    f"{epochs} epochs of batch {batch}; {neval} fresh y (50-sparse +-1, sigma 1e-2, "
+                    "rho = ||x_true||_1), each run to f <= 1.000001 f_ref",
+        "f_ref_source": "3000-iteration batched GPU run per problem, f recomputed in FP64 on the host",
+        "training": {"target_generation_s": round(t_gen, 3), "train_s": round(t_train, 3),
+                     "steps": steps, "loss_per_epoch": [round(v, 6) for v in losses]},
+        "plain_solver": {"seconds_per_problem": round(tp, 6), "sample": len(sample),
+                         "iterations_mean": round(float(np.mean(pits)), 1),
+                         "seconds_all_extrapolated": round(t_plain_all, 4)},
+        "batched_cold": {"seconds": round(tc, 4), "iterations_mean_max": [round(float(np.mean(itc)), 1), max(itc)],
+                         "reached_target": int(rc_), "max_gap_host": float(max(gc))},
+        "batched_learned": {"seconds": round(tw, 4), "network_forward_seconds": round(t_fwd, 4),
+                            "iterations_mean_max": [round(float(np.mean(itw)), 1), max(itw)],
+                            "reached_target": int(rw), "max_gap_host": float(max(gw)),
+                            "warm_start_kept": kept,
+                            "x0_rel_err_mean": round(float(np.mean(x0err)), 4),
+                            "net_raw_rel_err_fresh": round(raw_err, 4),
+                            "net_raw_rel_err_training": round(raw_err_train, 4)},
+        "speedup_learned_vs_plain": round(t_plain_all / tw, 2),
+        "speedup_learned_vs_batched_cold": round(tc / tw, 3),
+    }
+    log(f"  plain {tp * 1e3:.2f} ms/problem ({np.mean(pits):.1f} it) -> {t_plain_all:.2f}s for {neval}; "
+        f"batched cold {tc:.3f}s ({np.mean(itc):.1f} it, max {max(itc)}); learned {tw:.3f}s "
+        f"({np.mean(itw):.1f} it, max {max(itw)}, x0 err {np.mean(x0err):.3f}, kept {kept}, "
+        f"network {t_fwd * 1e3:.1f} ms); "
+        f"raw net error fresh {raw_err:.3f} / training {raw_err_train:.3f}")
+    net.close()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -206,6 +379,12 @@ def main():
     ap.add_argument("--no-gap", action="store_true", help="skip the time-to-gap leg")
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the BF16-storage and batched legs")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned warm-start leg")
+    ap.add_argument("--learned-train", type=int, default=16384,
+                    help="training pairs of the learned leg (the full workload uses 100000)")
+    ap.add_argument("--learned-eval", type=int, default=2048,
+                    help="fresh right-hand sides of the learned leg (the full workload uses 10000)")
+    ap.add_argument("--learned-epochs", type=int, default=6)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one plain 256 MiB device-to-device copy (a reference "
                          "kernel of known traffic for hardware-counter scaling)")
@@ -328,6 +507,11 @@ def main():
         out["_x_fp32"] = x_gpu
         out["forms"] = forms_legs(H, inst, np, torch, gpl1, instances, out)
         del out["_x_fp32"]
+
+    # ---- learned warm start + batched refinement --------------------------
+    if not args.no_learned:
+        out["learned_warm_start"] = learned_leg(H, np, torch, gpl1, instances, args.learned_train,
+                                                args.learned_eval, args.learned_epochs)
 
     # ---- CPU oracle baseline + parity at 500 iterations --------------------
     if not args.no_cpu_baseline:

@@ -82,6 +82,10 @@ typedef struct {
     int32_t fused_interleave; /* tuning: 1 = row blocks dealt round-robin to workgroups, 0 = slabs */
     const double* f_targets;  /* batched calls: host array of one f_target per problem (NULL = f_target
                                  for all); must stay valid for the call; ignored by gp_l1_solve */
+    int32_t x0_fallback;      /* 1: when x0 is given and f(P(x0)) >= f(0) = ||y||^2, start from x = 0
+                                 instead (result.x0_rejected = 1).  Shared-K batches test it on the
+                                 device in their first residual pass, gp_l1_solve with two extra
+                                 residual passes; uneven batches return GP_E_UNSUPPORTED. */
 } gp_opts;
 
 typedef struct {
@@ -96,12 +100,13 @@ typedef struct {
     double t_fused_ms;    /* with opts.profile: summed duration of the fused launches */
     int32_t n_fused;      /* with opts.profile: number of fused launches timed  */
     int32_t proj_passes;  /* threshold-search passes summed over the iterations */
+    int32_t x0_rejected;  /* 1 if opts.x0_fallback replaced x0 by 0            */
 } gp_result;
 
 typedef struct gp_handle_s* gp_handle;
 
 /* Fill `o` with the paper's GPSS parameters, max_iter = 100000,
- * f_target = -1 (off), f_targets = NULL, refresh_every = 0,
+ * f_target = -1 (off), f_targets = NULL, x0_fallback = 0, refresh_every = 0,
  * backtrack_cap = 60, chunk = 64, automatic kernel shapes. */
 void gp_opts_default(gp_opts* o);
 

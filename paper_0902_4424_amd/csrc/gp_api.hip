@@ -99,6 +99,7 @@ GPParams make_params(const gp_opts& o, double rho, double tol) {
     P.Malpha = o.M_alpha;
     P.max_iter = o.max_iter;
     P.bt_cap = o.backtrack_cap;
+    P.x0_fallback = o.x0_fallback ? 1 : 0;
     return P;
 }
 
@@ -309,6 +310,7 @@ void gp_opts_default(gp_opts* o) {
     o->profile = 0;
     o->fused_interleave = 0;
     o->f_targets = nullptr;
+    o->x0_fallback = 0;
 }
 
 int gp_create(gp_handle* out, int device) {
@@ -444,7 +446,33 @@ int gp_l1_solve(gp_handle h, gp_dtype kdtype, const void* K, int64_t n, int64_t 
         launch_fused(kdtype, P.cfg, aligned, s, P.G, fa_refresh);
         launch_update(kdtype, s, st, UM_REFRESH, spart, (int)P.G, wpart, P.ldw, p, n, x, g, d, r, q, upart);
     };
-    refresh();
+    int x0_rejected = 0;
+    if (x0 && o.x0_fallback) {
+        // f(0) = ||y||^2 from a residual pass at x = 0 (P(x0) parked in d),
+        // then f(P(x0)); x0 is kept only if it is strictly better
+        e = hipMemcpyAsync(d, x, 8 * p, hipMemcpyDeviceToDevice, s);
+        if (e == hipSuccess) e = hipMemsetAsync(x, 0, 8 * p, s);
+        if (e != hipSuccess) return hip_fail(h, e, "x0 fallback");
+        refresh();
+        e = hipMemcpyAsync(h->host_state, st, sizeof(GPState), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return hip_fail(h, e, "x0 fallback");
+        const double f0 = h->host_state->f_new;     // a refresh stages f until the next projection commits it
+        e = hipMemcpyAsync(x, d, 8 * p, hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess) return hip_fail(h, e, "x0 fallback");
+        refresh();
+        e = hipMemcpyAsync(h->host_state, st, sizeof(GPState), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return hip_fail(h, e, "x0 fallback");
+        if (!(h->host_state->f_new < f0)) {
+            x0_rejected = 1;
+            e = hipMemsetAsync(x, 0, 8 * p, s);
+            if (e != hipSuccess) return hip_fail(h, e, "x0 fallback");
+            refresh();
+        }
+    } else {
+        refresh();
+    }
     launch_proj(s, st, PM_ALPHA0, p, x, g, nullptr, nullptr, 0, vb);
     e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(h, e, "init launch");
@@ -478,6 +506,7 @@ int gp_l1_solve(gp_handle h, gp_dtype kdtype, const void* K, int64_t n, int64_t 
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(h, e, "final sync");
     fill_result(*h->host_state, res);
+    res->x0_rejected = x0_rejected;
     if (o.profile) {
         // fused launches that did work: one per accepted update, plus the one
         // whose direction was found stationary or failed the line search
@@ -501,5 +530,6 @@ void fill_result(const GPState& s, gp_result* res) {
     res->lambda_est = s.gmax / 2.0;
     res->l1norm = s.l1;
     res->proj_passes = s.michelot_total;
+    res->x0_rejected = s.x0_rejected;
 }
 }  // namespace gpl1

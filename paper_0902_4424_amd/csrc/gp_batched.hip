@@ -94,6 +94,7 @@ extern "C" int gp_l1_solve_batched_var(gp_handle h, gp_dtype kdtype, const gp_in
     if (rc0) return rc0;
     rc0 = check_targets(h, o, B);
     if (rc0) return rc0;
+    if (o.x0_fallback) return fail(h, GP_E_UNSUPPORTED, "opts.x0_fallback is not available for uneven batches");
     for (int64_t b = 0; b < B; ++b) { std::memset(&res[b], 0, sizeof(gp_result)); res[b].status = GP_E_ARG; }
     hipError_t e = hipSetDevice(h->device);
     if (e != hipSuccess) return hip_fail(h, e, "hipSetDevice");

@@ -181,16 +181,30 @@ __global__ __launch_bounds__(BS_T) void k_bs_rows(BsPtrs P, int mode, int refres
         return s;
     };
     if (mode == BR_REFRESH) {
-        double acc[1] = {0.0}, none[1] = {0.0};
+        // first pass with the x0 test: also ||y||^2 = f(0)
+        const bool fb = st->prm.x0_fallback && st->k == 0 && st->nhist == 0;
+        double acc[2] = {0.0, 0.0}, none[1] = {0.0};
         for (int64_t i = tid; i < n; i += BS_T) {
             const double ri = tval(i) - y[i];
             r[i] = ri;
             acc[0] += ri * ri;
+            acc[1] += y[i] * y[i];
             split3(ri, P.Qsp, P.plQ, b * P.npad + i);
         }
-        block_reduce<BS_T, 1, 1>(acc, none, lds);
+        block_reduce<BS_T, 2, 1>(acc, none, lds);
+        const bool reject = fb && !(acc[0] < acc[1]);
+        if (reject) {
+            // P(x0) is no better than 0: start from x = 0, r = -y
+            for (int64_t i = tid; i < n; i += BS_T) {
+                r[i] = -y[i];
+                split3(-y[i], P.Qsp, P.plQ, b * P.npad + i);
+            }
+            double* x = P.X + b * P.p;
+            for (int64_t j = tid; j < P.p; j += BS_T) x[j] = 0.0;
+        }
         if (tid == 0) {
-            const double f = acc[0];
+            const double f = reject ? acc[1] : acc[0];
+            if (reject) st->x0_rejected = 1;
             if (st->k == 0 && st->nhist == 0) {
                 st->hpos = 0;
                 st->fhist[0] = f;
@@ -498,7 +512,8 @@ int solve_batched_shared_mfma(gp_handle h, gp_dtype kdtype, const void* K, int64
     else
         hipLaunchKernelGGL(k_bs_pack_f32, dim3((unsigned)(ppad / 64), (unsigned)(npad / 64)), dim3(256), 0, s,
                            (const float*)K, n, p, ldk, Kp, ppad, kpl, Kt, npad, kpl);
-    const GPParams prm = make_params(o, 0.0, tol);
+    GPParams prm = make_params(o, 0.0, tol);
+    prm.x0_fallback = (o.x0_fallback && X0) ? 1 : 0;
     const int f64v = 0;
     GPL1_BS_NV_SWITCH(nv, hipLaunchKernelGGL(k_bs_init<NVc>, dim3((unsigned)B), dim3(BS_T), 0, s, P, prm, drho,
                                              dft, Y, ldy, X0, ldx, f64v));

@@ -31,6 +31,7 @@ enum Status : int32_t {
 struct GPParams {
     double theta, beta, amin, amax, tau1, f_target, tol, rho;
     int32_t M, Malpha, max_iter, bt_cap;
+    int32_t x0_fallback;       // start from 0 when f(P(x0)) >= f(0) = ||y||^2
 };
 
 struct GPState {
@@ -51,7 +52,7 @@ struct GPState {
     double lam, f_new, rel;
     int32_t k_new, pending, ss_pending, nb;
     int32_t backtracks;
-    int32_t status, done, projected;
+    int32_t status, done, projected, x0_rejected;
     int32_t live, stop_req;
     int32_t michelot_iters;    // diagnostics: passes of the last threshold search
     int32_t michelot_total;    // diagnostics: passes summed over the iterations

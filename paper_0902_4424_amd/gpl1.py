@@ -34,7 +34,8 @@ class GPOpts(C.Structure):
                 ("refresh_every", C.c_int32), ("backtrack_cap", C.c_int32),
                 ("chunk", C.c_int32), ("fused_cfg", C.c_int32),
                 ("fused_grid", C.c_int32), ("profile", C.c_int32),
-                ("fused_interleave", C.c_int32), ("f_targets", C.POINTER(C.c_double))]
+                ("fused_interleave", C.c_int32), ("f_targets", C.POINTER(C.c_double)),
+                ("x0_fallback", C.c_int32)]
 
 
 class GPResult(C.Structure):
@@ -43,7 +44,7 @@ class GPResult(C.Structure):
                 ("f", C.c_double), ("rel_change", C.c_double),
                 ("lambda_est", C.c_double), ("l1norm", C.c_double),
                 ("t_fused_ms", C.c_double), ("n_fused", C.c_int32),
-                ("proj_passes", C.c_int32)]
+                ("proj_passes", C.c_int32), ("x0_rejected", C.c_int32)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_}
@@ -411,22 +412,6 @@ class Lista:
                                                   Xstar.stride(0), B, _ptr(dWe), _ptr(dS), _ptr(dth),
                                                   C.byref(loss), _stream(stream)))
         return loss.value, dWe, dS, dth
-
-
-def warm_start(net: Lista, K, Y, rho, margin: float = 1e-9, **solve_kw):
-    """x0 = P_Omega(net(y)) for each row of Y, replaced by 0 wherever it does
-    not beat the zero start by more than rounding: kept only if
-    f(x0) < (1 - margin) f(0), f(0) = ||y||^2.  Both objective values come
-    from the library (a zero-iteration solve reports f at its start)."""
-    torch = _torch()
-    B = Y.shape[0]
-    X0 = net.forward(Y, rho=rho)
-    _, res = net.H.solve_batched_shared(K, Y, rho, X0=X0, tol=0.0, max_iter=0, **solve_kw)
-    _, res0 = net.H.solve_batched_shared(K, Y, rho, tol=0.0, max_iter=0, **solve_kw)
-    keep = torch.tensor([r["f"] < (1.0 - margin) * r0["f"] for r, r0 in zip(res, res0)],
-                        device=Y.device)
-    X0 = torch.where(keep[:, None], X0, torch.zeros_like(X0))
-    return X0, keep
 
 
 _DT_NAME = {GP_F64: "f64", GP_F32: "f32", GP_BF16: "bf16"}

@@ -281,3 +281,46 @@ def shared_rhs(seed=5, dtype="bf16", n=2048, p=8192, B=256) -> SharedBatch:
     return shared_batch(n, p, B, max(1, n // 20), amp="pm1", sigma=1e-2,
                         dtype=dtype, seed=seed, rhs_seed_base=5000,
                         name=f"shared_{n}x{p}x{B}")
+
+
+@dataclass
+class WarmStartSet:
+    """Right-hand sides for one fixed K: Y (B x n, FP32), rho (B), and the
+    sparse x_true of each row as (support B x s, signs B x s)."""
+    Y: np.ndarray
+    rho: np.ndarray
+    support: np.ndarray
+    signs: np.ndarray
+
+
+def warm_start_matrix(n=1024, p=4096, seed=6):
+    """The fixed K of the learned warm-start workload: N(0, 1/n) entries,
+    rounded to FP32 (returned as FP32, the stored problem)."""
+    rng = np.random.default_rng(seed)
+    return (rng.standard_normal((n, p)) / np.sqrt(n)).astype(np.float32)
+
+
+def warm_start_rhs(K32, B, s=50, sigma=1e-2, seed=0, chunk=1024) -> WarmStartSet:
+    """B data vectors y = K x_true + noise for one stored K: x_true s-sparse
+    with a uniformly random support and +/-1 amplitudes, noise N(0, sigma^2),
+    rho = ||x_true||_1 = s.  Drawn in chunks from one PCG64 stream (support
+    keys, signs, noise per chunk); y formed in FP64 and rounded to FP32."""
+    n, p = K32.shape
+    rng = np.random.default_rng(seed)
+    K64 = K32.astype(np.float64)
+    Y = np.empty((B, n), dtype=np.float32)
+    sup = np.empty((B, s), dtype=np.int64)
+    sg = np.empty((B, s), dtype=np.float64)
+    for b0 in range(0, B, chunk):
+        m = min(chunk, B - b0)
+        keys = rng.random((m, p))
+        sp = np.argpartition(keys, s, axis=1)[:, :s]
+        sv = rng.choice(np.array([-1.0, 1.0]), size=(m, s))
+        noise = sigma * rng.standard_normal((m, n))
+        Xc = np.zeros((m, p))
+        np.put_along_axis(Xc, sp, sv, axis=1)
+        Yc = Xc @ K64.T + noise
+        Y[b0:b0 + m] = Yc.astype(np.float32)
+        sup[b0:b0 + m] = sp
+        sg[b0:b0 + m] = sv
+    return WarmStartSet(Y, np.full(B, float(s)), sup, sg)

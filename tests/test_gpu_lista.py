@@ -211,22 +211,32 @@ def test_projected_output_and_warm_start(H):
         ref = project_l1(raw[b], rho[b])
         assert np.abs(proj[b] - ref).max() <= 1e-6 * max(1.0, np.abs(ref).max())
         assert np.abs(proj[b]).sum() <= rho[b] * (1 + 1e-6)
-    # a network with zero weights proposes 0, which is never kept
-    zero = gpl1.Lista(H, n, p, L)
+    # the solver's x0 test: a network with zero weights proposes 0, which is never kept
     Kd = _dev(K32)
-    X0z, keepz = gpl1.warm_start(zero, Kd, Yd, rho)
-    assert not keepz.any().item() and not X0z.any().item()
-    X0, keep = gpl1.warm_start(net, Kd, Yd, rho)
-    keep = keep.cpu().numpy()
+    zero = gpl1.Lista(H, n, p, L)
+    X0z = zero.forward(Yd, rho=rho)
+    assert not X0z.any().item()
+    _, rz = H.solve_batched_shared(Kd, Yd, rho, X0=X0z, tol=0.0, max_iter=0, x0_fallback=1)
+    assert all(r["x0_rejected"] == 1 for r in rz)
+    X0 = net.forward(Yd, rho=rho)
     X0h = X0.cpu().double().numpy()
     K64 = K32.astype(np.float64)
+    Xr, rr = H.solve_batched_shared(Kd, Yd, rho, X0=X0, tol=0.0, max_iter=0, x0_fallback=1)
+    _, rs = H.solve(Kd, Yd[0], float(rho[0]), x0=X0[0].contiguous(), tol=0.0, max_iter=0, x0_fallback=1)
+    keep = np.array([r["x0_rejected"] == 0 for r in rr])
+    assert rs["x0_rejected"] == rr[0]["x0_rejected"]
+    Xrh = Xr.cpu().double().numpy()
     for b in range(B):
-        f0 = np.sum((K64 @ proj[b] - Y[b]) ** 2)
+        f0 = np.sum((K64 @ X0h[b] - Y[b]) ** 2)
         fy = np.sum(Y[b] ** 2)
         if abs(f0 - fy) > 1e-6 * fy:             # away from a tie the host agrees on the choice
             assert keep[b] == (f0 < fy)
-        np.testing.assert_array_equal(X0h[b], proj[b] if keep[b] else 0.0)
+        expect = X0h[b] if keep[b] else 0.0
+        np.testing.assert_allclose(Xrh[b], expect, rtol=0, atol=1e-7)
+        assert abs(rr[b]["f"] - (f0 if keep[b] else fy)) <= 1e-6 * fy
     assert keep.mean() >= 0.5               # ISTA steps from zero mostly lower f
+    with pytest.raises(gpl1.GPError):
+        H.solve_batched_var([(Kd, Yd[0], float(rho[0]), X0[0])], x0_fallback=1)
     # warm-started solves reach the same solutions as cold ones
     cold, rc = H.solve_batched_var([(Kd, Yd[b], rho[b]) for b in range(B)], tol=1e-12, max_iter=5000,
                                    refresh_every=50)
