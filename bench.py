@@ -11,7 +11,11 @@ Prints ONE JSON line: iterations/s (whole job), the fused K/K^T kernel's
 roofline (algorithmic bytes per launch / its HIP-event-timed duration inside
 the timed solves), wall time to a 1e-6 relative objective gap, parity of the
 returned x against the FP64 CPU oracle, and the oracle's own iteration rate
-on this host as a reported CPU baseline.
+on this host as a reported CPU baseline.  Further legs, each reported in its
+own key: BF16 storage of the same instance, 256 right-hand sides sharing a
+bf16 K 2048x8192, 512 uneven problems, and the learned warm start (an
+unrolled network trained on 100000 batched solutions for a fixed FP32 K
+1024x4096, then 10000 fresh problems to a 1e-6 gap).
 """
 import argparse
 import hashlib
@@ -27,6 +31,10 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 ITERS = 500
 REFRESH = 50
+# the fused launch of every 8th iteration is timed with HIP events inside the
+# timed solves; an event pair on the stream costs a few microseconds, so timing
+# every launch would slow the iterations being measured
+PROFILE_EVERY = 8
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fused_traffic_gauss_4096x16384.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_0902_4424_amd", "csrc", f)
                   for f in ("gp_kernels.hpp", "gp_device.hpp")]
@@ -85,7 +93,7 @@ def forms_legs(H, inst, np, torch, gpl1, instances, out):
     b16 = instances.plain_large(seed=2, dtype="bf16")
     Kb = torch.from_numpy(b16.K_store.view(np.int16)).to(dev)
     yb = torch.from_numpy(b16.y_store).to(dev)
-    ob = gpl1.default_opts(max_iter=ITERS, refresh_every=REFRESH, profile=1)
+    ob = gpl1.default_opts(max_iter=ITERS, refresh_every=REFRESH, profile=PROFILE_EVERY)
     H.solve(Kb, yb, b16.rho, tol=0.0, opts=ob)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -195,6 +203,55 @@ def forms_legs(H, inst, np, torch, gpl1, instances, out):
         "sweep_GBps_lower_bound": round(kbytes * max(vits) / tvar / 1e9, 1)}
     log(f"batched uneven: {tvar * 1e3:.1f} ms for 512 problems; plain {tseq * 1e3:.2f} ms/problem")
     return res
+
+
+def ingest_counters(fetch_dir, write_dir):
+    """Write the fused kernel's measured HBM bytes per live launch from two
+    rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE; KiB per dispatch) of
+    `bench.py --steps 1 --warmup 0 --no-gap --no-cpu-baseline --no-forms
+    --no-learned --calibrate-copy`.  Each counter is scaled by what it reads for
+    the 256 MiB reference copy; launches below half the largest fetch (those
+    that exited at once after the solve stopped) are left out."""
+    import csv
+    import glob
+    from collections import defaultdict
+
+    def per_dispatch(d, counter):
+        path = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)[0]
+        val, name = defaultdict(float), {}
+        with open(path) as fh:
+            for r in csv.DictReader(fh):
+                if r["Counter_Name"] == counter:
+                    k = int(r["Dispatch_Id"])
+                    val[k] += float(r["Counter_Value"])
+                    name[k] = r["Kernel_Name"]
+        return val, name
+
+    fv, fname = per_dispatch(fetch_dir, "FETCH_SIZE")
+    wv, wname = per_dispatch(write_dir, "WRITE_SIZE")
+    copy_f = max(v for k, v in fv.items() if "copyBuffer" in fname[k])
+    copy_w = max(v for k, v in wv.items() if "copyBuffer" in wname[k])
+    ref_kib = 256 * 1024
+    fs, ws = ref_kib / copy_f, ref_kib / copy_w
+    fused_f = [v for k, v in fv.items() if "k_fused" in fname[k]]
+    fused_w = [v for k, v in wv.items() if "k_fused" in wname[k]]
+    kname = next(fname[k] for k in fv if "k_fused" in fname[k])
+    lf = [v for v in fused_f if v > 0.5 * max(fused_f)]
+    lw = sorted(fused_w)[-len(lf):]
+    fb = sum(lf) / len(lf) * 1024 * fs
+    wb = sum(lw) / len(lw) * 1024 * ws
+    t = {"kernel": kname.split("(")[0].replace("void ", ""), "workload": "gauss 4096x16384 fp32",
+         "kernel_hash": kernel_hash(), "fetch_scale": fs, "write_scale": ws, "live_launches": len(lf),
+         "fetch_bytes_per_launch": int(fb), "write_bytes_per_launch": int(wb),
+         "bytes_per_launch": int(fb + wb), "algorithmic_bytes_per_launch": 4096 * 16384 * 4 + 8 * 16384 +
+         16 * 4096 + 4 * 16384,
+         "command": "cd /tmp && export TMPDIR=/tmp && timeout -s KILL 120 rocprofv3 --pmc "
+                    "<FETCH_SIZE|WRITE_SIZE> -f csv -d <out> -o run -- python3 <repo>/bench.py --steps 1 "
+                    "--warmup 0 --no-gap --no-cpu-baseline --no-forms --no-learned --calibrate-copy"}
+    with open(TRAFFIC_FILE, "w") as fh:
+        json.dump(t, fh, indent=1)
+        fh.write("\n")
+    print(json.dumps(t, indent=1))
 
 
 def learned_leg(H, np, torch, gpl1, instances, ntrain, neval, epochs, batch=256, lr=3e-4,
@@ -380,15 +437,21 @@ def main():
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the BF16-storage and batched legs")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned warm-start leg")
-    ap.add_argument("--learned-train", type=int, default=16384,
-                    help="training pairs of the learned leg (the full workload uses 100000)")
-    ap.add_argument("--learned-eval", type=int, default=2048,
-                    help="fresh right-hand sides of the learned leg (the full workload uses 10000)")
+    ap.add_argument("--learned-train", type=int, default=100000,
+                    help="training pairs of the learned leg")
+    ap.add_argument("--learned-eval", type=int, default=10000,
+                    help="fresh right-hand sides of the learned leg")
     ap.add_argument("--learned-epochs", type=int, default=6)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one plain 256 MiB device-to-device copy (a reference "
                          "kernel of known traffic for hardware-counter scaling)")
+    ap.add_argument("--ingest-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="write the fused kernel's measured traffic from two rocprofv3 --pmc "
+                         "output folders and exit (no GPU needed)")
     args = ap.parse_args()
+    if args.ingest_counters:
+        ingest_counters(*args.ingest_counters)
+        return
     if args.gpus != 1:
         print(f"bench.py: this solver runs on one GPU; --gpus {args.gpus} is not supported "
               "(independent problems shard across GPUs without exchange, see the design notes)",
@@ -409,7 +472,7 @@ def main():
     y = torch.from_numpy(inst.y_store).to(dev)
     torch.cuda.synchronize()
     H = gpl1.Handle(0)
-    opts = gpl1.default_opts(max_iter=ITERS, refresh_every=REFRESH, profile=1)
+    opts = gpl1.default_opts(max_iter=ITERS, refresh_every=REFRESH, profile=PROFILE_EVERY)
     if args.calibrate_copy:
         src = torch.ones(64 << 20, dtype=torch.float32, device=dev)   # 256 MiB
         dst = torch.empty_like(src)

@@ -116,6 +116,7 @@ int check_opts(gp_handle h, const gp_opts& o) {
     if (o.backtrack_cap < 0 || o.backtrack_cap > 1000) return fail(h, GP_E_ARG, "opts.backtrack_cap must be in 0..1000");
     if (o.chunk < 1) return fail(h, GP_E_ARG, "opts.chunk must be >= 1");
     if (std::isnan(o.f_target)) return fail(h, GP_E_ARG, "opts.f_target is NaN");
+    if (o.profile < 0) return fail(h, GP_E_ARG, "opts.profile must be >= 0");
     return GP_OK_TOL;
 }
 
@@ -164,6 +165,7 @@ struct FusedArgs {
     const GPState* st; const void* K; int64_t n, p, ldk, rows;
     const double *v, *vsub, *g, *ysub, *rvec; double* tout; void* wpart; int64_t ldw; double* spart;
     int interleave;
+    const float* v32;   // float copy of the multiplied vector, or NULL
 };
 
 template <typename TK, typename ACC, int T, int CPT, int RB, int NB>
@@ -171,11 +173,11 @@ void launch_fused_t(bool aligned, hipStream_t s, int64_t G, const FusedArgs& a) 
     if (aligned)
         hipLaunchKernelGGL((k_fused<TK, ACC, T, CPT, RB, NB, true>), dim3((unsigned)G), dim3(T), 0, s, a.st,
                            (const TK*)a.K, a.n, a.p, a.ldk, a.rows, a.v, a.vsub, a.g, a.ysub, a.rvec, a.tout,
-                           (ACC*)a.wpart, a.ldw, a.spart, a.interleave);
+                           (ACC*)a.wpart, a.ldw, a.spart, a.interleave, a.v32);
     else
         hipLaunchKernelGGL((k_fused<TK, ACC, T, CPT, RB, NB, false>), dim3((unsigned)G), dim3(T), 0, s, a.st,
                            (const TK*)a.K, a.n, a.p, a.ldk, a.rows, a.v, a.vsub, a.g, a.ysub, a.rvec, a.tout,
-                           (ACC*)a.wpart, a.ldw, a.spart, a.interleave);
+                           (ACC*)a.wpart, a.ldw, a.spart, a.interleave, a.v32);
 }
 
 template <typename TK, typename ACC>
@@ -215,10 +217,10 @@ int proj_vpt(int64_t p) {
 }
 
 void launch_proj(hipStream_t s, GPState* st, int mode, int64_t p, double* x, const double* g, double* dout,
-                 const double* upart, int GU, double* vbuf) {
+                 const double* upart, int GU, double* vbuf, float* d32) {
     switch (proj_vpt(p)) {
 #define GPL1_PROJ_CASE(V) \
-    case V: hipLaunchKernelGGL(k_proj<V>, dim3(1), dim3(PROJ_T), 0, s, st, mode, p, x, g, dout, upart, GU, vbuf); break;
+    case V: hipLaunchKernelGGL(k_proj<V>, dim3(1), dim3(PROJ_T), 0, s, st, mode, p, x, g, dout, upart, GU, vbuf, d32); break;
         GPL1_PROJ_CASE(2)
         GPL1_PROJ_CASE(4)
         GPL1_PROJ_CASE(8)
@@ -273,6 +275,7 @@ Plan plan_single(gp_dtype dt, int64_t n, int64_t p, const gp_opts& o) {
     P.o_g = take(sizeof(double) * p);
     P.o_d = take(sizeof(double) * p);
     P.o_vbuf = take(sizeof(double) * p);
+    P.o_d32 = take(sizeof(float) * p);
     P.o_r = take(sizeof(double) * n);
     P.o_q = take(sizeof(double) * n);
     P.o_y = take(sizeof(double) * n);
@@ -375,7 +378,7 @@ int gp_l1_project(gp_handle h, gp_dtype vdtype, const void* v, int64_t p, double
     hipLaunchKernelGGL(k_init_state, dim3(1), dim3(1), 0, s, st, make_params(o, rho, 0.0));
     if (vdtype == GP_F64) launch_to_f64<double>(s, v, x, p);
     else launch_to_f64<float>(s, v, x, p);
-    launch_proj(s, st, PM_PLAIN, p, x, nullptr, hv, nullptr, 0, vb);
+    launch_proj(s, st, PM_PLAIN, p, x, nullptr, hv, nullptr, 0, vb, nullptr);
     if (vdtype == GP_F64) launch_from_f64<double>(s, hv, h_out, p);
     else launch_from_f64<float>(s, hv, h_out, p);
     e = hipGetLastError();
@@ -423,6 +426,8 @@ int gp_l1_solve(gp_handle h, gp_dtype kdtype, const void* K, int64_t n, int64_t 
     double* g = (double*)(ws + P.o_g);
     double* d = (double*)(ws + P.o_d);
     double* vb = (double*)(ws + P.o_vbuf);
+    // float copy of d for the fused pass (its products are float for FP32 and bf16 K)
+    float* d32 = kdtype == GP_F64 ? nullptr : (float*)(ws + P.o_d32);
     double* r = (double*)(ws + P.o_r);
     double* q = (double*)(ws + P.o_q);
     double* y64 = (double*)(ws + P.o_y);
@@ -436,12 +441,13 @@ int gp_l1_solve(gp_handle h, gp_dtype kdtype, const void* K, int64_t n, int64_t 
     hipLaunchKernelGGL(k_init_state, dim3(1), dim3(1), 0, s, st, make_params(o, rho, tol));
     if (f64v) { launch_to_f64<double>(s, y, y64, n); launch_to_f64<double>(s, x0, x, p); }
     else { launch_to_f64<float>(s, y, y64, n); launch_to_f64<float>(s, x0, x, p); }
-    if (x0) launch_proj(s, st, PM_INIT_X0, p, x, nullptr, nullptr, nullptr, 0, vb);
+    if (x0) launch_proj(s, st, PM_INIT_X0, p, x, nullptr, nullptr, nullptr, 0, vb, nullptr);
     // r = K x - y, g = 2 K^T r, f = ||r||^2
     // d holds h = P(x - alpha g) between the projection and the update
     const int il = o.fused_interleave;
-    const FusedArgs fa_refresh{st, K, n, p, ldk, P.rows, x, nullptr, nullptr, y64, nullptr, q, wpart, P.ldw, spart, il};
-    const FusedArgs fa_iter{st, K, n, p, ldk, P.rows, d, x, g, nullptr, r, q, wpart, P.ldw, spart, il};
+    const FusedArgs fa_refresh{st, K, n, p, ldk, P.rows, x, nullptr, nullptr, y64, nullptr, q, wpart, P.ldw, spart, il,
+                               nullptr};
+    const FusedArgs fa_iter{st, K, n, p, ldk, P.rows, d, x, g, nullptr, r, q, wpart, P.ldw, spart, il, d32};
     auto refresh = [&]() {
         launch_fused(kdtype, P.cfg, aligned, s, P.G, fa_refresh);
         launch_update(kdtype, s, st, UM_REFRESH, spart, (int)P.G, wpart, P.ldw, p, n, x, g, d, r, q, upart);
@@ -473,7 +479,7 @@ int gp_l1_solve(gp_handle h, gp_dtype kdtype, const void* K, int64_t n, int64_t 
     } else {
         refresh();
     }
-    launch_proj(s, st, PM_ALPHA0, p, x, g, nullptr, nullptr, 0, vb);
+    launch_proj(s, st, PM_ALPHA0, p, x, g, nullptr, nullptr, 0, vb, nullptr);
     e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(h, e, "init launch");
 
@@ -481,8 +487,9 @@ int gp_l1_solve(gp_handle h, gp_dtype kdtype, const void* K, int64_t n, int64_t 
     while (it < o.max_iter) {
         const int end = std::min(o.max_iter, it + o.chunk);
         for (; it < end; ++it) {
-            launch_proj(s, st, PM_ITER, p, x, g, d, upart, P.GU, vb);
-            hipEvent_t e0 = o.profile ? prof_event(h) : nullptr;
+            launch_proj(s, st, PM_ITER, p, x, g, d, upart, P.GU, vb, d32);
+            // every profile-th iteration's fused launch is bracketed by events
+            hipEvent_t e0 = (o.profile > 0 && it % o.profile == 0) ? prof_event(h) : nullptr;
             if (e0) (void)hipEventRecord(e0, s);
             launch_fused(kdtype, P.cfg, aligned, s, P.G, fa_iter);
             hipEvent_t e1 = e0 ? prof_event(h) : nullptr;
@@ -511,7 +518,7 @@ int gp_l1_solve(gp_handle h, gp_dtype kdtype, const void* K, int64_t n, int64_t 
         // fused launches that did work: one per accepted update, plus the one
         // whose direction was found stationary or failed the line search
         const int live = res->iters + ((res->status == GP_STATIONARY || res->status == GP_BACKTRACK_LIMIT) ? 1 : 0);
-        res->t_fused_ms = prof_collect(h, live, &res->n_fused);
+        res->t_fused_ms = prof_collect(h, (live + o.profile - 1) / o.profile, &res->n_fused);
     }
     if (res->status < 0) return fail(h, res->status, "solve ended with a non-finite value");
     return res->status;

@@ -28,7 +28,7 @@ struct Plan {
     int64_t rows;     // rows per slab
     int64_t ldw;      // stride of the partial w vectors
     int nbp, GU;      // update kernel: column workgroups, all workgroups
-    size_t o_state, o_x, o_g, o_d, o_vbuf, o_r, o_q, o_y, o_spart, o_upart, o_wpart, bytes;
+    size_t o_state, o_x, o_g, o_d, o_vbuf, o_d32, o_r, o_q, o_y, o_spart, o_upart, o_wpart, bytes;
 };
 
 int fail(gp_handle h, int code, const std::string& msg);

@@ -195,22 +195,46 @@ __global__ __launch_bounds__(PROJ_T) void k_proj(GPState* __restrict__ st, int m
                                                  double* __restrict__ x, const double* __restrict__ g,
                                                  double* __restrict__ dout,
                                                  const double* __restrict__ upart, int GU,
-                                                 double* __restrict__ vbuf) {
+                                                 double* __restrict__ vbuf, float* __restrict__ d32) {
     constexpr int T = PROJ_T;
     constexpr int NV = VPT > 0 ? VPT : 1;
     __shared__ double lds[3 * (T / WAVE)];
     __shared__ double sh_alpha, sh_mu;
     __shared__ GPState S;
     const int tid = threadIdx.x;
+    // x and g are requested first so that their latency overlaps the state
+    // load and the steplength rule; v = x - alpha g is formed once alpha is
+    // known (up to 16 slots per thread; beyond that g would not fit in
+    // registers and both are read after the steplength rule).  g is not read
+    // in the modes that have none.
+    constexpr bool PREF = VPT > 0 && VPT <= 16;
+    const bool use_g = mode == PM_ITER || mode == PM_ALPHA0;
+    double vr[NV], gr[PREF ? NV : 1];
+    if (PREF) {
+#pragma unroll
+        for (int e = 0; e < NV; e += 2) {
+            const int j = 2 * ((e / 2) * T + tid);   // p < 2^31: 32-bit offsets
+            if (NV > 1 && j + 1 < p) {
+                const double2 x2 = *reinterpret_cast<const double2*>(x + j);
+                double2 g2 = make_double2(0.0, 0.0);
+                if (use_g) g2 = *reinterpret_cast<const double2*>(g + j);
+                vr[e] = x2.x;
+                vr[e + 1] = x2.y;
+                gr[PREF ? e : 0] = g2.x;
+                gr[PREF ? e + 1 : 0] = g2.y;
+            } else {
+                vr[e] = j < p ? x[j] : 0.0;
+                gr[PREF ? e : 0] = (j < p && use_g) ? g[j] : 0.0;
+                if (NV > 1) { vr[e + 1] = 0.0; gr[PREF ? e + 1 : 0] = 0.0; }
+            }
+        }
+    }
     state_load(S, st);
     __syncthreads();
     if (S.done || S.stop_req) {
         if (tid == 0) st->live = 0;
         return;
     }
-    // x (and g) stay in registers for the whole kernel; v = x - alpha g is
-    // recomputed where needed.  g is not read in the modes that have none.
-    const bool use_g = mode == PM_ITER || mode == PM_ALPHA0;
 
     // -- steplength (Algorithm 2) from the partial dots of the last update --
     if (mode == PM_ITER) {
@@ -246,21 +270,27 @@ __global__ __launch_bounds__(PROJ_T) void k_proj(GPState* __restrict__ st, int m
     // -- v = x - alpha g ---------------------------------------------------
     // Register slot e holds element j = 2*((e/2)*T + tid) + (e&1): each
     // thread owns pairs of neighbours, read with 16-byte loads.
-    double vr[NV];
     double Sm_s[1] = {0.0}, Sm_m[1] = {0.0};
     if (VPT > 0) {
+        if (PREF) {
+            if (use_g) {
 #pragma unroll
-        for (int e = 0; e < NV; e += 2) {
-            const int j = 2 * ((e / 2) * T + tid);   // p < 2^31: 32-bit offsets
-            if (NV > 1 && j + 1 < p) {
-                const double2 x2 = *reinterpret_cast<const double2*>(x + j);
-                double2 g2 = make_double2(0.0, 0.0);
-                if (use_g) g2 = *reinterpret_cast<const double2*>(g + j);
-                vr[e] = x2.x - alpha * g2.x;
-                vr[e + 1] = x2.y - alpha * g2.y;
-            } else {
-                vr[e] = j < p ? (use_g ? x[j] - alpha * g[j] : x[j]) : 0.0;
-                if (NV > 1) vr[e + 1] = 0.0;
+                for (int e = 0; e < NV; ++e) vr[e] -= alpha * gr[PREF ? e : 0];
+            }
+        } else {
+#pragma unroll
+            for (int e = 0; e < NV; e += 2) {
+                const int j = 2 * ((e / 2) * T + tid);
+                if (NV > 1 && j + 1 < p) {
+                    const double2 x2 = *reinterpret_cast<const double2*>(x + j);
+                    double2 g2 = make_double2(0.0, 0.0);
+                    if (use_g) g2 = *reinterpret_cast<const double2*>(g + j);
+                    vr[e] = x2.x - alpha * g2.x;
+                    vr[e + 1] = x2.y - alpha * g2.y;
+                } else {
+                    vr[e] = j < p ? (use_g ? x[j] - alpha * g[j] : x[j]) : 0.0;
+                    if (NV > 1) vr[e + 1] = 0.0;
+                }
             }
         }
 #pragma unroll
@@ -344,13 +374,24 @@ __global__ __launch_bounds__(PROJ_T) void k_proj(GPState* __restrict__ st, int m
             for (int e = 0; e < NV; e += 2) {
                 const int j = 2 * ((e / 2) * T + tid);
                 if (NV > 1 && j + 1 < p) {
-                    *reinterpret_cast<double2*>(dout + j) = make_double2(hval(vr[e]), hval(vr[e + 1]));
+                    const double h0 = hval(vr[e]), h1 = hval(vr[e + 1]);
+                    *reinterpret_cast<double2*>(dout + j) = make_double2(h0, h1);
+                    if (d32) {   // x re-read (it is in L2) rather than held in registers
+                        const double2 x2 = *reinterpret_cast<const double2*>(x + j);
+                        *reinterpret_cast<float2*>(d32 + j) = make_float2((float)(h0 - x2.x), (float)(h1 - x2.y));
+                    }
                 } else if (j < p) {
-                    dout[j] = hval(vr[e]);
+                    const double h0 = hval(vr[e]);
+                    dout[j] = h0;
+                    if (d32) d32[j] = (float)(h0 - x[j]);
                 }
             }
         } else {
-            for (int64_t j = tid; j < p; j += T) dout[j] = hval(vbuf[j]);
+            for (int64_t j = tid; j < p; j += T) {
+                const double h0 = hval(vbuf[j]);
+                dout[j] = h0;
+                if (d32) d32[j] = (float)(h0 - x[j]);
+            }
         }
         if (tid == 0) {
             S.mu = inside ? 0.0 : m + t;
@@ -486,7 +527,8 @@ __device__ __forceinline__ void fused_body(const TK* __restrict__ K, int64_t n, 
                                            const double* __restrict__ vsub, const double* __restrict__ g,
                                            const double* __restrict__ ysub, const double* __restrict__ rvec,
                                            double* __restrict__ tout, ACC* __restrict__ wrow, int64_t ldw,
-                                           double* __restrict__ sp, int interleave, int64_t wg, int64_t ngroups) {
+                                           double* __restrict__ sp, int interleave, int64_t wg, int64_t ngroups,
+                                           const float* __restrict__ v32 = nullptr) {
     using FB = FusedBlock<TK, ACC, T, CPT, RB>;
     constexpr int VEC = FB::VEC;
     constexpr int NW = FB::NW;
@@ -512,13 +554,16 @@ __device__ __forceinline__ void fused_body(const TK* __restrict__ K, int64_t n, 
     if (NB > 2 && first + step < lim) FB::template load<ALIGNED>(B, K, ldk, p, first + step, lim);
 
     ACC dv[CPT][VEC], w[CPT][VEC];
+    // the multiplied vector: its float copy when the caller has one (ACC is
+    // float then, so the products are the same), else v - vsub in double
 #pragma unroll
     for (int c = 0; c < CPT; ++c) {
         const int64_t col = ((int64_t)c * T + tid) * VEC;
 #pragma unroll
         for (int e = 0; e < VEC; ++e) {
             const int64_t j = col + e;
-            dv[c][e] = j < p ? (ACC)(vsub ? v[j] - vsub[j] : v[j]) : (ACC)0;
+            if (v32) dv[c][e] = j < p ? (ACC)v32[j] : (ACC)0;
+            else dv[c][e] = j < p ? (ACC)(vsub ? v[j] - vsub[j] : v[j]) : (ACC)0;
             w[c][e] = 0;
         }
     }
@@ -625,12 +670,13 @@ __global__ __launch_bounds__(T) void k_fused(const GPState* __restrict__ st, con
                                                 const double* __restrict__ g, const double* __restrict__ ysub,
                                                 const double* __restrict__ rvec, double* __restrict__ tout,
                                                 ACC* __restrict__ wpart, int64_t ldw,
-                                                double* __restrict__ spart, int interleave) {
+                                                double* __restrict__ spart, int interleave,
+                                                const float* __restrict__ v32) {
     if (!st->live) return;
     fused_body<TK, ACC, T, CPT, RB, NB, ALIGNED>(K, n, p, ldk, rows_per_wg, v, vsub, g, ysub, rvec, tout,
                                                  wpart + (int64_t)blockIdx.x * ldw, ldw,
                                                  spart + (int64_t)SPART * blockIdx.x, interleave,
-                                                 (int64_t)blockIdx.x, (int64_t)gridDim.x);
+                                                 (int64_t)blockIdx.x, (int64_t)gridDim.x, v32);
 }
 
 // ---------------------------------------------------------------------------

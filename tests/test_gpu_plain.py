@@ -274,3 +274,17 @@ def test_nonmonotone_memory(H):
     x, res = H.solve(_K_tensor(inst), _dev(inst.y_store), inst.rho, tol=0.0, M=5)
     gap, err, _ = _gap_err(inst, x.cpu().numpy(), ref)
     assert gap <= 1e-10 and err <= 1e-6
+
+
+def test_sampled_profiling(H):
+    say("[solve] timing every k-th fused launch; x unchanged by it")
+    inst = instances.gaussian_instance(512, 2048, 20, dtype="f32", seed=5)
+    K, y = _K_tensor(inst), _dev(inst.y_store)
+    x0, r0 = H.solve(K, y, inst.rho, tol=0.0, max_iter=20)
+    assert r0["iters"] == 20 and r0["n_fused"] == 0
+    for k, want in ((1, 20), (4, 5), (7, 3), (25, 1)):
+        x, r = H.solve(K, y, inst.rho, tol=0.0, max_iter=20, profile=k)
+        assert r["n_fused"] == want and r["t_fused_ms"] > 0.0
+        assert torch.equal(x, x0)
+    with pytest.raises(gpl1.GPError):
+        H.solve(K, y, inst.rho, profile=-1)
