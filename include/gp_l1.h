@@ -203,6 +203,14 @@ int gp_lista_init_from_K(gp_lista net, const float* K, int64_t ldk, double L, do
 int gp_lista_set_weights(gp_lista net, const float* We, const float* S, const float* theta, void* stream);
 int gp_lista_get_weights(gp_lista net, float* We, float* S, float* theta, void* stream);
 
+/* Weights to and from a file: the 8-byte tag "GPLISTA1", int64 n, int64 p,
+ * int32 layers, int32 0, then float32 little-endian W_e^T (n x p, row-major,
+ * element (a, i) = W_e[i][a]), S^T (p x p, element (j, i) = S[i][j]) and
+ * theta (layers).  load requires the network's n, p and layers, and resets
+ * the Adam state.  Errors: GP_E_ARG for a bad path, tag or shape. */
+int gp_lista_save(gp_lista net, const char* path);
+int gp_lista_load(gp_lista net, const char* path);
+
 /* Forward pass on B samples: Y (device, B x n, ldy) -> X_out (device,
  * B x p, ldx).  rho: host array of B radii, or NULL for the raw network
  * output; with rho each row is projected onto its ball. */

@@ -21,6 +21,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -551,6 +552,69 @@ int gp_lista_get_weights(gp_lista net, float* We, float* S, float* theta, void* 
     hipError_t e = hipMemcpyAsync(theta, net->th, 4 * net->L, hipMemcpyDeviceToDevice, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     return e == hipSuccess ? GP_OK_TOL : hip_fail(net->h, e, "get weights");
+}
+
+int gp_lista_save(gp_lista net, const char* path) {
+    if (!net) return GP_E_ARG;
+    gp_handle h = net->h;
+    if (!path) return fail(h, GP_E_ARG, "null path");
+    const int64_t n = net->n, p = net->p, pp = net->pp;
+    std::vector<float> W((size_t)(n * p)), S((size_t)(p * p)), th((size_t)net->L);
+    hipError_t e = hipSetDevice(h->device);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e == hipSuccess) e = hipMemcpy2D(W.data(), 4 * p, net->WeT, 4 * pp, 4 * p, n, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy2D(S.data(), 4 * p, net->ST, 4 * pp, 4 * p, p, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(th.data(), net->th, 4 * net->L, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(h, e, "weights to host");
+    FILE* f = std::fopen(path, "wb");
+    if (!f) return fail(h, GP_E_ARG, std::string("cannot open ") + path);
+    const int32_t hdr32[2] = {net->L, 0};
+    const int64_t hdr64[2] = {n, p};
+    bool ok = std::fwrite("GPLISTA1", 1, 8, f) == 8 && std::fwrite(hdr64, 8, 2, f) == 2 &&
+              std::fwrite(hdr32, 4, 2, f) == 2 && std::fwrite(W.data(), 4, W.size(), f) == W.size() &&
+              std::fwrite(S.data(), 4, S.size(), f) == S.size() && std::fwrite(th.data(), 4, th.size(), f) == th.size();
+    ok = (std::fclose(f) == 0) && ok;
+    return ok ? GP_OK_TOL : fail(h, GP_E_ARG, std::string("write failed: ") + path);
+}
+
+int gp_lista_load(gp_lista net, const char* path) {
+    if (!net) return GP_E_ARG;
+    gp_handle h = net->h;
+    if (!path) return fail(h, GP_E_ARG, "null path");
+    FILE* f = std::fopen(path, "rb");
+    if (!f) return fail(h, GP_E_ARG, std::string("cannot open ") + path);
+    char tag[8];
+    int64_t hdr64[2];
+    int32_t hdr32[2];
+    bool ok = std::fread(tag, 1, 8, f) == 8 && std::memcmp(tag, "GPLISTA1", 8) == 0 &&
+              std::fread(hdr64, 8, 2, f) == 2 && std::fread(hdr32, 4, 2, f) == 2;
+    if (!ok || hdr64[0] != net->n || hdr64[1] != net->p || hdr32[0] != net->L) {
+        std::fclose(f);
+        return fail(h, GP_E_ARG, "not a network file of this shape");
+    }
+    const int64_t n = net->n, p = net->p, pp = net->pp;
+    std::vector<float> W((size_t)(n * p)), S((size_t)(p * p)), th((size_t)net->L);
+    ok = std::fread(W.data(), 4, W.size(), f) == W.size() && std::fread(S.data(), 4, S.size(), f) == S.size() &&
+         std::fread(th.data(), 4, th.size(), f) == th.size();
+    std::fclose(f);
+    if (!ok) return fail(h, GP_E_ARG, "truncated network file");
+    hipError_t e = hipSetDevice(h->device);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e == hipSuccess) e = hipMemcpy2D(net->WeT, 4 * pp, W.data(), 4 * p, 4 * p, n, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy2D(net->ST, 4 * pp, S.data(), 4 * p, 4 * p, p, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(net->th, th.data(), 4 * net->L, hipMemcpyHostToDevice);
+    // a fresh Adam state
+    const int64_t np = net->np;
+    if (e == hipSuccess) e = hipMemset(net->mWe, 0, 4 * np * pp);
+    if (e == hipSuccess) e = hipMemset(net->vWe, 0, 4 * np * pp);
+    if (e == hipSuccess) e = hipMemset(net->mS, 0, 4 * pp * pp);
+    if (e == hipSuccess) e = hipMemset(net->vS, 0, 4 * pp * pp);
+    if (e == hipSuccess) e = hipMemset(net->mth, 0, 4 * 64);
+    if (e == hipSuccess) e = hipMemset(net->vth, 0, 4 * 64);
+    if (e != hipSuccess) return hip_fail(h, e, "weights to device");
+    net->step = 0;
+    net->bf_valid = false;
+    return GP_OK_TOL;
 }
 
 int gp_lista_forward(gp_lista net, const float* Y, int64_t ldy, int64_t B, const double* rho, float* X_out,

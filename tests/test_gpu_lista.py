@@ -252,6 +252,30 @@ def test_projected_output_and_warm_start(H):
     net.close()
 
 
+def test_save_and_load(H, tmp_path):
+    say("[lista] weights through a file")
+    n, p, L, B = 70, 150, 3, 20
+    K, Y, Xs = _problem(n, p, B, 5, seed=51)
+    We, S, th = _weights(K, 0.1 * np.abs(K.T @ Y[0]).max(), seed=9)
+    a = _net(H, n, p, L, We, S, _bf(np.full(L, th) * np.array([1.0, 1.1, 1.2])))
+    Yd = _dev(Y)
+    a.train_step(Yd, _dev(Xs), 1e-3)
+    path = str(tmp_path / "net.bin")
+    a.save(path)
+    b = gpl1.Lista(H, n, p, L)
+    b.load(path)
+    for u, v in zip(a.get_weights(), b.get_weights()):
+        assert torch.equal(u, v)
+    assert torch.equal(a.forward(Yd), b.forward(Yd))
+    c = gpl1.Lista(H, n, p + 1, L)
+    with pytest.raises(gpl1.GPError):
+        c.load(path)
+    with pytest.raises(gpl1.GPError):
+        b.load(str(tmp_path / "missing.bin"))
+    for net in (a, b, c):
+        net.close()
+
+
 def test_argument_errors(H):
     say("[lista] argument errors")
     with pytest.raises(gpl1.GPError):
