@@ -8,9 +8,9 @@
 // accuracy.  K^T is a transposed bf16 copy made once per call so that both
 // GEMMs read their left operand with the reduction index contiguous.  An
 // FP32 K is kept as three bf16 planes Kh + Km + Kl as well; a product is then
-// Kh (Dh + Dm + Dl) + Km (Dh + Dm) + Kl Dh, three GEMMs whose partial sums
-// add up with the split-K partials (the dropped plane products are below
-// 2^-24 of the result).
+// Kh (Dh + Dm + Dl) + Km (Dh + Dm) + Kl Dh, formed in one GEMM pass that
+// stages all six planes (the dropped plane products are below 2^-24 of the
+// result).
 //
 // Everything per problem (projection and threshold search, the steplength
 // rule of Algorithm 2, the closed-form Armijo backtracking of Algorithm 1,
@@ -165,8 +165,9 @@ __global__ __launch_bounds__(BS_T) void k_bs_init(BsPtrs P, GPParams prm, const 
 // ---------------------------------------------------------------------------
 // row side: t = sum of the K-products; refresh (r = t - y) or the line search
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(BS_T) void k_bs_rows(BsPtrs P, int mode, int refresh_next) {
-    __shared__ double lds[3 * (BS_T / WAVE)];
+template <int T>
+__global__ __launch_bounds__(T) void k_bs_rows(BsPtrs P, int mode) {
+    __shared__ double lds[3 * (T / WAVE)];
     __shared__ double sh[4];
     const int b = blockIdx.x, tid = threadIdx.x;
     GPState* st = P.st + b;
@@ -184,23 +185,23 @@ __global__ __launch_bounds__(BS_T) void k_bs_rows(BsPtrs P, int mode, int refres
         // first pass with the x0 test: also ||y||^2 = f(0)
         const bool fb = st->prm.x0_fallback && st->k == 0 && st->nhist == 0;
         double acc[2] = {0.0, 0.0}, none[1] = {0.0};
-        for (int64_t i = tid; i < n; i += BS_T) {
+        for (int64_t i = tid; i < n; i += T) {
             const double ri = tval(i) - y[i];
             r[i] = ri;
             acc[0] += ri * ri;
             acc[1] += y[i] * y[i];
             split3(ri, P.Qsp, P.plQ, b * P.npad + i);
         }
-        block_reduce<BS_T, 2, 1>(acc, none, lds);
+        block_reduce<T, 2, 1>(acc, none, lds);
         const bool reject = fb && !(acc[0] < acc[1]);
         if (reject) {
             // P(x0) is no better than 0: start from x = 0, r = -y
-            for (int64_t i = tid; i < n; i += BS_T) {
+            for (int64_t i = tid; i < n; i += T) {
                 r[i] = -y[i];
                 split3(-y[i], P.Qsp, P.plQ, b * P.npad + i);
             }
             double* x = P.X + b * P.p;
-            for (int64_t j = tid; j < P.p; j += BS_T) x[j] = 0.0;
+            for (int64_t j = tid; j < P.p; j += T) x[j] = 0.0;
         }
         if (tid == 0) {
             const double f = reject ? acc[1] : acc[0];
@@ -219,13 +220,13 @@ __global__ __launch_bounds__(BS_T) void k_bs_rows(BsPtrs P, int mode, int refres
     }
     // iteration: q = K d, its dots, the Armijo step, then r, x updates
     double acc[2] = {0.0, 0.0}, none[1] = {0.0};
-    for (int64_t i = tid; i < n; i += BS_T) {
+    for (int64_t i = tid; i < n; i += T) {
         const double qi = tval(i);
         qv[i] = qi;
         acc[0] += qi * qi;
         acc[1] += r[i] * qi;
     }
-    block_reduce<BS_T, 2, 1>(acc, none, lds);
+    block_reduce<T, 2, 1>(acc, none, lds);
     if (tid == 0) {
         const GPParams& Pm = st->prm;
         const double qq = acc[0], rq = acc[1], f = st->f, gd = st->gd;
@@ -271,30 +272,29 @@ __global__ __launch_bounds__(BS_T) void k_bs_rows(BsPtrs P, int mode, int refres
     __syncthreads();
     if (sh[1] != 0.0) return;
     const double lam = sh[0];
-    for (int64_t i = tid; i < n; i += BS_T) {
+    for (int64_t i = tid; i < n; i += T) {
         const double qi = qv[i];
         r[i] += lam * qi;
         split3(qi, P.Qsp, P.plQ, b * P.npad + i);
     }
-    double* x = P.X + b * p;
-    double* hd = P.H + b * p;       // holds h on entry, d on exit
-    for (int64_t j = tid; j < p; j += BS_T) {
-        const double xj = x[j];
-        const double dj = hd[j] - xj;
-        const double xn = xj + lam * dj;
-        x[j] = xn;
-        hd[j] = dj;
-        if (refresh_next) split3(xn, P.Dsp, P.plD, b * P.ppad + j);
-    }
+    // the p-space part of the step (x += lam d) is applied by the column
+    // kernel, which reads x anyway
 }
 
 // ---------------------------------------------------------------------------
-// column side: gradient update from W = K^T Q, steplength rule, projection,
-// direction d = P(x - alpha g) - x and its dots, d split for the next K D
+// column side: the accepted step (x += lam d with d = h - x, g += 2 lam w from
+// W = K^T Q), the steplength rule, the projection, the next direction
+// d = P(x - alpha g) - x and its dots, d split for the next K D.  Every
+// thread keeps its elements of x and g in registers (pairs of neighbours), so
+// each vector is read and written once per iteration.
+// Modes: BC_INIT (g = 2 W at x0, then alpha_0 and the first projection);
+// BC_ITER (step, rule, projection); BC_ITER_NOPROJ (step and rule only, x
+// split for the residual refresh that follows); BC_REFRESH_PROJ (g = 2 W at
+// the current x, then the projection).
 // ---------------------------------------------------------------------------
-template <int NV>
-__global__ __launch_bounds__(BS_T) void k_bs_cols(BsPtrs P, int mode) {
-    __shared__ double lds[3 * (BS_T / WAVE)];
+template <int T, int NV>
+__global__ __launch_bounds__(T) void k_bs_cols(BsPtrs P, int mode) {
+    __shared__ double lds[3 * (T / WAVE)];
     __shared__ double sh[4];
     const int b = blockIdx.x, tid = threadIdx.x;
     GPState* st = P.st + b;
@@ -302,32 +302,75 @@ __global__ __launch_bounds__(BS_T) void k_bs_cols(BsPtrs P, int mode) {
     double* x = P.X + b * p;
     double* g = P.G + b * p;
     double* hd = P.H + b * p;
-    const int need_ss = (mode == BC_ITER || mode == BC_ITER_NOPROJ) ? st->ss_pending : 0;
+    const bool iter = mode == BC_ITER || mode == BC_ITER_NOPROJ;
+    const int step_pending = iter ? st->ss_pending : 0;
     const int col_done = P.done[b];
-    if (col_done && !need_ss) return;
+    if (col_done && !step_pending) return;
     auto wval = [&](int64_t j) {
-        double s = 0.0;
-        for (int c = 0; c < P.S2; ++c) s += (double)P.Wpart[c * P.sW + b * P.ppad + j];
-        return s;
+        double sw = 0.0;
+        for (int c = 0; c < P.S2; ++c) sw += (double)P.Wpart[c * P.sW + b * P.ppad + j];
+        return sw;
     };
-    if (mode == BC_INIT || mode == BC_REFRESH_PROJ) {
-        for (int64_t j = tid; j < p; j += BS_T) g[j] = 2.0 * wval(j);
-    } else if (need_ss) {
+    // slot e <-> element j = 2*((e/2)*T + tid) + (e&1)
+    double xr[NV], gr[NV];
+    if (step_pending) {
         const double lam = st->lam;
         double acc[2] = {0.0, 0.0}, none[1] = {0.0};
-        for (int64_t j = tid; j < p; j += BS_T) {
-            const double w = wval(j);
-            g[j] += 2.0 * lam * w;
-            acc[0] += hd[j] * w;     // d'w
-            acc[1] += w * w;         // w'w
+#pragma unroll
+        for (int e = 0; e < NV; e += 2) {
+            const int64_t j = 2 * ((e / 2) * T + tid);
+            double xo[2] = {0.0, 0.0}, go[2] = {0.0, 0.0}, ho[2] = {0.0, 0.0}, w[2] = {0.0, 0.0};
+            if (j + 1 < p) {      // 16-byte loads for the pair
+                const double2 x2 = *reinterpret_cast<const double2*>(x + j);
+                const double2 g2 = *reinterpret_cast<const double2*>(g + j);
+                const double2 h2 = *reinterpret_cast<const double2*>(hd + j);
+                xo[0] = x2.x; xo[1] = x2.y; go[0] = g2.x; go[1] = g2.y; ho[0] = h2.x; ho[1] = h2.y;
+                w[0] = wval(j);
+                w[1] = wval(j + 1);
+            } else if (j < p) {
+                xo[0] = x[j]; go[0] = g[j]; ho[0] = hd[j];
+                w[0] = wval(j);
+            }
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const double dj = ho[u] - xo[u];                 // hd holds the last h
+                xr[e + u] = xo[u] + lam * dj;
+                gr[e + u] = go[u] + 2.0 * lam * w[u];
+                acc[0] += dj * w[u];                             // d'w
+                acc[1] += w[u] * w[u];                           // w'w
+            }
         }
-        block_reduce<BS_T, 2, 1>(acc, none, lds);
+        block_reduce<T, 2, 1>(acc, none, lds);
         if (tid == 0) {
             // s = lam d, z = 2 lam w: s's = lam^2 d'd, s'z = 2 lam^2 d'w,
             // z'z = 4 lam^2 w'w (equation (5)), then Algorithm 2
             const double l2 = lam * lam;
             ss_update(st, st->k, l2 * st->dd, 2.0 * l2 * acc[0], 4.0 * l2 * acc[1]);
             st->ss_pending = 0;
+        }
+#pragma unroll
+        for (int e = 0; e < NV; e += 2) {
+            const int64_t j = 2 * ((e / 2) * T + tid);
+            if (j + 1 < p) {
+                *reinterpret_cast<double2*>(x + j) = make_double2(xr[e], xr[e + 1]);
+                *reinterpret_cast<double2*>(g + j) = make_double2(gr[e], gr[e + 1]);
+            } else if (j < p) {
+                x[j] = xr[e];
+                g[j] = gr[e];
+            }
+            if (mode == BC_ITER_NOPROJ) {
+                if (j < p) split3(xr[e], P.Dsp, P.plD, b * P.ppad + j);
+                if (j + 1 < p) split3(xr[e + 1], P.Dsp, P.plD, b * P.ppad + j + 1);
+            }
+        }
+    } else {
+        // BC_INIT / BC_REFRESH_PROJ: fresh gradient at the current x
+#pragma unroll
+        for (int e = 0; e < NV; ++e) {
+            const int64_t j = 2 * ((e / 2) * T + tid) + (e & 1);
+            xr[e] = j < p ? x[j] : 0.0;
+            gr[e] = j < p ? 2.0 * wval(j) : 0.0;
+            if (j < p) g[j] = gr[e];
         }
     }
     if (col_done || mode == BC_ITER_NOPROJ) return;
@@ -343,15 +386,12 @@ __global__ __launch_bounds__(BS_T) void k_bs_cols(BsPtrs P, int mode) {
     if (mode == BC_INIT) {
         // alpha_0 = max{alpha_min, min{1/||P(x0 - grad f(x0))||_inf, alpha_max}}
 #pragma unroll
-        for (int e = 0; e < NV; ++e) {
-            const int j = 2 * ((e / 2) * BS_T + tid) + (e & 1);
-            vr[e] = j < p ? x[j] - g[j] : 0.0;
-        }
-        l1_threshold_regs<BS_T, NV>(vr, p, rho, -1.0, lds, m, t, inside, passes);
+        for (int e = 0; e < NV; ++e) vr[e] = xr[e] - gr[e];
+        l1_threshold_regs<T, NV>(vr, p, rho, -1.0, lds, m, t, inside, passes);
         double hm = 0.0;
 #pragma unroll
         for (int e = 0; e < NV; ++e) hm = fmax(hm, fabs(l1_hval(vr[e], m, t, inside, rho)));
-        hm = block_max<BS_T>(hm, lds);
+        hm = block_max<T>(hm, lds);
         alpha = hm > 0.0 ? clamp_alpha(1.0 / hm, st->prm) : st->prm.amax;
         __syncthreads();
         if (tid == 0) st->alpha = alpha;
@@ -360,33 +400,29 @@ __global__ __launch_bounds__(BS_T) void k_bs_cols(BsPtrs P, int mode) {
     }
     const double mu_prev = mode == BC_INIT ? 0.0 : sh[1];
 #pragma unroll
-    for (int e = 0; e < NV; ++e) {
-        const int j = 2 * ((e / 2) * BS_T + tid) + (e & 1);
-        vr[e] = j < p ? x[j] - alpha * g[j] : 0.0;
-    }
+    for (int e = 0; e < NV; ++e) vr[e] = xr[e] - alpha * gr[e];
     // warm start from the previous threshold when it lies below max|v|
     double mloc = 0.0;
 #pragma unroll
     for (int e = 0; e < NV; ++e) mloc = fmax(mloc, fabs(vr[e]));
-    mloc = block_max<BS_T>(mloc, lds);
+    mloc = block_max<T>(mloc, lds);
     const double start = (mu_prev > 0.0 && mu_prev < mloc) ? mu_prev - mloc : -1.0;
-    l1_threshold_regs<BS_T, NV>(vr, p, rho, start, lds, m, t, inside, passes);
+    l1_threshold_regs<T, NV>(vr, p, rho, start, lds, m, t, inside, passes);
     double sums[2] = {0.0, 0.0}, mx[1] = {0.0};
 #pragma unroll
     for (int e = 0; e < NV; ++e) {
-        const int j = 2 * ((e / 2) * BS_T + tid) + (e & 1);
+        const int64_t j = 2 * ((e / 2) * T + tid) + (e & 1);
         if (j < p) {
             const double h = l1_hval(vr[e], m, t, inside, rho);
-            const double xj = x[j];
-            const double dj = h - xj;
+            const double dj = h - xr[e];
             hd[j] = h;
             split3(dj, P.Dsp, P.plD, b * P.ppad + j);
-            sums[0] += g[j] * dj;
+            sums[0] += gr[e] * dj;
             sums[1] += dj * dj;
             mx[0] = fmax(mx[0], fabs(dj));
         }
     }
-    block_reduce<BS_T, 2, 1>(sums, mx, lds);
+    block_reduce<T, 2, 1>(sums, mx, lds);
     if (tid == 0) {
         if (!isfinite(m)) { st->status = ST_NONFINITE; st->done = 1; P.done[b] = 1; return; }
         st->gd = sums[0];
@@ -421,6 +457,24 @@ __global__ __launch_bounds__(BS_T) void k_bs_finish(BsPtrs P, void* __restrict__
 
 namespace {
 
+// Column-kernel shape: the fewest threads (256, 512 or 1024) that hold p in
+// at most 16 register slots each, so that several problems share a CU and
+// one problem's reductions overlap another's loads.
+int bs_cols_t(int64_t p) {
+    if ((p + 255) / 256 <= 16) return 256;
+    if ((p + 511) / 512 <= 16) return 512;
+    return 1024;
+}
+
+int bs_nv_t(int64_t p, int T) {
+    const int64_t per = (p + T - 1) / T;
+    if (per <= 2) return 2;
+    if (per <= 4) return 4;
+    if (per <= 8) return 8;
+    if (per <= 16) return 16;
+    return 0;
+}
+
 int bs_nv(int64_t p) {
     const int64_t per = (p + BS_T - 1) / BS_T;
     if (per <= 2) return 2;
@@ -437,6 +491,14 @@ int bs_nv(int64_t p) {
         case 8: { constexpr int NVc = 8; STMT; } break;   \
         case 16: { constexpr int NVc = 16; STMT; } break; \
     }
+
+void launch_cols(int T, int nv, int64_t B, hipStream_t s, const BsPtrs& P, int mode) {
+#define GPL1_BS_COLS(TT, NN) \
+    if (T == TT && nv == NN) { hipLaunchKernelGGL((k_bs_cols<TT, NN>), dim3((unsigned)B), dim3(TT), 0, s, P, mode); return; }
+    GPL1_BS_COLS(256, 2) GPL1_BS_COLS(256, 4) GPL1_BS_COLS(256, 8) GPL1_BS_COLS(256, 16)
+    GPL1_BS_COLS(512, 16) GPL1_BS_COLS(1024, 16)
+#undef GPL1_BS_COLS
+}
 
 int64_t rup(int64_t a, int64_t m) { return (a + m - 1) / m * m; }
 
@@ -458,6 +520,7 @@ int solve_batched_shared_mfma(gp_handle h, gp_dtype kdtype, const void* K, int64
     if (kdtype != GP_BF16 && kdtype != GP_F32) return GP_E_UNSUPPORTED;
     const int nK = kdtype == GP_F32 ? 3 : 1;   // bf16 planes of K
     const int nv = bs_nv(p);
+    const int ct = bs_cols_t(p), cnv = bs_nv_t(p, ct);
     if (nv == 0 || B > (1 << 20)) return GP_E_UNSUPPORTED;
     const int64_t npad = rup(n, BS_PAD), ppad = rup(p, BS_PAD), bpad = rup(B, BS_PAD);
     // split-K chunks of about 1024 (multiples of 32) per GEMM
@@ -477,7 +540,7 @@ int solve_batched_shared_mfma(gp_handle h, gp_dtype kdtype, const void* K, int64
     const size_t o_R = take(8 * B * n), o_Y = take(8 * B * n), o_Qv = take(8 * B * n);
     const size_t o_Kp = take(2 * nK * kpl), o_Kt = take(2 * nK * kpl);
     const size_t o_Dsp = take(2 * NSPL * bpad * ppad), o_Qsp = take(2 * NSPL * bpad * npad);
-    const size_t o_Qp = take(4 * (size_t)S1 * nK * bpad * npad), o_Wp = take(4 * (size_t)S2 * nK * bpad * ppad);
+    const size_t o_Qp = take(4 * (size_t)S1 * bpad * npad), o_Wp = take(4 * (size_t)S2 * bpad * ppad);
     const size_t o_rho = take(8 * B), o_ft = take(8 * B);
     int rc = ensure_workspace(h, off);
     if (rc) return rc;
@@ -495,7 +558,7 @@ int solve_batched_shared_mfma(gp_handle h, gp_dtype kdtype, const void* K, int64
     P.Qpart = Qpart; P.Wpart = Wpart;
     P.n = n; P.p = p; P.npad = npad; P.ppad = ppad;
     P.plD = bpad * ppad; P.plQ = bpad * npad;
-    P.S1 = S1 * nK; P.S2 = S2 * nK;          // partial planes: split-K chunks x K planes
+    P.S1 = S1; P.S2 = S2;
     P.sQ = bpad * npad; P.sW = bpad * ppad;
     double* drho = (double*)(ws + o_rho);
     double* dft = o.f_targets ? (double*)(ws + o_ft) : nullptr;
@@ -517,20 +580,16 @@ int solve_batched_shared_mfma(gp_handle h, gp_dtype kdtype, const void* K, int64
     const int f64v = 0;
     GPL1_BS_NV_SWITCH(nv, hipLaunchKernelGGL(k_bs_init<NVc>, dim3((unsigned)B), dim3(BS_T), 0, s, P, prm, drho,
                                              dft, Y, ldy, X0, ldx, f64v));
-    // one GEMM per K plane a: A = plane a, right operand = its first 3 - a
-    // planes (all three for a bf16 K), partials after those of plane a - 1
+    // bf16 K: one plane times the three planes of the right operand; FP32 K:
+    // the six plane products of k_gemm_bf16_planes<3, 3> in one pass
     auto gemm_planes = [&](const uint16_t* A0, int64_t lda, int64_t M, const uint16_t* Bpl, int64_t ldb,
                            int64_t plB, int S, int64_t kc, float* Cp, int64_t ldc, int64_t cs) {
-        for (int a = 0; a < nK; ++a) {
-            const dim3 grid((unsigned)(M / GM_BM), (unsigned)(bpad / GM_BN), (unsigned)S);
-            const uint16_t* A = A0 + a * kpl;
-            float* C = Cp + (int64_t)a * S * cs;
-            switch (nK == 1 ? NSPL : NSPL - a) {
-                case 3: hipLaunchKernelGGL(k_gemm_bf16<3>, grid, dim3(GM_T), 0, s, A, lda, Bpl, ldb, plB, (int)kc, C, ldc, cs); break;
-                case 2: hipLaunchKernelGGL(k_gemm_bf16<2>, grid, dim3(GM_T), 0, s, A, lda, Bpl, ldb, plB, (int)kc, C, ldc, cs); break;
-                default: hipLaunchKernelGGL(k_gemm_bf16<1>, grid, dim3(GM_T), 0, s, A, lda, Bpl, ldb, plB, (int)kc, C, ldc, cs); break;
-            }
-        }
+        const dim3 grid((unsigned)(M / GM_BM), (unsigned)(bpad / GM_BN), (unsigned)S);
+        if (nK == 1)
+            hipLaunchKernelGGL(k_gemm_bf16<NSPL>, grid, dim3(GM_T), 0, s, A0, lda, Bpl, ldb, plB, (int)kc, Cp, ldc, cs);
+        else
+            hipLaunchKernelGGL((k_gemm_bf16_planes<3, 3>), grid, dim3(GM_T), 0, s, A0, lda, kpl, Bpl, ldb, plB,
+                               (int)kc, Cp, ldc, cs);
     };
     auto gemm1 = [&]() {   // Qpart = K * (Dsp planes)
         gemm_planes(Kp, ppad, npad, P.Dsp, ppad, P.plD, S1, kc1, Qpart, npad, P.sQ);
@@ -538,15 +597,15 @@ int solve_batched_shared_mfma(gp_handle h, gp_dtype kdtype, const void* K, int64
     auto gemm2 = [&]() {   // Wpart = K^T * (Qsp planes)
         gemm_planes(Kt, npad, ppad, P.Qsp, npad, P.plQ, S2, kc2, Wpart, ppad, P.sW);
     };
-    auto rows = [&](int mode, int refresh_next) {
-        hipLaunchKernelGGL(k_bs_rows, dim3((unsigned)B), dim3(BS_T), 0, s, P, mode, refresh_next);
+    auto rows = [&](int mode) {
+        hipLaunchKernelGGL(k_bs_rows<256>, dim3((unsigned)B), dim3(256), 0, s, P, mode);
     };
     auto cols = [&](int mode) {
-        GPL1_BS_NV_SWITCH(nv, hipLaunchKernelGGL(k_bs_cols<NVc>, dim3((unsigned)B), dim3(BS_T), 0, s, P, mode));
+        launch_cols(ct, cnv, B, s, P, mode);
     };
     // r = K x - y, g = 2 K^T r, alpha_0, first direction
     gemm1();
-    rows(BR_REFRESH, 0);
+    rows(BR_REFRESH);
     gemm2();
     cols(BC_INIT);
     e = hipGetLastError();
@@ -559,12 +618,12 @@ int solve_batched_shared_mfma(gp_handle h, gp_dtype kdtype, const void* K, int64
         for (; it < end; ++it) {
             const bool refresh = o.refresh_every > 0 && (it + 1) % o.refresh_every == 0 && it + 1 < o.max_iter;
             gemm1();
-            rows(BR_ITER, refresh ? 1 : 0);
+            rows(BR_ITER);
             gemm2();
             if (refresh) {
                 cols(BC_ITER_NOPROJ);
                 gemm1();
-                rows(BR_REFRESH, 0);
+                rows(BR_REFRESH);
                 gemm2();
                 cols(BC_REFRESH_PROJ);
             } else {

@@ -145,4 +145,144 @@ __global__ __launch_bounds__(GM_T) void k_gemm_bf16(const uint16_t* __restrict__
 #undef GPL1_ST
 }
 
+// Both operands as bf16 planes: A = sum_a A_a (NA planes, stride apstride),
+// B = sum_t B_t (NB planes), and only the plane products with a + t < NB are
+// formed: for NA = NB = 3 that is A_h (B_h + B_m + B_l) + A_m (B_h + B_m) +
+// A_l B_h, an FP32-accurate product of two FP32 matrices (the dropped plane
+// products are below 2^-24 of the result) in one pass that stages every
+// plane once.  Same tiling, padding rules and output layout as k_gemm_bf16.
+// LDS holds the (NA + NB) tiles of one k-step (60 KiB for 3 + 3, so two
+// workgroups fit a CU); the next step waits in registers, two barriers a step.
+template <int NA, int NB>
+__global__ __launch_bounds__(GM_T) void k_gemm_bf16_planes(const uint16_t* __restrict__ A, int64_t lda,
+                                                           int64_t apstride, const uint16_t* __restrict__ Bp,
+                                                           int64_t ldb, int64_t bpstride, int kchunk,
+                                                           float* __restrict__ Cpart, int64_t ldc,
+                                                           int64_t cstride) {
+    static_assert(NA >= 1 && NA <= 3 && NB >= 1 && NB <= 3 && NA <= NB, "one to three planes each");
+    constexpr int TILE = GM_BM * GM_LDS_ROW;
+    constexpr int NT = NA + NB;
+    __shared__ __attribute__((aligned(16))) uint16_t lds[1][NT * TILE];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave & 1, wn = wave >> 1;
+    const int64_t m0 = (int64_t)blockIdx.x * GM_BM;
+    const int64_t n0 = (int64_t)blockIdx.y * GM_BN;
+    const int64_t k_begin = (int64_t)blockIdx.z * kchunk;
+    const int nsteps = kchunk / GM_BK;
+
+    // two 16-byte chunks per thread per tile (rows row0_/row1_, k offsets kc0_/kc1_)
+    const int c0_ = tid, c1_ = tid + GM_T;
+    const int row0_ = c0_ >> 2, kc0_ = (c0_ & 3) * 8, row1_ = c1_ >> 2, kc1_ = (c1_ & 3) * 8;
+    const uint16_t* a0p = A + (m0 + row0_) * lda + k_begin + kc0_;
+    const uint16_t* a1p = A + (m0 + row1_) * lda + k_begin + kc1_;
+    const uint16_t* b0p = Bp + (n0 + row0_) * ldb + k_begin + kc0_;
+    const uint16_t* b1p = Bp + (n0 + row1_) * ldb + k_begin + kc1_;
+    // staging registers for the next k-step (its loads are in flight while
+    // the current step is multiplied), named one by one so that they stay in
+    // VGPRs
+    uint4 r0a00, r0a01, r0a10, r0a11, r0a20, r0a21, r0b00, r0b01, r0b10, r0b11, r0b20, r0b21;
+#define GPL1_PL_LD(p_, off_) (*reinterpret_cast<const uint4*>((p_) + (off_)))
+#define GPL1_PL_GLOAD(S_, step_)                                                \
+    {                                                                           \
+        const int64_t ko_ = (int64_t)(step_) * GM_BK;                           \
+        S_##a00 = GPL1_PL_LD(a0p, ko_);                                         \
+        S_##a01 = GPL1_PL_LD(a1p, ko_);                                         \
+        if constexpr (NA > 1) {                                                 \
+            S_##a10 = GPL1_PL_LD(a0p, apstride + ko_);                          \
+            S_##a11 = GPL1_PL_LD(a1p, apstride + ko_);                          \
+        }                                                                       \
+        if constexpr (NA > 2) {                                                 \
+            S_##a20 = GPL1_PL_LD(a0p, 2 * apstride + ko_);                      \
+            S_##a21 = GPL1_PL_LD(a1p, 2 * apstride + ko_);                      \
+        }                                                                       \
+        S_##b00 = GPL1_PL_LD(b0p, ko_);                                         \
+        S_##b01 = GPL1_PL_LD(b1p, ko_);                                         \
+        if constexpr (NB > 1) {                                                 \
+            S_##b10 = GPL1_PL_LD(b0p, bpstride + ko_);                          \
+            S_##b11 = GPL1_PL_LD(b1p, bpstride + ko_);                          \
+        }                                                                       \
+        if constexpr (NB > 2) {                                                 \
+            S_##b20 = GPL1_PL_LD(b0p, 2 * bpstride + ko_);                      \
+            S_##b21 = GPL1_PL_LD(b1p, 2 * bpstride + ko_);                      \
+        }                                                                       \
+    }
+#define GPL1_PL_ST(u_, row_, kc_, v_) \
+    (*reinterpret_cast<uint4*>(&lds[0][(u_) * TILE + (row_) * GM_LDS_ROW + (kc_)]) = (v_))
+#define GPL1_PL_LSTORE(S_)                                                      \
+    {                                                                           \
+        GPL1_PL_ST(0, row0_, kc0_, S_##a00);                                    \
+        GPL1_PL_ST(0, row1_, kc1_, S_##a01);                                    \
+        if constexpr (NA > 1) {                                                 \
+            GPL1_PL_ST(1, row0_, kc0_, S_##a10);                                \
+            GPL1_PL_ST(1, row1_, kc1_, S_##a11);                                \
+        }                                                                       \
+        if constexpr (NA > 2) {                                                 \
+            GPL1_PL_ST(2, row0_, kc0_, S_##a20);                                \
+            GPL1_PL_ST(2, row1_, kc1_, S_##a21);                                \
+        }                                                                       \
+        GPL1_PL_ST(NA, row0_, kc0_, S_##b00);                                   \
+        GPL1_PL_ST(NA, row1_, kc1_, S_##b01);                                   \
+        if constexpr (NB > 1) {                                                 \
+            GPL1_PL_ST(NA + 1, row0_, kc0_, S_##b10);                           \
+            GPL1_PL_ST(NA + 1, row1_, kc1_, S_##b11);                           \
+        }                                                                       \
+        if constexpr (NB > 2) {                                                 \
+            GPL1_PL_ST(NA + 2, row0_, kc0_, S_##b20);                           \
+            GPL1_PL_ST(NA + 2, row1_, kc1_, S_##b21);                           \
+        }                                                                       \
+    }
+    // one k-step on the tiles in LDS
+#define GPL1_PL_COMPUTE()                                                       \
+    {                                                                           \
+        _Pragma("unroll") for (int a = 0; a < NA; ++a) {                        \
+            bf16x8_t af[4];                                                     \
+            _Pragma("unroll") for (int i = 0; i < 4; ++i)                       \
+                af[i] = *reinterpret_cast<const bf16x8_t*>(                     \
+                    &lds[0][a * TILE + (wm * 64 + i * 16 + fr) * GM_LDS_ROW + fk]); \
+            _Pragma("unroll") for (int t = 0; t + a < NB; ++t)                  \
+            _Pragma("unroll") for (int j = 0; j < 4; ++j) {                     \
+                const bf16x8_t bfr = *reinterpret_cast<const bf16x8_t*>(        \
+                    &lds[0][(NA + t) * TILE + (wn * 64 + j * 16 + fr) * GM_LDS_ROW + fk]); \
+                _Pragma("unroll") for (int i = 0; i < 4; ++i)                   \
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr, acc[i][j], 0, 0, 0); \
+            }                                                                   \
+        }                                                                       \
+    }
+
+    f32x4_t acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+
+    const int fr = lane & 15, fk = (lane >> 4) * 8;
+    GPL1_PL_GLOAD(r0, 0)
+    GPL1_PL_LSTORE(r0)
+    __syncthreads();
+    for (int step = 0; step < nsteps; ++step) {
+        if (step + 1 < nsteps) GPL1_PL_GLOAD(r0, step + 1)
+        GPL1_PL_COMPUTE()
+        if (step + 1 < nsteps) {
+            __syncthreads();          // every wave is done reading this step's tiles
+            GPL1_PL_LSTORE(r0)
+            __syncthreads();
+        }
+    }
+    float* out = Cpart + (int64_t)blockIdx.z * cstride;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int64_t m = m0 + wm * 64 + i * 16 + (lane >> 4) * 4;
+            const int64_t nn = n0 + wn * 64 + j * 16 + (lane & 15);
+            *reinterpret_cast<float4*>(out + nn * ldc + m) =
+                make_float4(acc[i][j][0], acc[i][j][1], acc[i][j][2], acc[i][j][3]);
+        }
+#undef GPL1_PL_GLOAD
+#undef GPL1_PL_LSTORE
+#undef GPL1_PL_LD
+#undef GPL1_PL_ST
+#undef GPL1_PL_COMPUTE
+}
+
 }  // namespace gpl1
