@@ -122,7 +122,7 @@ def forms_legs(H, inst, np, torch, gpl1, instances, out):
     batch = instances.shared_rhs(seed=5, dtype="bf16")
     Ks = torch.from_numpy(batch.K_store.view(np.int16)).to(dev)
     Y = torch.from_numpy(batch.Y_store).to(dev)
-    kw = dict(tol=1e-10, max_iter=5000, refresh_every=REFRESH)
+    kw = dict(tol=1e-10, max_iter=5000, refresh_every=REFRESH, chunk=8)
     H.solve_batched_shared(Ks, Y, batch.rho, **kw)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -134,7 +134,8 @@ def forms_legs(H, inst, np, torch, gpl1, instances, out):
     t0 = time.perf_counter()
     pits = 0
     for b in range(8):
-        _, r1 = H.solve(Ks, Y[b].contiguous(), float(batch.rho[b]), **kw)
+        _, r1 = H.solve(Ks, Y[b].contiguous(), float(batch.rho[b]), tol=1e-10, max_iter=5000,
+                        refresh_every=REFRESH)
         pits += r1["iters"]
     torch.cuda.synchronize()
     tpl = (time.perf_counter() - t0) / 8
@@ -275,7 +276,8 @@ def learned_leg(H, np, torch, gpl1, instances, ntrain, neval, epochs, batch=256,
     log(f"learned leg: {ntrain} training and {neval} evaluation right-hand sides drawn "
         f"({time.time() - t0:.1f}s)")
     CH = 2048
-    kw = dict(refresh_every=REFRESH)
+    # batched calls poll every 8 iterations: finished problems leave the launches
+    kw = dict(refresh_every=REFRESH, chunk=8)
 
     # 1. training targets from the batched solver (matrix cores, FP32 K as bf16 planes)
     Ytr = torch.from_numpy(tr.Y).to(dev)
@@ -384,13 +386,15 @@ def learned_leg(H, np, torch, gpl1, instances, ntrain, neval, epochs, batch=256,
     raw_err_train = float(np.mean(np.linalg.norm(Xrt - Xt0, axis=1) / np.linalg.norm(Xt0, axis=1)))
     # plain solver, one problem at a time, on a sample
     sample = list(range(0, neval, max(1, neval // 32)))[:32]
-    H.solve(Kd, Yev[0], float(ev.rho[0]), tol=0.0, f_target=float(targets[0]), max_iter=20000, **kw)
+    # (its own default host-poll interval: one poll per 64 iterations)
+    H.solve(Kd, Yev[0], float(ev.rho[0]), tol=0.0, f_target=float(targets[0]), max_iter=20000,
+            refresh_every=REFRESH)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     pits = []
     for b in sample:
         _, r = H.solve(Kd, Yev[b], float(ev.rho[b]), tol=0.0, f_target=float(targets[b]),
-                       max_iter=20000, **kw)
+                       max_iter=20000, refresh_every=REFRESH)
         pits.append(r["iters"])
     torch.cuda.synchronize()
     tp = (time.perf_counter() - t0) / len(sample)

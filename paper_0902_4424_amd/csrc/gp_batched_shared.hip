@@ -108,6 +108,7 @@ struct BsPtrs {
     int64_t n, p, npad, ppad, plD, plQ;       // plane strides of Dsp / Qsp
     int S1, S2;                               // split-K chunks of the two GEMMs
     int64_t sQ, sW;                           // partial strides (elements)
+    const int32_t* list;                      // problems of the launch's workgroups (NULL: 0..B-1)
 };
 
 // ---------------------------------------------------------------------------
@@ -169,7 +170,7 @@ template <int T>
 __global__ __launch_bounds__(T) void k_bs_rows(BsPtrs P, int mode) {
     __shared__ double lds[3 * (T / WAVE)];
     __shared__ double sh[4];
-    const int b = blockIdx.x, tid = threadIdx.x;
+    const int b = P.list ? P.list[blockIdx.x] : (int)blockIdx.x, tid = threadIdx.x;
     GPState* st = P.st + b;
     if (P.done[b]) return;
     const int64_t n = P.n, p = P.p;
@@ -296,7 +297,7 @@ template <int T, int NV>
 __global__ __launch_bounds__(T) void k_bs_cols(BsPtrs P, int mode) {
     __shared__ double lds[3 * (T / WAVE)];
     __shared__ double sh[4];
-    const int b = blockIdx.x, tid = threadIdx.x;
+    const int b = P.list ? P.list[blockIdx.x] : (int)blockIdx.x, tid = threadIdx.x;
     GPState* st = P.st + b;
     const int64_t p = P.p;
     double* x = P.X + b * p;
@@ -539,9 +540,12 @@ int solve_batched_shared_mfma(gp_handle h, gp_dtype kdtype, const void* K, int64
     const size_t o_X = take(8 * B * p), o_G = take(8 * B * p), o_H = take(8 * B * p);
     const size_t o_R = take(8 * B * n), o_Y = take(8 * B * n), o_Qv = take(8 * B * n);
     const size_t o_Kp = take(2 * nK * kpl), o_Kt = take(2 * nK * kpl);
-    const size_t o_Dsp = take(2 * NSPL * bpad * ppad), o_Qsp = take(2 * NSPL * bpad * npad);
-    const size_t o_Qp = take(4 * (size_t)S1 * bpad * npad), o_Wp = take(4 * (size_t)S2 * bpad * ppad);
-    const size_t o_rho = take(8 * B), o_ft = take(8 * B);
+    // GEMM right operands and outputs get one extra row (index bpad) that
+    // stays zero: the column list of a compacted batch is padded with it
+    const int64_t brows = bpad + 1;
+    const size_t o_Dsp = take(2 * NSPL * brows * ppad), o_Qsp = take(2 * NSPL * brows * npad);
+    const size_t o_Qp = take(4 * (size_t)S1 * brows * npad), o_Wp = take(4 * (size_t)S2 * brows * ppad);
+    const size_t o_rho = take(8 * B), o_ft = take(8 * B), o_list = take(4 * bpad);
     int rc = ensure_workspace(h, off);
     if (rc) return rc;
     char* ws = (char*)h->ws;
@@ -557,17 +561,19 @@ int solve_batched_shared_mfma(gp_handle h, gp_dtype kdtype, const void* K, int64
     float* Wpart = (float*)(ws + o_Wp);
     P.Qpart = Qpart; P.Wpart = Wpart;
     P.n = n; P.p = p; P.npad = npad; P.ppad = ppad;
-    P.plD = bpad * ppad; P.plQ = bpad * npad;
+    P.plD = brows * ppad; P.plQ = brows * npad;
     P.S1 = S1; P.S2 = S2;
-    P.sQ = bpad * npad; P.sW = bpad * ppad;
+    P.sQ = brows * npad; P.sW = brows * ppad;
+    P.list = nullptr;
+    int32_t* dlist = (int32_t*)(ws + o_list);
     double* drho = (double*)(ws + o_rho);
     double* dft = o.f_targets ? (double*)(ws + o_ft) : nullptr;
 
     hipError_t e = hipMemcpyAsync(drho, rho, 8 * B, hipMemcpyHostToDevice, s);
     if (e == hipSuccess && dft) e = hipMemcpyAsync(dft, o.f_targets, 8 * B, hipMemcpyHostToDevice, s);
     // zero padding of the GEMM operands (rows beyond n, p and columns beyond B)
-    if (e == hipSuccess) e = hipMemsetAsync(P.Dsp, 0, 2 * NSPL * bpad * ppad, s);
-    if (e == hipSuccess) e = hipMemsetAsync(P.Qsp, 0, 2 * NSPL * bpad * npad, s);
+    if (e == hipSuccess) e = hipMemsetAsync(P.Dsp, 0, 2 * NSPL * brows * ppad, s);
+    if (e == hipSuccess) e = hipMemsetAsync(P.Qsp, 0, 2 * NSPL * brows * npad, s);
     if (e != hipSuccess) return hip_fail(h, e, "batched set-up");
     if (nK == 1)
         hipLaunchKernelGGL(k_bs_pack, dim3((unsigned)(ppad / 64), (unsigned)(npad / 64)), dim3(256), 0, s,
@@ -582,14 +588,19 @@ int solve_batched_shared_mfma(gp_handle h, gp_dtype kdtype, const void* K, int64
                                              dft, Y, ldy, X0, ldx, f64v));
     // bf16 K: one plane times the three planes of the right operand; FP32 K:
     // the six plane products of k_gemm_bf16_planes<3, 3> in one pass
+    // Active set: after each status poll the problems still running are
+    // listed (padded to the tile with the zero row), and the GEMMs and the
+    // per-problem kernels cover only them.
+    int64_t live = B;
     auto gemm_planes = [&](const uint16_t* A0, int64_t lda, int64_t M, const uint16_t* Bpl, int64_t ldb,
                            int64_t plB, int S, int64_t kc, float* Cp, int64_t ldc, int64_t cs) {
-        const dim3 grid((unsigned)(M / GM_BM), (unsigned)(bpad / GM_BN), (unsigned)S);
+        const dim3 grid((unsigned)(M / GM_BM), (unsigned)(rup(live, GM_BN) / GM_BN), (unsigned)S);
         if (nK == 1)
-            hipLaunchKernelGGL(k_gemm_bf16<NSPL>, grid, dim3(GM_T), 0, s, A0, lda, Bpl, ldb, plB, (int)kc, Cp, ldc, cs);
+            hipLaunchKernelGGL(k_gemm_bf16<NSPL>, grid, dim3(GM_T), 0, s, A0, lda, Bpl, ldb, plB, (int)kc, Cp, ldc, cs,
+                               P.list);
         else
             hipLaunchKernelGGL((k_gemm_bf16_planes<3, 3>), grid, dim3(GM_T), 0, s, A0, lda, kpl, Bpl, ldb, plB,
-                               (int)kc, Cp, ldc, cs);
+                               (int)kc, Cp, ldc, cs, P.list);
     };
     auto gemm1 = [&]() {   // Qpart = K * (Dsp planes)
         gemm_planes(Kp, ppad, npad, P.Dsp, ppad, P.plD, S1, kc1, Qpart, npad, P.sQ);
@@ -598,10 +609,10 @@ int solve_batched_shared_mfma(gp_handle h, gp_dtype kdtype, const void* K, int64
         gemm_planes(Kt, npad, ppad, P.Qsp, npad, P.plQ, S2, kc2, Wpart, ppad, P.sW);
     };
     auto rows = [&](int mode) {
-        hipLaunchKernelGGL(k_bs_rows<256>, dim3((unsigned)B), dim3(256), 0, s, P, mode);
+        hipLaunchKernelGGL(k_bs_rows<256>, dim3((unsigned)live), dim3(256), 0, s, P, mode);
     };
     auto cols = [&](int mode) {
-        launch_cols(ct, cnv, B, s, P, mode);
+        launch_cols(ct, cnv, live, s, P, mode);
     };
     // r = K x - y, g = 2 K^T r, alpha_0, first direction
     gemm1();
@@ -611,7 +622,7 @@ int solve_batched_shared_mfma(gp_handle h, gp_dtype kdtype, const void* K, int64
     e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(h, e, "batched init launch");
 
-    std::vector<int32_t> hdone((size_t)B);
+    std::vector<int32_t> hdone((size_t)B), hlist((size_t)bpad);
     int it = 0;
     while (it < o.max_iter) {
         const int end = std::min(o.max_iter, it + o.chunk);
@@ -636,9 +647,19 @@ int solve_batched_shared_mfma(gp_handle h, gp_dtype kdtype, const void* K, int64
             e = hipMemcpyAsync(hdone.data(), P.done, 4 * B, hipMemcpyDeviceToHost, s);
             if (e == hipSuccess) e = hipStreamSynchronize(s);
             if (e != hipSuccess) return hip_fail(h, e, "batched status poll");
-            bool all = true;
-            for (int64_t b = 0; b < B && all; ++b) all = hdone[(size_t)b] != 0;
-            if (all) break;
+            int64_t nlive = 0;
+            for (int64_t b = 0; b < B; ++b)
+                if (!hdone[(size_t)b]) hlist[(size_t)nlive++] = (int32_t)b;
+            if (nlive == 0) break;
+            if (nlive < live) {
+                // compact: later launches cover the listed problems only
+                for (int64_t k = nlive; k < rup(nlive, GM_BN); ++k) hlist[(size_t)k] = (int32_t)bpad;
+                e = hipMemcpyAsync(dlist, hlist.data(), 4 * rup(nlive, GM_BN), hipMemcpyHostToDevice, s);
+                if (e == hipSuccess) e = hipStreamSynchronize(s);   // hlist is reused at the next poll
+                if (e != hipSuccess) return hip_fail(h, e, "batched active set");
+                live = nlive;
+                P.list = dlist;
+            }
         }
     }
     hipLaunchKernelGGL(k_bs_finish, dim3((unsigned)B), dim3(BS_T), 0, s, P, X_out, ldx, f64v);

@@ -13,7 +13,10 @@
 //
 // Shapes are padded by the host: M and N multiples of 128, Kd and kchunk
 // multiples of 32, leading dimensions multiples of 8 (16-byte rows), padding
-// filled with zeros.  No bounds checks are needed inside.
+// filled with zeros.  No bounds checks are needed inside.  With `nmap`, row
+// n of the right operand and of the output is nmap[n] (so a grid over a list
+// of columns reads and writes only those; the host pads the list to the tile
+// size with the index of a zero row).
 //
 // Tiling: a 256-thread workgroup computes a 128 x 128 tile; its four waves
 // each own a 64 x 64 sub-tile = 4 x 4 MFMA 16x16x32 blocks.  Each k-step of
@@ -38,7 +41,7 @@ __global__ __launch_bounds__(GM_T) void k_gemm_bf16(const uint16_t* __restrict__
                                                     const uint16_t* __restrict__ Bp, int64_t ldb,
                                                     int64_t pstride, int kchunk,
                                                     float* __restrict__ Cpart, int64_t ldc,
-                                                    int64_t cstride) {
+                                                    int64_t cstride, const int32_t* __restrict__ nmap) {
     static_assert(NSPLIT >= 1 && NSPLIT <= 3, "one to three bf16 planes");
     constexpr int TILE = GM_BM * GM_LDS_ROW;               // elements of one staged tile
     __shared__ __attribute__((aligned(16))) uint16_t lds[2][(1 + NSPLIT) * TILE];
@@ -57,8 +60,10 @@ __global__ __launch_bounds__(GM_T) void k_gemm_bf16(const uint16_t* __restrict__
     const int row0_ = c0_ >> 2, kc0_ = (c0_ & 3) * 8, row1_ = c1_ >> 2, kc1_ = (c1_ & 3) * 8;
     const uint16_t* a0p = A + (m0 + row0_) * lda + k_begin + kc0_;
     const uint16_t* a1p = A + (m0 + row1_) * lda + k_begin + kc1_;
-    const uint16_t* b0p = Bp + (n0 + row0_) * ldb + k_begin + kc0_;
-    const uint16_t* b1p = Bp + (n0 + row1_) * ldb + k_begin + kc1_;
+    const int64_t bn0_ = nmap ? nmap[n0 + row0_] : n0 + row0_;
+    const int64_t bn1_ = nmap ? nmap[n0 + row1_] : n0 + row1_;
+    const uint16_t* b0p = Bp + bn0_ * ldb + k_begin + kc0_;
+    const uint16_t* b1p = Bp + bn1_ * ldb + k_begin + kc1_;
 #define GPL1_LD(p_, off_) (*reinterpret_cast<const uint4*>((p_) + (off_)))
 #define GPL1_GEMM_GLOAD(step_)                                                  \
     {                                                                           \
@@ -135,7 +140,8 @@ __global__ __launch_bounds__(GM_T) void k_gemm_bf16(const uint16_t* __restrict__
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int64_t m = m0 + wm * 64 + i * 16 + (lane >> 4) * 4;
-            const int64_t nn = n0 + wn * 64 + j * 16 + (lane & 15);
+            const int64_t nl = n0 + wn * 64 + j * 16 + (lane & 15);
+            const int64_t nn = nmap ? nmap[nl] : nl;
             *reinterpret_cast<float4*>(out + nn * ldc + m) =
                 make_float4(acc[i][j][0], acc[i][j][1], acc[i][j][2], acc[i][j][3]);
         }
@@ -158,7 +164,7 @@ __global__ __launch_bounds__(GM_T) void k_gemm_bf16_planes(const uint16_t* __res
                                                            int64_t apstride, const uint16_t* __restrict__ Bp,
                                                            int64_t ldb, int64_t bpstride, int kchunk,
                                                            float* __restrict__ Cpart, int64_t ldc,
-                                                           int64_t cstride) {
+                                                           int64_t cstride, const int32_t* __restrict__ nmap) {
     static_assert(NA >= 1 && NA <= 3 && NB >= 1 && NB <= 3 && NA <= NB, "one to three planes each");
     constexpr int TILE = GM_BM * GM_LDS_ROW;
     constexpr int NT = NA + NB;
@@ -175,8 +181,10 @@ __global__ __launch_bounds__(GM_T) void k_gemm_bf16_planes(const uint16_t* __res
     const int row0_ = c0_ >> 2, kc0_ = (c0_ & 3) * 8, row1_ = c1_ >> 2, kc1_ = (c1_ & 3) * 8;
     const uint16_t* a0p = A + (m0 + row0_) * lda + k_begin + kc0_;
     const uint16_t* a1p = A + (m0 + row1_) * lda + k_begin + kc1_;
-    const uint16_t* b0p = Bp + (n0 + row0_) * ldb + k_begin + kc0_;
-    const uint16_t* b1p = Bp + (n0 + row1_) * ldb + k_begin + kc1_;
+    const int64_t bn0_ = nmap ? nmap[n0 + row0_] : n0 + row0_;
+    const int64_t bn1_ = nmap ? nmap[n0 + row1_] : n0 + row1_;
+    const uint16_t* b0p = Bp + bn0_ * ldb + k_begin + kc0_;
+    const uint16_t* b1p = Bp + bn1_ * ldb + k_begin + kc1_;
     // staging registers for the next k-step (its loads are in flight while
     // the current step is multiplied), named one by one so that they stay in
     // VGPRs
@@ -274,7 +282,8 @@ __global__ __launch_bounds__(GM_T) void k_gemm_bf16_planes(const uint16_t* __res
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int64_t m = m0 + wm * 64 + i * 16 + (lane >> 4) * 4;
-            const int64_t nn = n0 + wn * 64 + j * 16 + (lane & 15);
+            const int64_t nl = n0 + wn * 64 + j * 16 + (lane & 15);
+            const int64_t nn = nmap ? nmap[nl] : nl;
             *reinterpret_cast<float4*>(out + nn * ldc + m) =
                 make_float4(acc[i][j][0], acc[i][j][1], acc[i][j][2], acc[i][j][3]);
         }

@@ -283,11 +283,11 @@ void gemm(hipStream_t s, const uint16_t* A, int64_t lda, int64_t M, const uint16
           int64_t N, int64_t Kd, int64_t kchunk, float* C, int64_t ldc, int64_t cstride, int nsplit = 3) {
     const dim3 grid((unsigned)(M / GM_BM), (unsigned)(N / GM_BN), (unsigned)(Kd / kchunk));
     if (nsplit == 3)
-        hipLaunchKernelGGL(k_gemm_bf16<3>, grid, dim3(GM_T), 0, s, A, lda, Bp, ldb, pstride, (int)kchunk, C, ldc, cstride);
+        hipLaunchKernelGGL(k_gemm_bf16<3>, grid, dim3(GM_T), 0, s, A, lda, Bp, ldb, pstride, (int)kchunk, C, ldc, cstride, nullptr);
     else if (nsplit == 2)
-        hipLaunchKernelGGL(k_gemm_bf16<2>, grid, dim3(GM_T), 0, s, A, lda, Bp, ldb, pstride, (int)kchunk, C, ldc, cstride);
+        hipLaunchKernelGGL(k_gemm_bf16<2>, grid, dim3(GM_T), 0, s, A, lda, Bp, ldb, pstride, (int)kchunk, C, ldc, cstride, nullptr);
     else
-        hipLaunchKernelGGL(k_gemm_bf16<1>, grid, dim3(GM_T), 0, s, A, lda, Bp, ldb, pstride, (int)kchunk, C, ldc, cstride);
+        hipLaunchKernelGGL(k_gemm_bf16<1>, grid, dim3(GM_T), 0, s, A, lda, Bp, ldb, pstride, (int)kchunk, C, ldc, cstride, nullptr);
 }
 
 struct Act {

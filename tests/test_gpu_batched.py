@@ -164,6 +164,26 @@ def test_shared_per_problem_targets(H):
         H.solve_batched_shared(Kt, Y, batch.rho, f_targets=targets[:5])
 
 
+@pytest.mark.parametrize("dtype", ["bf16", "f32"])
+def test_shared_active_set_is_exact(H, dtype):
+    say(f"[batched-shared] finished problems dropped from the launches ({dtype}): same bits")
+    batch = instances.shared_batch(192, 700, 300, 8, dtype=dtype, seed=81, rhs_seed_base=810)
+    Kt = _kt(batch) if dtype == "bf16" else torch.from_numpy(batch.K_store).to(DEV)
+    Y = torch.from_numpy(batch.Y_store).to(DEV)
+    rho = list(batch.rho)
+    rho[3] = 0.0                       # finishes at once
+    Y[7] = 0.0
+    kw = dict(tol=1e-9, max_iter=3000, refresh_every=20)
+    Xa, ra = H.solve_batched_shared(Kt, Y, rho, chunk=3, **kw)       # polls (and compacts) often
+    Xb, rb = H.solve_batched_shared(Kt, Y, rho, chunk=10 ** 6, **kw)  # never compacts
+    assert torch.equal(Xa, Xb)
+    assert [r["iters"] for r in ra] == [r["iters"] for r in rb]
+    its = [r["iters"] for r in ra]
+    say(f"   iterations min {min(its)} mean {np.mean(its):.1f} max {max(its)}")
+    assert min(its) < max(its)
+    _check_columns(batch, Xa, ra, [0, 150, 299])
+
+
 # ---------------------------------------------------------------------------
 # independent problems of different sizes (lockstep batch)
 # ---------------------------------------------------------------------------
