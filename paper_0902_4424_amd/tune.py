@@ -1,7 +1,7 @@
 """Tile autotuner for the fused K / K^T kernel.
 
 For each problem shape (K dtype, n, p) it times the solver's fused kernel
-(HIP events around every launch, `profile` option) and the whole iteration
+(HIP events around every 4th launch, `profile` option) and the whole iteration
 over the candidate kernel shapes (threads, column chunks per thread, rows
 per block) and grid sizes (row slabs), and records the fastest pair in
 tuned.json next to this file.  The binding reads that table and passes the
@@ -69,7 +69,7 @@ def tune_shape(H, dtype, n, p, iters=40, reps=3, log=print):
     y = torch.from_numpy(inst.y_store).cuda()
     best = None
     for cfg, grid, il in candidates(dtype, n, p):
-        opts = gpl1.default_opts(max_iter=iters, profile=1, fused_cfg=cfg, fused_grid=grid,
+        opts = gpl1.default_opts(max_iter=iters, profile=4, fused_cfg=cfg, fused_grid=grid,
                                  fused_interleave=il)
         H.solve(K, y, inst.rho, tol=0.0, opts=opts)          # warm
         torch.cuda.synchronize()
