@@ -299,6 +299,7 @@ def learned_leg(H, np, torch, gpl1, instances, ntrain, neval, epochs, batch=256,
     lam = 0.1 * float(np.median(np.abs(tr.Y[:256].astype(np.float64) @ K64).max(axis=1)))
     net = gpl1.Lista(H, n, p, layers)
     net.init_from_K(Kd, Lk, lam)
+    net.set_forward_planes(1)            # bf16 activations suffice for a warm start
     gen = torch.Generator(device="cpu").manual_seed(7)
     steps = 0
     losses = []

@@ -211,6 +211,12 @@ int gp_lista_get_weights(gp_lista net, float* We, float* S, float* theta, void* 
 int gp_lista_save(gp_lista net, const char* path);
 int gp_lista_load(gp_lista net, const char* path);
 
+/* Activations enter the forward products of gp_lista_forward as `planes`
+ * bf16 planes (3, the default: FP32-accurate; 1: bf16 activations, a third of
+ * the matrix-core work, enough for a warm start).  Training and
+ * gp_lista_gradients always use 3.  planes outside 1..3: GP_E_ARG. */
+int gp_lista_set_forward_planes(gp_lista net, int32_t planes);
+
 /* Forward pass on B samples: Y (device, B x n, ldy) -> X_out (device,
  * B x p, ldx).  rho: host array of B radii, or NULL for the raw network
  * output; with rho each row is projected onto its ball. */

@@ -49,6 +49,7 @@ struct gp_lista_s {
     void* act = nullptr;
     size_t act_bytes = 0;
     int64_t act_bp = 0;
+    int fwd_planes = 3;   // bf16 planes of the activations in gp_lista_forward
 };
 
 namespace gpl1 {
@@ -354,7 +355,7 @@ void refresh_bf16(gp_lista net, hipStream_t s) {
 }
 
 // forward pass; keeps U, X of every layer in `a`
-void forward(gp_lista net, const float* Y, int64_t ldy, int64_t B, Act& a, hipStream_t s) {
+void forward(gp_lista net, const float* Y, int64_t ldy, int64_t B, Act& a, hipStream_t s, int planes = 3) {
     const int64_t pp = net->pp, np = net->np, bp = a.bp;
     const int64_t plY = bp * np, plX = bp * pp;
     refresh_bf16(net, s);
@@ -363,14 +364,14 @@ void forward(gp_lista net, const float* Y, int64_t ldy, int64_t B, Act& a, hipSt
     // c = We y
     const int64_t kc1 = kchunk_for(np);
     const int S1 = (int)(np / kc1);
-    gemm(s, net->We_bf, np, pp, a.Ypl, np, plY, bp, np, kc1, a.part, pp, bp * pp);
+    gemm(s, net->We_bf, np, pp, a.Ypl, np, plY, bp, np, kc1, a.part, pp, bp * pp, planes);
     const dim3 eg((unsigned)((pp + 255) / 256), (unsigned)bp);
     hipLaunchKernelGGL(k_li_fwd_act, eg, dim3(256), 0, s, a.part, S1, bp * pp, pp, B, net->p, a.C, 1, a.U, a.X,
                        net->th, 0, net->L > 1 ? a.Xpl : nullptr, plX);
     const int64_t kc2 = kchunk_for(pp);
     const int S2 = (int)(pp / kc2);
     for (int t = 1; t < net->L; ++t) {
-        gemm(s, net->S_bf, pp, pp, a.Xpl, pp, plX, bp, pp, kc2, a.part, pp, bp * pp);
+        gemm(s, net->S_bf, pp, pp, a.Xpl, pp, plX, bp, pp, kc2, a.part, pp, bp * pp, planes);
         hipLaunchKernelGGL(k_li_fwd_act, eg, dim3(256), 0, s, a.part, S2, bp * pp, pp, B, net->p, a.C, 0,
                            a.U + t * bp * pp, a.X + t * bp * pp, net->th, t,
                            t + 1 < net->L ? a.Xpl : nullptr, plX);
@@ -554,6 +555,13 @@ int gp_lista_get_weights(gp_lista net, float* We, float* S, float* theta, void* 
     return e == hipSuccess ? GP_OK_TOL : hip_fail(net->h, e, "get weights");
 }
 
+int gp_lista_set_forward_planes(gp_lista net, int32_t planes) {
+    if (!net) return GP_E_ARG;
+    if (planes < 1 || planes > 3) return fail(net->h, GP_E_ARG, "planes must be 1, 2 or 3");
+    net->fwd_planes = planes;
+    return GP_OK_TOL;
+}
+
 int gp_lista_save(gp_lista net, const char* path) {
     if (!net) return GP_E_ARG;
     gp_handle h = net->h;
@@ -635,7 +643,7 @@ int gp_lista_forward(gp_lista net, const float* Y, int64_t ldy, int64_t B, const
         Act a;
         rc = act_layout(net, bs, a, true);
         if (rc) return fail(h, rc, "activation allocation failed");
-        forward(net, Y + b0 * ldy, ldy, bs, a, s);
+        forward(net, Y + b0 * ldy, ldy, bs, a, s, net->fwd_planes);
         const float* XL = a.X + (int64_t)(net->L - 1) * a.bp * net->pp;
         if (rho) {
             std::vector<double> r((size_t)bs);

@@ -24,7 +24,7 @@ SYMBOLS = ("gp_opts_default", "gp_create", "gp_destroy", "gp_last_error",
            "gp_l1_solve_batched_var", "gp_lista_create", "gp_lista_destroy",
            "gp_lista_init_from_K", "gp_lista_set_weights", "gp_lista_get_weights",
            "gp_lista_forward", "gp_lista_train_step", "gp_lista_gradients", "gp_lista_save",
-           "gp_lista_load")
+           "gp_lista_load", "gp_lista_set_forward_planes")
 
 
 class GPOpts(C.Structure):
@@ -110,6 +110,8 @@ def load():
     lib.gp_lista_train_step.restype = i32
     lib.gp_lista_gradients.argtypes = [vp, fp, i64, fp, i64, i64, fp, fp, fp, C.POINTER(dbl), vp]
     lib.gp_lista_gradients.restype = i32
+    lib.gp_lista_set_forward_planes.argtypes = [vp, C.c_int32]
+    lib.gp_lista_set_forward_planes.restype = i32
     lib.gp_lista_save.argtypes = [vp, C.c_char_p]
     lib.gp_lista_save.restype = i32
     lib.gp_lista_load.argtypes = [vp, C.c_char_p]
@@ -380,6 +382,10 @@ class Lista:
         th = torch.empty(self.layers, dtype=torch.float32, device=dev)
         self.H._raise(self.lib.gp_lista_get_weights(self.net, _ptr(We), _ptr(S), _ptr(th), _stream(stream)))
         return We, S, th
+
+    def set_forward_planes(self, planes: int):
+        """bf16 planes of the activations in forward(): 3 = FP32-accurate, 1 = bf16."""
+        self.H._raise(self.lib.gp_lista_set_forward_planes(self.net, int(planes)))
 
     def save(self, path: str):
         self.H._raise(self.lib.gp_lista_save(self.net, os.fsencode(path)))

@@ -104,6 +104,27 @@ def test_forward_matches_oracle(H, n, p, L, B):
     net.close()
 
 
+def test_forward_with_bf16_activations(H):
+    say("[lista] forward with one activation plane: bf16-level agreement")
+    n, p, L, B = 200, 1100, 4, 130
+    K, Y, _ = _problem(n, p, B, max(1, p // 30), seed=n + p)
+    lam = 0.1 * np.abs(K.T @ Y[0]).max()
+    We, S, th = _weights(K, lam, seed=3)
+    ths = _bf(np.full(L, th))
+    net = _net(H, n, p, L, We, S, ths)
+    Yd = _dev(Y)
+    X3 = net.forward(Yd).cpu().double().numpy()
+    net.set_forward_planes(1)
+    X1 = net.forward(Yd).cpu().double().numpy()
+    err = np.linalg.norm(X1 - X3) / np.linalg.norm(X3)
+    say(f"   relative difference {err:.2e}")
+    # bf16 rounding (2^-9) of every activation, carried through the layers
+    assert 0.0 < err <= 2e-2
+    with pytest.raises(gpl1.GPError):
+        net.set_forward_planes(4)
+    net.close()
+
+
 def test_ista_initialisation(H):
     say("[lista] initialisation from K equals the ISTA weights")
     n, p, L = 96, 300, 5
