@@ -93,7 +93,7 @@ def forms_legs(H, inst, np, torch, gpl1, instances, out):
     b16 = instances.plain_large(seed=2, dtype="bf16")
     Kb = torch.from_numpy(b16.K_store.view(np.int16)).to(dev)
     yb = torch.from_numpy(b16.y_store).to(dev)
-    ob = gpl1.default_opts(max_iter=ITERS, refresh_every=REFRESH, profile=PROFILE_EVERY)
+    ob = gpl1.opts_for(Kb, max_iter=ITERS, refresh_every=REFRESH, profile=PROFILE_EVERY)
     H.solve(Kb, yb, b16.rho, tol=0.0, opts=ob)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -477,7 +477,7 @@ def main():
     y = torch.from_numpy(inst.y_store).to(dev)
     torch.cuda.synchronize()
     H = gpl1.Handle(0)
-    opts = gpl1.default_opts(max_iter=ITERS, refresh_every=REFRESH, profile=PROFILE_EVERY)
+    opts = gpl1.opts_for(K, max_iter=ITERS, refresh_every=REFRESH, profile=PROFILE_EVERY)
     if args.calibrate_copy:
         src = torch.ones(64 << 20, dtype=torch.float32, device=dev)   # 256 MiB
         dst = torch.empty_like(src)
@@ -553,7 +553,7 @@ def main():
         g = 2.0 * (K64.T @ rl64)
         fw = float(g @ xl + inst.rho * np.abs(g).max())
         target = f_ref * (1 + 1e-6)
-        gopts = gpl1.default_opts(max_iter=20000, refresh_every=REFRESH, f_target=target, chunk=16)
+        gopts = gpl1.opts_for(K, max_iter=20000, refresh_every=REFRESH, f_target=target, chunk=16)
         H.solve(K, y, inst.rho, tol=0.0, opts=gopts)       # warm
         torch.cuda.synchronize()
         tg0 = time.perf_counter()

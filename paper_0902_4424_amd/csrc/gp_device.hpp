@@ -233,4 +233,24 @@ __device__ __forceinline__ void block_sum2(int& c, double& v, double* lds) {
     v = vs;
 }
 
+// block_sum2 for a loop of reductions with one barrier each: successive
+// calls alternate between two slot sets of `slots` (4 * T/64 doubles, used
+// by nothing else), so a wave writing the slots of call k + 1 never meets a
+// wave still reading those of call k - 1 (it passed call k's barrier first).
+template <int T>
+__device__ __forceinline__ void block_sum2_alt(int& c, double& v, double* slots, int parity) {
+    constexpr int NWV = T / WAVE;
+    c = wave_sum(c);
+    v = wave_sum(v);
+    const int lane = threadIdx.x & (WAVE - 1), wid = threadIdx.x / WAVE;
+    double* sl = slots + (parity & 1) * 2 * NWV;
+    if (lane == 0) { sl[2 * wid] = (double)c; sl[2 * wid + 1] = v; }
+    __syncthreads();
+    double cs = 0.0, vs = 0.0;
+#pragma unroll
+    for (int i = 0; i < NWV; ++i) { cs += sl[2 * i]; vs += sl[2 * i + 1]; }
+    c = (int)cs;
+    v = vs;
+}
+
 }  // namespace gpl1

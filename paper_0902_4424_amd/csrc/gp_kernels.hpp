@@ -145,6 +145,7 @@ __device__ __forceinline__ void l1_threshold_regs(const double (&vr)[NV], int64_
                                                   double* lds, double& m, double& t, bool& inside,
                                                   int& passes) {
     const int tid = threadIdx.x;
+    __shared__ double slots[4 * (T / WAVE)];   // the passes' reductions (one barrier each)
     double Sm_s[1] = {0.0}, Sm_m[1] = {0.0};
 #pragma unroll
     for (int e = 0; e < NV; ++e) {
@@ -172,7 +173,7 @@ __device__ __forceinline__ void l1_threshold_regs(const double (&vr)[NV], int64_
             const double b = fabs(vr[e]) - m;
             if (j < p && b > t) { ++c; sum += b; }
         }
-        block_sum2<T>(c, sum, lds);
+        block_sum2_alt<T>(c, sum, slots, passes);
         ++passes;
         if (c == cprev || passes >= (1 << 20)) break;
         cprev = c;
@@ -199,6 +200,7 @@ __global__ __launch_bounds__(PROJ_T) void k_proj(GPState* __restrict__ st, int m
     constexpr int T = PROJ_T;
     constexpr int NV = VPT > 0 ? VPT : 1;
     __shared__ double lds[3 * (T / WAVE)];
+    __shared__ double slots[4 * (T / WAVE)];   // the threshold passes' reductions
     __shared__ double sh_alpha, sh_mu;
     __shared__ GPState S;
     const int tid = threadIdx.x;
@@ -345,7 +347,7 @@ __global__ __launch_bounds__(PROJ_T) void k_proj(GPState* __restrict__ st, int m
                     if (b > t) { ++c; sum += b; }
                 }
             }
-            block_sum2<T>(c, sum, lds);
+            block_sum2_alt<T>(c, sum, slots, passes);
             ++passes;
             // c >= 1: the largest entry has b = 0 > t.  After the first
             // (Newton) step t is kept monotone, so the sets are nested in

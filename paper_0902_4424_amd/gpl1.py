@@ -450,6 +450,13 @@ def _tuned(kdt, n, p, kw):
     return kw
 
 
+def opts_for(K, **kw) -> GPOpts:
+    """Options for solving with this K: the autotuned kernel shape of its
+    (dtype, n, p) from tuned.json (unless given) plus the caller's options."""
+    n, p = K.shape
+    return default_opts(**_tuned(k_dtype(K), n, p, kw))
+
+
 _default_handles = {}
 
 
