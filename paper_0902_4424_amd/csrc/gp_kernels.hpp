@@ -210,8 +210,16 @@ __global__ __launch_bounds__(PROJ_T) void k_proj(GPState* __restrict__ st, int m
     // registers and both are read after the steplength rule).  g is not read
     // in the modes that have none.
     constexpr bool PREF = VPT > 0 && VPT <= 16;
+    // x kept per thread in LDS (slot e of thread tid at e*T + tid) for the
+    // float copy of d at the end, instead of a second read from memory
+    __shared__ double xkeep[PREF ? NV * T : 1];
     const bool use_g = mode == PM_ITER || mode == PM_ALPHA0;
+    const bool keep_x = PREF && d32 != nullptr;
     double vr[NV], gr[PREF ? NV : 1];
+    // the partial dots of the last update, requested with x and g
+    double dots[2] = {0.0, 0.0};
+    if (mode == PM_ITER)
+        for (int i = tid; i < GU; i += T) { dots[0] += upart[4 * i]; dots[1] += upart[4 * i + 1]; }
     if (PREF) {
 #pragma unroll
         for (int e = 0; e < NV; e += 2) {
@@ -230,6 +238,10 @@ __global__ __launch_bounds__(PROJ_T) void k_proj(GPState* __restrict__ st, int m
                 if (NV > 1) { vr[e + 1] = 0.0; gr[PREF ? e + 1 : 0] = 0.0; }
             }
         }
+        if (keep_x) {
+#pragma unroll
+            for (int e = 0; e < NV; ++e) xkeep[PREF ? e * T + tid : 0] = vr[e];
+        }
     }
     state_load(S, st);
     __syncthreads();
@@ -241,12 +253,8 @@ __global__ __launch_bounds__(PROJ_T) void k_proj(GPState* __restrict__ st, int m
     // -- steplength (Algorithm 2) from the partial dots of the last update --
     if (mode == PM_ITER) {
         const int need_ss = S.ss_pending;
-        double dots[2] = {0.0, 0.0};
         double none[1] = {0.0};
-        if (need_ss) {
-            for (int i = tid; i < GU; i += T) { dots[0] += upart[4 * i]; dots[1] += upart[4 * i + 1]; }
-            block_reduce<T, 2, 1>(dots, none, lds);
-        }
+        if (need_ss) block_reduce<T, 2, 1>(dots, none, lds);
         if (tid == 0) {
             commit_pending(&S);
             if (need_ss) {
@@ -322,6 +330,19 @@ __global__ __launch_bounds__(PROJ_T) void k_proj(GPState* __restrict__ st, int m
     const bool inside = Sv <= rho;
     double t = 0.0;     // mu - m
     int passes = 0;
+    // Outside the ball the register slots are turned into b = |v| - m once
+    // (-inf for slots past p) with the signs kept in `neg`, so that a pass is
+    // one compare and one add per slot.
+    const bool shifted = VPT > 0 && !inside && rho > 0.0;
+    uint32_t neg = 0;
+    if (shifted) {
+#pragma unroll
+        for (int e = 0; e < NV; ++e) {
+            const int j = 2 * ((e / 2) * T + tid) + (e & 1);
+            if (vr[e] < 0.0) neg |= 1u << e;
+            vr[e] = j < p ? fabs(vr[e]) - m : -INFINITY;
+        }
+    }
     if (!inside && rho > 0.0) {
         // start: the previous threshold if it lies below m, else the lower
         // bound max(-rho, mean bound); any start with t < 0 is valid
@@ -336,11 +357,8 @@ __global__ __launch_bounds__(PROJ_T) void k_proj(GPState* __restrict__ st, int m
             double sum = 0.0;
             if (VPT > 0) {
 #pragma unroll
-                for (int e = 0; e < NV; ++e) {
-                    const int j = 2 * ((e / 2) * T + tid) + (e & 1);
-                    const double b = fabs(vr[e]) - m;
-                    if (j < p && b > t) { ++c; sum += b; }
-                }
+                for (int e = 0; e < NV; ++e)
+                    if (vr[e] > t) { ++c; sum += vr[e]; }
             } else {
                 for (int64_t j = tid; j < p; j += T) {
                     const double b = fabs(vbuf[j]) - m;
@@ -359,12 +377,19 @@ __global__ __launch_bounds__(PROJ_T) void k_proj(GPState* __restrict__ st, int m
             first = false;
         }
     }
-    // h_i = sgn(v_i) max(b_i - t, 0);  rho == 0 gives h = 0
+    // h_i = sgn(v_i) max(b_i - t, 0);  rho == 0 gives h = 0.  hval takes a
+    // value of v (the vbuf path), hreg register slot e (v itself, or b with
+    // its sign in `neg` once shifted)
     auto hval = [&](double vj) -> double {
         if (inside) return vj;
         if (!(rho > 0.0)) return 0.0;
         const double a = fmax((fabs(vj) - m) - t, 0.0);
         return vj < 0.0 ? -a : a;
+    };
+    auto hreg = [&](int e) -> double {
+        if (!shifted) return hval(vr[e]);
+        const double a = fmax(vr[e] - t, 0.0);
+        return ((neg >> e) & 1u) ? -a : a;
     };
 
     // -- outputs ------------------------------------------------------------
@@ -376,16 +401,19 @@ __global__ __launch_bounds__(PROJ_T) void k_proj(GPState* __restrict__ st, int m
             for (int e = 0; e < NV; e += 2) {
                 const int j = 2 * ((e / 2) * T + tid);
                 if (NV > 1 && j + 1 < p) {
-                    const double h0 = hval(vr[e]), h1 = hval(vr[e + 1]);
+                    const double h0 = hreg(e), h1 = hreg(e + 1);
                     *reinterpret_cast<double2*>(dout + j) = make_double2(h0, h1);
-                    if (d32) {   // x re-read (it is in L2) rather than held in registers
+                    if (keep_x) {
+                        const double x0 = xkeep[PREF ? e * T + tid : 0], x1 = xkeep[PREF ? (e + 1) * T + tid : 0];
+                        *reinterpret_cast<float2*>(d32 + j) = make_float2((float)(h0 - x0), (float)(h1 - x1));
+                    } else if (d32) {
                         const double2 x2 = *reinterpret_cast<const double2*>(x + j);
                         *reinterpret_cast<float2*>(d32 + j) = make_float2((float)(h0 - x2.x), (float)(h1 - x2.y));
                     }
                 } else if (j < p) {
-                    const double h0 = hval(vr[e]);
+                    const double h0 = hreg(e);
                     dout[j] = h0;
-                    if (d32) d32[j] = (float)(h0 - x[j]);
+                    if (d32) d32[j] = (float)(h0 - (keep_x ? xkeep[PREF ? e * T + tid : 0] : x[j]));
                 }
             }
         } else {
@@ -407,7 +435,7 @@ __global__ __launch_bounds__(PROJ_T) void k_proj(GPState* __restrict__ st, int m
 #pragma unroll
             for (int e = 0; e < NV; ++e) {
                 const int j = 2 * ((e / 2) * T + tid) + (e & 1);
-                if (j < p) hmax = fmax(hmax, fabs(hval(vr[e])));
+                if (j < p) hmax = fmax(hmax, fabs(hreg(e)));
             }
         } else {
             for (int64_t j = tid; j < p; j += T) hmax = fmax(hmax, fabs(hval(vbuf[j])));
@@ -424,7 +452,7 @@ __global__ __launch_bounds__(PROJ_T) void k_proj(GPState* __restrict__ st, int m
 #pragma unroll
             for (int e = 0; e < NV; ++e) {
                 const int j = 2 * ((e / 2) * T + tid) + (e & 1);
-                if (j < p) out[j] = hval(vr[e]);
+                if (j < p) out[j] = hreg(e);
             }
         } else {
             for (int64_t j = tid; j < p; j += T) out[j] = hval(vbuf[j]);
