@@ -587,19 +587,28 @@ def main():
         if K64 is None:
             K64, y64 = inst.K64, inst.y64
         threads = blas_threads()
+        # the same solve as one timed step, repeated until about 10 s of CPU
+        # work (each solve stops at the stationarity floor, as the GPU's does)
         tc0 = time.perf_counter()
-        ref = gpss(K64, y64, inst.rho, tol=0.0, max_iter=ITERS)
+        nsolve = cpu_iters = 0
+        while True:
+            ref = gpss(K64, y64, inst.rho, tol=0.0, max_iter=ITERS)
+            nsolve += 1
+            cpu_iters += ref["iters"]
+            if time.perf_counter() - tc0 >= 10.0 or nsolve >= 200:
+                break
         tc = time.perf_counter() - tc0
-        out["cpu_baseline"] = {"value": round(ref["iters"] / tc, 3), "unit": "iterations/s",
+        out["cpu_baseline"] = {"value": round(cpu_iters / tc, 3), "unit": "iterations/s",
                                "cores": threads, "kind": "oracle",
-                               "sample": f"one full {ITERS}-iteration FP64 numpy solve of the "
-                                         f"same stored instance ({tc:.1f} s)"}
+                               "sample": f"{nsolve} full solves ({ITERS}-iteration budget, "
+                                         f"{cpu_iters} iterations) of the same stored instance by "
+                                         f"the FP64 numpy oracle, {tc:.1f} s"}
         fx = float(np.sum((K64 @ x_gpu - y64) ** 2))
         out["parity"] = {"rel_objective_diff_vs_oracle_500": (fx - ref["f"]) / ref["f"],
                          "x_rel_err_vs_oracle_500":
                              float(np.linalg.norm(x_gpu - ref["x"]) / np.linalg.norm(ref["x"])),
                          "oracle_status": ref["status"], "oracle_iters": ref["iters"]}
-        log(f"cpu oracle: {ref['iters'] / tc:.2f} it/s on {threads} threads; parity "
+        log(f"cpu oracle: {cpu_iters / tc:.2f} it/s on {threads} threads; parity "
             f"{out['parity']}")
     print(json.dumps(out), flush=True)
 
