@@ -206,6 +206,117 @@ def forms_legs(H, inst, np, torch, gpl1, instances, out):
     return res
 
 
+def configs_leg(H, np, torch, gpl1, instances, with_cpu):
+    """The other single-instance workloads: K 256x1024 FP64 to a relative
+    change of 1e-10, and the ill-conditioned 4096x4096 FP32 operator for 2000
+    iterations; iteration rate, wall time to a 1e-6 gap, and the oracle beside
+    them (timed on a bounded sample for the large one)."""
+    dev = torch.device("cuda:0")
+    out = {}
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            r = fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps, r
+
+    def fval(K64, y64, x):
+        r = K64 @ x.cpu().double().numpy() - y64
+        return float(r @ r)
+
+    # ---- K 256x1024 FP64, tol 1e-10 ----
+    a = instances.plain_small(seed=1, dtype="f64")
+    K = torch.from_numpy(a.K_store).to(dev)
+    y = torch.from_numpy(a.y_store).to(dev)
+    ts, (x, r) = timed(lambda: H.solve(K, y, a.rho, tol=1e-10, max_iter=100000), 20)
+    from oracle import gpss
+    ref = gpss(a.K64, a.y64, a.rho, tol=0.0, max_iter=100000)       # tight reference (stationary)
+    f_ref = ref["f"]
+    tg, (xg, rg) = timed(lambda: H.solve(K, y, a.rho, tol=0.0, max_iter=100000,
+                                         f_target=f_ref * (1 + 1e-6)), 20)
+    e = {"workload": "K 256x1024 N(0,1/256) FP64, 20-sparse +-1, sigma 1e-3, rho = ||x_true||_1, "
+                     "stop at relative change < 1e-10",
+         "iterations": r["iters"], "status": r["status_name"], "seconds_per_solve": round(ts, 6),
+         "iterations_per_s": round(r["iters"] / ts, 1),
+         "gap_vs_oracle_tight": (fval(a.K64, a.y64, x) - f_ref) / f_ref,
+         "x_rel_err_vs_oracle_tight": float(np.linalg.norm(x.cpu().numpy() - ref["x"]) /
+                                            np.linalg.norm(ref["x"])),
+         "time_to_gap_1e-6": {"seconds": round(tg, 6), "iterations": rg["iters"],
+                              "gap": (fval(a.K64, a.y64, xg) - f_ref) / f_ref}}
+    if with_cpu:
+        t0 = time.perf_counter()
+        n_it = nsol = 0
+        while time.perf_counter() - t0 < 3.0:
+            n_it += gpss(a.K64, a.y64, a.rho, tol=1e-10, max_iter=100000)["iters"]
+            nsol += 1
+        e["oracle_iterations_per_s"] = round(n_it / (time.perf_counter() - t0), 1)
+        e["oracle_sample"] = f"{nsol} solves to relative change < 1e-10"
+    out["fp64_256x1024"] = e
+    log(f"256x1024 fp64: {r['iters']} it in {ts * 1e3:.2f} ms ({r['iters'] / ts:.0f} it/s); "
+        f"gap {e['gap_vs_oracle_tight']:.1e}")
+
+    # ---- ill-conditioned 4096x4096 FP32, 2000 iterations ----
+    t0 = time.time()
+    c = instances.plain_illcond(seed=3, dtype="f32")
+    log(f"ill-conditioned instance generated in {time.time() - t0:.1f}s")
+    K = torch.from_numpy(c.K_store).to(dev)
+    y = torch.from_numpy(c.y_store).to(dev)
+    o2000 = gpl1.opts_for(K, max_iter=2000, refresh_every=REFRESH)
+    ts, (x, r) = timed(lambda: H.solve(K, y, c.rho, tol=0.0, opts=o2000), 3)
+    K64, y64 = c.K64, c.y64
+    xl, _ = H.solve(K, y, c.rho, tol=0.0, max_iter=40000, refresh_every=REFRESH)
+    f_ref = fval(K64, y64, xl)
+    og = gpl1.opts_for(K, max_iter=40000, refresh_every=REFRESH, f_target=f_ref * (1 + 1e-6))
+    tg, (xg, rg) = timed(lambda: H.solve(K, y, c.rho, tol=0.0, opts=og), 1)
+    e = {"workload": "K = U diag(s) V^T 4096x4096 FP32, s geometric 1..1e-4, 200-sparse +-1, "
+                     "sigma 1e-3, rho = ||x_true||_1, 2000 iterations",
+         "iterations": r["iters"], "status": r["status_name"], "seconds_per_solve": round(ts, 5),
+         "iterations_per_s": round(r["iters"] / ts, 1),
+         "gap_at_budget": (fval(K64, y64, x) - f_ref) / f_ref,
+         "f_ref_source": "40000-iteration GPU run, f recomputed in FP64 on the host",
+         "time_to_gap_1e-6": {"seconds": round(tg, 5), "iterations": rg["iters"], "status": rg["status_name"],
+                              "gap": (fval(K64, y64, xg) - f_ref) / f_ref}}
+    if with_cpu:
+        t0 = time.perf_counter()
+        o = gpss(K64, y64, c.rho, tol=0.0, max_iter=200)
+        tcpu = time.perf_counter() - t0
+        x200, _ = H.solve(K, y, c.rho, tol=0.0, max_iter=200, refresh_every=REFRESH)
+        e["oracle_iterations_per_s"] = round(o["iters"] / tcpu, 1)
+        e["oracle_sample"] = f"first {o['iters']} iterations ({tcpu:.1f} s)"
+        e["gap_at_200_gpu_vs_oracle"] = [(fval(K64, y64, x200) - f_ref) / f_ref, (o["f"] - f_ref) / f_ref]
+    out["illcond_4096"] = e
+    log(f"illcond 4096: {r['iters']} it in {ts * 1e3:.1f} ms ({r['iters'] / ts:.0f} it/s); gap at 2000 "
+        f"{e['gap_at_budget']:.2e}; to 1e-6: {tg * 1e3:.1f} ms, {rg['iters']} it")
+    return out
+
+
+def mall_leg(H, np, torch, gpl1, instances):
+    """The fused kernel on a K twice the size of the 256 MB Infinity Cache
+    (8192 x 16384 FP32, 512 MiB), so that no part of K can stay cached between
+    iterations: its rate is the HBM rate."""
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    inst = instances.gaussian_instance(8192, 16384, 400, amp="normal", sigma=1e-2, rho_scale=0.9,
+                                       kscale=1 / np.sqrt(8192), dtype="f32", seed=22, name="gauss_8192x16384")
+    log(f"8192x16384 instance generated in {time.time() - t0:.1f}s")
+    K = torch.from_numpy(inst.K_store).to(dev)
+    y = torch.from_numpy(inst.y_store).to(dev)
+    o = gpl1.opts_for(K, max_iter=ITERS, refresh_every=REFRESH, profile=PROFILE_EVERY)
+    H.solve(K, y, inst.rho, tol=0.0, opts=o)
+    torch.cuda.synchronize()
+    _, r = H.solve(K, y, inst.rho, tol=0.0, opts=o)
+    us = r["t_fused_ms"] * 1e3 / max(r["n_fused"], 1)
+    alg = 8192 * 16384 * 4 + 8 * 16384 + 16 * 8192 + 4 * 16384
+    res = {"workload": "gauss 8192x16384 fp32 (512 MiB, twice the Infinity Cache)",
+           "fused_avg_us": round(us, 2), "fused_GBps": round(alg / us / 1e3, 1),
+           "frac_of_8TBps": round(alg / us / 1e3 / HBM_PEAK_GBS, 4), "timed_launches": r["n_fused"]}
+    log(f"512 MiB K: fused {us:.1f} us -> {alg / us / 1e3:.0f} GB/s")
+    return res
+
+
 def ingest_counters(fetch_dir, write_dir):
     """Write the fused kernel's measured HBM bytes per live launch from two
     rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE; KiB per dispatch) of
@@ -442,6 +553,9 @@ def main():
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the BF16-storage and batched legs")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned warm-start leg")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the FP64 256x1024 and ill-conditioned 4096x4096 legs")
+    ap.add_argument("--no-mall", action="store_true", help="skip the 512 MiB K check")
     ap.add_argument("--learned-train", type=int, default=100000,
                     help="training pairs of the learned leg")
     ap.add_argument("--learned-eval", type=int, default=10000,
@@ -576,6 +690,12 @@ def main():
         out["forms"] = forms_legs(H, inst, np, torch, gpl1, instances, out)
         del out["_x_fp32"]
 
+    # ---- the other single-instance workloads; a K larger than the cache ----
+    if not args.no_configs:
+        out["other_configs"] = configs_leg(H, np, torch, gpl1, instances, not args.no_cpu_baseline)
+    if not args.no_mall:
+        out["hbm_check_512MiB"] = mall_leg(H, np, torch, gpl1, instances)
+
     # ---- learned warm start + batched refinement --------------------------
     if not args.no_learned:
         out["learned_warm_start"] = learned_leg(H, np, torch, gpl1, instances, args.learned_train,
@@ -603,6 +723,19 @@ def main():
                                "sample": f"{nsolve} full solves ({ITERS}-iteration budget, "
                                          f"{cpu_iters} iterations) of the same stored instance by "
                                          f"the FP64 numpy oracle, {tc:.1f} s"}
+        # the same oracle on one BLAS thread, a shorter sample
+        try:
+            from threadpoolctl import threadpool_limits
+            with threadpool_limits(limits=1, user_api="blas"):
+                t1 = time.perf_counter()
+                n1 = 0
+                while time.perf_counter() - t1 < 5.0:
+                    n1 += gpss(K64, y64, inst.rho, tol=0.0, max_iter=ITERS)["iters"]
+                t1 = time.perf_counter() - t1
+            out["cpu_oracle_1_thread"] = {"value": round(n1 / t1, 3), "unit": "iterations/s",
+                                          "sample": f"{n1} iterations in {t1:.1f} s"}
+        except ImportError:
+            pass
         fx = float(np.sum((K64 @ x_gpu - y64) ** 2))
         out["parity"] = {"rel_objective_diff_vs_oracle_500": (fx - ref["f"]) / ref["f"],
                          "x_rel_err_vs_oracle_500":
