@@ -269,6 +269,14 @@ def test_projected_output_and_warm_start(H):
         assert abs(fw - fc) <= 1e-6 * fc
     say(f"   mean iterations cold {np.mean([r['iters'] for r in rc]):.1f}, "
         f"warm {np.mean([r['iters'] for r in rw]):.1f}")
+    # warm-started solutions against the oracle (FP32 bar)
+    from oracle import gpss
+    for b in (0, 7):
+        ref = gpss(K64, Y[b], float(rho[b]), tol=0.0, max_iter=100000)
+        xw = warm[b].cpu().double().numpy()
+        fw = float(np.sum((K64 @ xw - Y[b]) ** 2))
+        assert (fw - ref["f"]) / ref["f"] <= 1e-6
+        assert np.linalg.norm(xw - ref["x"]) / np.linalg.norm(ref["x"]) <= 1e-4
     zero.close()
     net.close()
 

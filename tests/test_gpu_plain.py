@@ -288,3 +288,22 @@ def test_sampled_profiling(H):
         assert torch.equal(x, x0)
     with pytest.raises(gpl1.GPError):
         H.solve(K, y, inst.rho, profile=-1)
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 5, 8, 13, 21, 34])
+def test_fp64_trajectory_matches_oracle(H, k):
+    """Trajectory level: after k accepted updates the FP64 iterate, objective
+    and backtrack count equal the oracle's (the steplength branches and the
+    line search take the same decisions while rounding stays far below the
+    branch margins)."""
+    say(f"[solve] FP64 trajectory after {k} iterations")
+    inst = instances.plain_small(seed=1, dtype="f64")
+    ref = gpss(inst.K64, inst.y64, inst.rho, tol=0.0, max_iter=k)
+    x, res = H.solve(_K_tensor(inst), _dev(inst.y_store), inst.rho, tol=0.0, max_iter=k)
+    assert res["iters"] == ref["iters"] == k
+    assert res["backtracks"] == ref["backtracks"]
+    xn = x.cpu().numpy()
+    err = np.linalg.norm(xn - ref["x"]) / np.linalg.norm(ref["x"])
+    say(f"   x rel err {err:.2e}, f rel diff {abs(res['f'] - ref['f']) / ref['f']:.2e}")
+    assert err <= 1e-10
+    assert abs(res["f"] - ref["f"]) <= 1e-10 * ref["f"]
