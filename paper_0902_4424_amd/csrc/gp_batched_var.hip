@@ -31,7 +31,7 @@ namespace gpl1 {
 
 constexpr int BV_T = 1024;   // per-problem workgroups
 constexpr int BV_FT = 256;   // fused-pass workgroups
-constexpr int BV_ROWS = 32;  // rows per work item
+constexpr int BV_ROWS = 64;  // rows per work item
 
 struct VarInst {
     const void* K;
