@@ -386,7 +386,7 @@ def learned_leg(H, np, torch, gpl1, instances, ntrain, neval, epochs, batch=256,
     ev = instances.warm_start_rhs(K32, neval, seed=62)
     log(f"learned leg: {ntrain} training and {neval} evaluation right-hand sides drawn "
         f"({time.time() - t0:.1f}s)")
-    CH = 2048
+    CH = 10000
     # batched calls poll every 8 iterations: finished problems leave the launches
     kw = dict(refresh_every=REFRESH, chunk=8)
 
