@@ -79,7 +79,8 @@ typedef struct {
     int32_t fused_cfg;    /* tuning: fused K/K^T kernel shape, 1..10 (0 = automatic) */
     int32_t fused_grid;   /* tuning: workgroups (row slabs) of that kernel (0 = automatic) */
     int32_t profile;      /* k > 0: time the fused K/K^T launch of every k-th iteration with HIP
-                             events (result.t_fused_ms over result.n_fused launches); 0 = off */
+                             events stamped by the launch itself (result.t_fused_ms over
+                             result.n_fused launches); 0 = off */
     int32_t fused_interleave; /* tuning: 1 = row blocks dealt round-robin to workgroups, 0 = slabs */
     const double* f_targets;  /* batched calls: host array of one f_target per problem (NULL = f_target
                                  for all); must stay valid for the call; ignored by gp_l1_solve */

@@ -2,6 +2,7 @@
 // sequence.  The iteration runs entirely on the device; the host enqueues
 // `chunk` iterations at a time and reads one status word between chunks.
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include <algorithm>
 #include <cmath>
@@ -166,18 +167,25 @@ struct FusedArgs {
     const double *v, *vsub, *g, *ysub, *rvec; double* tout; void* wpart; int64_t ldw; double* spart;
     int interleave;
     const float* v32;   // float copy of the multiplied vector, or NULL
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;   // timing: recorded by the launch itself
 };
+
+template <typename TK, typename ACC, int T, int CPT, int RB, int NB, bool AL>
+void launch_fused_one(hipStream_t s, int64_t G, const FusedArgs& a) {
+    if (a.ev0)   // start and stop stamped by the dispatch itself (no separate marker packets)
+        hipExtLaunchKernelGGL((k_fused<TK, ACC, T, CPT, RB, NB, AL>), dim3((unsigned)G), dim3(T), 0, s, a.ev0,
+                              a.ev1, 0, a.st, (const TK*)a.K, a.n, a.p, a.ldk, a.rows, a.v, a.vsub, a.g, a.ysub,
+                              a.rvec, a.tout, (ACC*)a.wpart, a.ldw, a.spart, a.interleave, a.v32);
+    else
+        hipLaunchKernelGGL((k_fused<TK, ACC, T, CPT, RB, NB, AL>), dim3((unsigned)G), dim3(T), 0, s, a.st,
+                           (const TK*)a.K, a.n, a.p, a.ldk, a.rows, a.v, a.vsub, a.g, a.ysub, a.rvec, a.tout,
+                           (ACC*)a.wpart, a.ldw, a.spart, a.interleave, a.v32);
+}
 
 template <typename TK, typename ACC, int T, int CPT, int RB, int NB>
 void launch_fused_t(bool aligned, hipStream_t s, int64_t G, const FusedArgs& a) {
-    if (aligned)
-        hipLaunchKernelGGL((k_fused<TK, ACC, T, CPT, RB, NB, true>), dim3((unsigned)G), dim3(T), 0, s, a.st,
-                           (const TK*)a.K, a.n, a.p, a.ldk, a.rows, a.v, a.vsub, a.g, a.ysub, a.rvec, a.tout,
-                           (ACC*)a.wpart, a.ldw, a.spart, a.interleave, a.v32);
-    else
-        hipLaunchKernelGGL((k_fused<TK, ACC, T, CPT, RB, NB, false>), dim3((unsigned)G), dim3(T), 0, s, a.st,
-                           (const TK*)a.K, a.n, a.p, a.ldk, a.rows, a.v, a.vsub, a.g, a.ysub, a.rvec, a.tout,
-                           (ACC*)a.wpart, a.ldw, a.spart, a.interleave, a.v32);
+    if (aligned) launch_fused_one<TK, ACC, T, CPT, RB, NB, true>(s, G, a);
+    else launch_fused_one<TK, ACC, T, CPT, RB, NB, false>(s, G, a);
 }
 
 template <typename TK, typename ACC>
@@ -489,11 +497,15 @@ int gp_l1_solve(gp_handle h, gp_dtype kdtype, const void* K, int64_t n, int64_t 
         for (; it < end; ++it) {
             launch_proj(s, st, PM_ITER, p, x, g, d, upart, P.GU, vb, d32);
             // every profile-th iteration's fused launch is bracketed by events
-            hipEvent_t e0 = (o.profile > 0 && it % o.profile == 0) ? prof_event(h) : nullptr;
-            if (e0) (void)hipEventRecord(e0, s);
-            launch_fused(kdtype, P.cfg, aligned, s, P.G, fa_iter);
-            hipEvent_t e1 = e0 ? prof_event(h) : nullptr;
-            if (e1) (void)hipEventRecord(e1, s);
+            if (o.profile > 0 && it % o.profile == 0) {
+                FusedArgs fa = fa_iter;
+                fa.ev0 = prof_event(h);
+                fa.ev1 = fa.ev0 ? prof_event(h) : nullptr;
+                if (fa.ev0 && !fa.ev1) { --h->ev_used; fa.ev0 = nullptr; }   // keep the pairs aligned
+                launch_fused(kdtype, P.cfg, aligned, s, P.G, fa);
+            } else {
+                launch_fused(kdtype, P.cfg, aligned, s, P.G, fa_iter);
+            }
             launch_update(kdtype, s, st, UM_ITER, spart, (int)P.G, wpart, P.ldw, p, n, x, g, d, r, q, upart);
             if (o.refresh_every > 0 && (it + 1) % o.refresh_every == 0 && it + 1 < o.max_iter) refresh();
         }
