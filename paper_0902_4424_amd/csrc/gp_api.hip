@@ -213,9 +213,15 @@ void launch_fused(gp_dtype dt, int cfg, bool aligned, hipStream_t s, int64_t G, 
     else launch_fused_dt<bf16_t, float>(cfg, aligned, s, G, a);
 }
 
+// Projection shape: 256 threads when p fits 16 register slots of each
+// (fewer waves make the workgroup reductions of the threshold passes
+// cheaper), else 1024 threads with up to 22 slots, else the buffered path.
+int proj_threads(int64_t p) { return p <= 256 * 16 ? 256 : PROJ_T; }
+
 int proj_vpt(int64_t p) {
     // register slots per thread (pairs of neighbours, so at least 2)
-    const int64_t per = (p + PROJ_T - 1) / PROJ_T;
+    const int T = proj_threads(p);
+    const int64_t per = (p + T - 1) / T;
     if (per <= 2) return 2;
     if (per <= 4) return 4;
     if (per <= 8) return 8;
@@ -226,12 +232,23 @@ int proj_vpt(int64_t p) {
 
 void launch_proj(hipStream_t s, GPState* st, int mode, int64_t p, double* x, const double* g, double* dout,
                  const double* upart, int GU, double* vbuf, float* d32) {
-    switch (proj_vpt(p)) {
+    const int v = proj_vpt(p);
+    if (proj_threads(p) == 256) {
+        switch (v) {
 #define GPL1_PROJ_CASE(V) \
-    case V: hipLaunchKernelGGL(k_proj<V>, dim3(1), dim3(PROJ_T), 0, s, st, mode, p, x, g, dout, upart, GU, vbuf, d32); break;
-        GPL1_PROJ_CASE(2)
-        GPL1_PROJ_CASE(4)
-        GPL1_PROJ_CASE(8)
+    case V: hipLaunchKernelGGL((k_proj<V, 256>), dim3(1), dim3(256), 0, s, st, mode, p, x, g, dout, upart, GU, vbuf, d32); break;
+            GPL1_PROJ_CASE(2)
+            GPL1_PROJ_CASE(4)
+            GPL1_PROJ_CASE(8)
+            GPL1_PROJ_CASE(16)
+#undef GPL1_PROJ_CASE
+        }
+        return;
+    }
+    switch (v) {
+#define GPL1_PROJ_CASE(V) \
+    case V: hipLaunchKernelGGL((k_proj<V, PROJ_T>), dim3(1), dim3(PROJ_T), 0, s, st, mode, p, x, g, dout, upart, GU, vbuf, d32); break;
+        GPL1_PROJ_CASE(8)      // p in (4096, 8192]
         GPL1_PROJ_CASE(16)
         GPL1_PROJ_CASE(22)
         GPL1_PROJ_CASE(0)

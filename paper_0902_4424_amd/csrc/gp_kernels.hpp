@@ -191,13 +191,12 @@ __device__ __forceinline__ double l1_hval(double vj, double m, double t, bool in
     return vj < 0.0 ? -a : a;
 }
 
-template <int VPT>
-__global__ __launch_bounds__(PROJ_T) void k_proj(GPState* __restrict__ st, int mode, int64_t p,
+template <int VPT, int T>
+__global__ __launch_bounds__(T) void k_proj(GPState* __restrict__ st, int mode, int64_t p,
                                                  double* __restrict__ x, const double* __restrict__ g,
                                                  double* __restrict__ dout,
                                                  const double* __restrict__ upart, int GU,
                                                  double* __restrict__ vbuf, float* __restrict__ d32) {
-    constexpr int T = PROJ_T;
     constexpr int NV = VPT > 0 ? VPT : 1;
     __shared__ double lds[3 * (T / WAVE)];
     __shared__ double slots[4 * (T / WAVE)];   // the threshold passes' reductions
