@@ -115,10 +115,10 @@ __global__ __launch_bounds__(BV_FT) void k_bv_fused(const VarInst* __restrict__ 
 }
 
 // line search, updates, steplength rule (iteration) or r, g, f (refresh)
-template <typename ACC>
-__global__ __launch_bounds__(BV_T) void k_bv_update(const VarInst* __restrict__ I, GPState* __restrict__ st_all,
+template <typename ACC, int T>
+__global__ __launch_bounds__(T) void k_bv_update(const VarInst* __restrict__ I, GPState* __restrict__ st_all,
                                                     int refresh) {
-    __shared__ double lds[3 * (BV_T / WAVE)];
+    __shared__ double lds[3 * (T / WAVE)];
     __shared__ double sh[4];
     const int b = blockIdx.x, tid = threadIdx.x;
     GPState* st = st_all + b;
@@ -129,11 +129,11 @@ __global__ __launch_bounds__(BV_T) void k_bv_update(const VarInst* __restrict__ 
     else wp = (const ACC*)D.wpart;
     // partial dots of the items, fixed order
     double a[2] = {0.0, 0.0}, none[1] = {0.0};
-    for (int64_t i = tid; i < D.nitems; i += BV_T) {
+    for (int64_t i = tid; i < D.nitems; i += T) {
         a[0] += D.spart[SPART * i];
         a[1] += D.spart[SPART * i + 1];
     }
-    block_reduce<BV_T, 2, 1>(a, none, lds);
+    block_reduce<T, 2, 1>(a, none, lds);
     const double tt = a[0], tr = a[1];
     auto wsum = [&](int64_t j) {
         double s = 0.0;
@@ -141,8 +141,8 @@ __global__ __launch_bounds__(BV_T) void k_bv_update(const VarInst* __restrict__ 
         return s;
     };
     if (refresh) {
-        for (int64_t i = tid; i < D.n; i += BV_T) D.r[i] = D.q[i];
-        for (int64_t j = tid; j < D.p; j += BV_T) D.g[j] = 2.0 * wsum(j);
+        for (int64_t i = tid; i < D.n; i += T) D.r[i] = D.q[i];
+        for (int64_t j = tid; j < D.p; j += T) D.g[j] = 2.0 * wsum(j);
         if (tid == 0) {
             if (st->k == 0 && st->nhist == 0) { st->hpos = 0; st->nhist = 1; }
             st->fhist[st->hpos] = tt;
@@ -188,9 +188,9 @@ __global__ __launch_bounds__(BV_T) void k_bv_update(const VarInst* __restrict__ 
     __syncthreads();
     if (sh[1] != 0.0) return;
     const double lam = sh[0];
-    for (int64_t i = tid; i < D.n; i += BV_T) D.r[i] += lam * D.q[i];
+    for (int64_t i = tid; i < D.n; i += T) D.r[i] += lam * D.q[i];
     double dots[2] = {0.0, 0.0};
-    for (int64_t j = tid; j < D.p; j += BV_T) {
+    for (int64_t j = tid; j < D.p; j += T) {
         const double w = wsum(j);
         const double dj = D.d[j];
         D.x[j] += lam * dj;
@@ -198,7 +198,7 @@ __global__ __launch_bounds__(BV_T) void k_bv_update(const VarInst* __restrict__ 
         dots[0] += dj * w;
         dots[1] += w * w;
     }
-    block_reduce<BV_T, 2, 1>(dots, none, lds);
+    block_reduce<T, 2, 1>(dots, none, lds);
     if (tid == 0) {
         const GPParams& P = st->prm;
         // s = lam d, z = 2 lam w: equation (5), then Algorithm 2
@@ -215,10 +215,10 @@ __global__ __launch_bounds__(BV_T) void k_bv_update(const VarInst* __restrict__ 
 }
 
 // projection (alpha0 first on init), direction and its dots
-template <int NV>
-__global__ __launch_bounds__(BV_T) void k_bv_proj(const VarInst* __restrict__ I, GPState* __restrict__ st_all,
+template <int T, int NV>
+__global__ __launch_bounds__(T) void k_bv_proj(const VarInst* __restrict__ I, GPState* __restrict__ st_all,
                                                   int init) {
-    __shared__ double lds[3 * (BV_T / WAVE)];
+    __shared__ double lds[3 * (T / WAVE)];
     __shared__ double sh[4];
     const int b = blockIdx.x, tid = threadIdx.x;
     GPState* st = st_all + b;
@@ -236,14 +236,14 @@ __global__ __launch_bounds__(BV_T) void k_bv_proj(const VarInst* __restrict__ I,
     if (init) {
 #pragma unroll
         for (int e = 0; e < NV; ++e) {
-            const int j = 2 * ((e / 2) * BV_T + tid) + (e & 1);
+            const int j = 2 * ((e / 2) * T + tid) + (e & 1);
             vr[e] = j < p ? D.x[j] - D.g[j] : 0.0;
         }
-        l1_threshold_regs<BV_T, NV>(vr, p, rho, -1.0, lds, m, t, inside, passes);
+        l1_threshold_regs<T, NV>(vr, p, rho, -1.0, lds, m, t, inside, passes);
         double hm = 0.0;
 #pragma unroll
         for (int e = 0; e < NV; ++e) hm = fmax(hm, fabs(l1_hval(vr[e], m, t, inside, rho)));
-        hm = block_max<BV_T>(hm, lds);
+        hm = block_max<T>(hm, lds);
         alpha = hm > 0.0 ? clamp_alpha(1.0 / hm, st->prm) : st->prm.amax;
         __syncthreads();
         if (tid == 0) st->alpha = alpha;
@@ -251,19 +251,19 @@ __global__ __launch_bounds__(BV_T) void k_bv_proj(const VarInst* __restrict__ I,
     const double mu_prev = init ? 0.0 : sh[1];
 #pragma unroll
     for (int e = 0; e < NV; ++e) {
-        const int j = 2 * ((e / 2) * BV_T + tid) + (e & 1);
+        const int j = 2 * ((e / 2) * T + tid) + (e & 1);
         vr[e] = j < p ? D.x[j] - alpha * D.g[j] : 0.0;
     }
     double mloc = 0.0;
 #pragma unroll
     for (int e = 0; e < NV; ++e) mloc = fmax(mloc, fabs(vr[e]));
-    mloc = block_max<BV_T>(mloc, lds);
+    mloc = block_max<T>(mloc, lds);
     const double start = (mu_prev > 0.0 && mu_prev < mloc) ? mu_prev - mloc : -1.0;
-    l1_threshold_regs<BV_T, NV>(vr, p, rho, start, lds, m, t, inside, passes);
+    l1_threshold_regs<T, NV>(vr, p, rho, start, lds, m, t, inside, passes);
     double sums[2] = {0.0, 0.0}, mx[1] = {0.0};
 #pragma unroll
     for (int e = 0; e < NV; ++e) {
-        const int j = 2 * ((e / 2) * BV_T + tid) + (e & 1);
+        const int j = 2 * ((e / 2) * T + tid) + (e & 1);
         if (j < p) {
             const double dj = l1_hval(vr[e], m, t, inside, rho) - D.x[j];
             D.d[j] = dj;
@@ -272,7 +272,7 @@ __global__ __launch_bounds__(BV_T) void k_bv_proj(const VarInst* __restrict__ I,
             mx[0] = fmax(mx[0], fabs(dj));
         }
     }
-    block_reduce<BV_T, 2, 1>(sums, mx, lds);
+    block_reduce<T, 2, 1>(sums, mx, lds);
     if (tid == 0) {
         st->gd = sums[0];
         st->dd = sums[1];
@@ -348,6 +348,7 @@ int solve_batched_var_lockstep(gp_handle h, gp_dtype kdtype, const gp_instance* 
     for (int c : {1, 2, 4})
         if ((int64_t)BV_FT * c * vec >= maxp) { cpt = c; break; }
     const int nv = bv_nv(maxp);
+    const int pnv = maxp <= 512 ? 2 : maxp <= 1024 ? 4 : maxp <= 2048 ? 8 : 16;   // slots at 256 threads
     if (cpt == 0 || nv == 0) return GP_E_UNSUPPORTED;
     const bool f64v = kdtype == GP_F64;
 
@@ -408,11 +409,18 @@ int solve_batched_var_lockstep(gp_handle h, gp_dtype kdtype, const gp_instance* 
         else launch_bv_fused<bf16_t, float>(cpt, s, nit, dI, ditems, st, refresh);
     };
     auto update = [&](int refresh) {
-        if (f64v) hipLaunchKernelGGL(k_bv_update<double>, dim3((unsigned)B), dim3(BV_T), 0, s, dI, st, refresh);
-        else hipLaunchKernelGGL(k_bv_update<float>, dim3((unsigned)B), dim3(BV_T), 0, s, dI, st, refresh);
+        if (f64v) hipLaunchKernelGGL((k_bv_update<double, BV_T>), dim3((unsigned)B), dim3(BV_T), 0, s, dI, st, refresh);
+        else hipLaunchKernelGGL((k_bv_update<float, BV_T>), dim3((unsigned)B), dim3(BV_T), 0, s, dI, st, refresh);
     };
     auto proj = [&](int init) {
-        GPL1_BV_NV_SWITCH(nv, hipLaunchKernelGGL(k_bv_proj<NVc>, dim3((unsigned)B), dim3(BV_T), 0, s, dI, st, init));
+        // 256 threads (several problems per CU) when the largest p fits 16 slots of each
+        if (maxp <= 256 * 16) {
+            GPL1_BV_NV_SWITCH(pnv, hipLaunchKernelGGL((k_bv_proj<256, NVc>), dim3((unsigned)B), dim3(256), 0, s, dI,
+                                                      st, init));
+        } else {
+            GPL1_BV_NV_SWITCH(nv, hipLaunchKernelGGL((k_bv_proj<BV_T, NVc>), dim3((unsigned)B), dim3(BV_T), 0, s,
+                                                     dI, st, init));
+        }
     };
     GPL1_BV_NV_SWITCH(nv, hipLaunchKernelGGL(k_bv_init<NVc>, dim3((unsigned)B), dim3(BV_T), 0, s, dI, st, prm,
                                              f64v ? 1 : 0));
