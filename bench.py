@@ -371,7 +371,7 @@ def ingest_counters(fetch_dir, write_dir):
 
 
 def learned_leg(H, np, torch, gpl1, instances, ntrain, neval, epochs, batch=256, lr=3e-4,
-                layers=8):
+                layers=8, oracle_check=0):
     """Learned warm start + batched GP refinement on one fixed FP32 K 1024x4096.
 
     Training pairs (y, x*) come from the batched shared-K solver; the unrolled
@@ -445,6 +445,17 @@ def learned_leg(H, np, torch, gpl1, instances, ntrain, neval, epochs, batch=256,
         R = Xl.cpu().double().numpy() @ K64.T - ev.Y[b0:b0 + m].astype(np.float64)
         f_ref[b0:b0 + m] = np.einsum("ij,ij->i", R, R)
     targets = f_ref * (1 + 1e-6)
+    # the FP64 oracle, run to stationarity on a random subset, checks these optima
+    oracle_f = None
+    if oracle_check:
+        from oracle import gpss
+        pick = np.random.default_rng(63).choice(neval, size=min(oracle_check, neval), replace=False)
+        t0 = time.perf_counter()
+        rel = [(gpss(K64, ev.Y[b].astype(np.float64), float(ev.rho[b]), tol=0.0, max_iter=100000)["f"]
+                - f_ref[b]) / f_ref[b] for b in pick]
+        oracle_f = {"instances": len(pick), "max_rel_diff_f_ref_vs_oracle": float(np.max(np.abs(rel))),
+                    "seconds": round(time.perf_counter() - t0, 1)}
+        log(f"  oracle check of f_ref on {len(pick)} problems: max rel diff {np.max(np.abs(rel)):.2e}")
 
     def host_gaps(X, b0, m):
         R = X.cpu().double().numpy() @ K64.T - ev.Y[b0:b0 + m].astype(np.float64)
@@ -521,6 +532,7 @@ def learned_leg(H, np, torch, gpl1, instances, ntrain, neval, epochs, batch=256,
                     f"{epochs} epochs of batch {batch}; {neval} fresh y (50-sparse +-1, sigma 1e-2, "
                     "rho = ||x_true||_1), each run to f <= 1.000001 f_ref",
         "f_ref_source": "3000-iteration batched GPU run per problem, f recomputed in FP64 on the host",
+        "f_ref_oracle_check": oracle_f,
         "training": {"target_generation_s": round(t_gen, 3), "train_s": round(t_train, 3),
                      "steps": steps, "loss_per_epoch": [round(v, 6) for v in losses]},
         "plain_solver": {"seconds_per_problem": round(tp, 6), "sample": len(sample),
@@ -703,7 +715,8 @@ def main():
     # ---- learned warm start + batched refinement --------------------------
     if not args.no_learned:
         out["learned_warm_start"] = learned_leg(H, np, torch, gpl1, instances, args.learned_train,
-                                                args.learned_eval, args.learned_epochs)
+                                                args.learned_eval, args.learned_epochs,
+                                                oracle_check=0 if args.no_cpu_baseline else 100)
 
     # ---- CPU oracle baseline + parity at 500 iterations --------------------
     if not args.no_cpu_baseline:
