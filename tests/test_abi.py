@@ -83,3 +83,29 @@ def test_null_handle_is_rejected_without_gpu_work():
                            C.byref(res), None) == -1
     assert lib.gp_destroy(None) == 0
     assert lib.gp_l1_project(None, 0, None, 0, 1.0, None, None, None) == -1
+
+
+def test_missing_library_fails_loudly(monkeypatch):
+    # no fallback path: without the built library every entry point raises
+    monkeypatch.setattr(gpl1, "_lib", None)
+    monkeypatch.setattr(gpl1, "LIB_PATH", "/nonexistent/libgpl1.so")
+    with pytest.raises(RuntimeError, match="missing"):
+        gpl1.load()
+    with pytest.raises(RuntimeError):
+        gpl1.default_opts()
+
+
+def test_option_helpers_without_gpu():
+    # per-problem targets are carried as a host array kept alive by the struct
+    o = gpl1.default_opts(f_targets=[1.0, 2.5, 3.0], x0_fallback=1, profile=8)
+    assert o.x0_fallback == 1 and o.profile == 8
+    assert [o.f_targets[i] for i in range(3)] == [1.0, 2.5, 3.0]
+    gpl1._check_targets(o, 3)
+    with pytest.raises(ValueError):
+        gpl1._check_targets(o, 4)
+    assert not gpl1.default_opts(f_targets=None).f_targets
+    # the tuned-shape lookup adds the table's kernel shape unless one is given
+    kw = gpl1._tuned(gpl1.GP_F32, 4096, 16384, {})
+    assert {"fused_cfg", "fused_grid", "fused_interleave"} <= set(kw)
+    assert gpl1._tuned(gpl1.GP_F32, 4096, 16384, {"fused_cfg": 2}) == {"fused_cfg": 2}
+    assert gpl1._tuned(gpl1.GP_F32, 3, 5, {}) == {}

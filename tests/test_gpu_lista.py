@@ -125,6 +125,26 @@ def test_forward_with_bf16_activations(H):
     net.close()
 
 
+def test_forward_in_slices(H):
+    say("[lista] forward over 1100 samples (two slices of the activation buffers), projected")
+    n, p, L, B = 48, 160, 3, 1100
+    K, Y, Xt = _problem(n, p, B, 4, seed=61)
+    lam = 0.1 * np.abs(K.T @ Y[0]).max()
+    We, S, th = _weights(K, lam, seed=13)
+    ths = _bf(np.full(L, th))
+    net = _net(H, n, p, L, We, S, ths)
+    rho = np.abs(Xt).sum(axis=1) * 0.7
+    Yd = _dev(Y)
+    raw = net.forward(Yd).cpu().double().numpy()
+    proj = net.forward(Yd, rho=rho).cpu().double().numpy()
+    ref, _, _ = olista.forward(We, S, ths, Y.T)
+    assert np.abs(raw - ref.T).max() <= 1e-5 * np.abs(ref).max()
+    for b in (0, 1023, 1024, 1099):
+        pr = project_l1(raw[b], rho[b])
+        assert np.abs(proj[b] - pr).max() <= 1e-6 * max(1.0, np.abs(pr).max())
+    net.close()
+
+
 def test_ista_initialisation(H):
     say("[lista] initialisation from K equals the ISTA weights")
     n, p, L = 96, 300, 5
