@@ -76,7 +76,7 @@ typedef struct {
     int32_t refresh_every;/* recompute r = Kx - y, g = 2K^T r every R iters (0 = never) */
     int32_t backtrack_cap;/* max reductions of the line-search step            */
     int32_t chunk;        /* iterations enqueued between host status polls     */
-    int32_t fused_cfg;    /* tuning: fused K/K^T kernel shape, 1..10 (0 = automatic) */
+    int32_t fused_cfg;    /* tuning: fused K/K^T kernel shape, 1..12 (0 = automatic) */
     int32_t fused_grid;   /* tuning: workgroups (row slabs) of that kernel (0 = automatic) */
     int32_t profile;      /* k > 0: time the fused K/K^T launch of every k-th iteration with HIP
                              events stamped by the launch itself (result.t_fused_ms over

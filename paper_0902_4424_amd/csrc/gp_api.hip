@@ -128,10 +128,11 @@ int check_opts(gp_handle h, const gp_opts& o) {
 // workgroup = T * CPT * VEC.
 // (threads, column chunks per thread, rows per block, register buffers);
 // columns covered by one workgroup = T * CPT * VEC.
+// Shapes 11 and 12 keep the partial w in LDS (1024 threads, no spills).
 struct FusedCfg { int T, CPT, RB, NB; };
 static const FusedCfg kFusedCfgs[] = {
     {256, 1, 4, 2}, {256, 2, 4, 2}, {256, 4, 2, 2}, {512, 4, 2, 2}, {512, 8, 1, 2}, {1024, 8, 1, 2},
-    {256, 4, 1, 3}, {512, 4, 1, 3}, {512, 8, 1, 3}, {1024, 4, 1, 3},
+    {256, 4, 1, 3}, {512, 4, 1, 3}, {512, 8, 1, 3}, {1024, 4, 1, 3}, {1024, 4, 1, 2}, {1024, 2, 1, 3},
 };
 constexpr int kNumFusedCfgs = sizeof(kFusedCfgs) / sizeof(kFusedCfgs[0]);
 
@@ -170,22 +171,22 @@ struct FusedArgs {
     hipEvent_t ev0 = nullptr, ev1 = nullptr;   // timing: recorded by the launch itself
 };
 
-template <typename TK, typename ACC, int T, int CPT, int RB, int NB, bool AL>
+template <typename TK, typename ACC, int T, int CPT, int RB, int NB, bool AL, bool WL>
 void launch_fused_one(hipStream_t s, int64_t G, const FusedArgs& a) {
     if (a.ev0)   // start and stop stamped by the dispatch itself (no separate marker packets)
-        hipExtLaunchKernelGGL((k_fused<TK, ACC, T, CPT, RB, NB, AL>), dim3((unsigned)G), dim3(T), 0, s, a.ev0,
+        hipExtLaunchKernelGGL((k_fused<TK, ACC, T, CPT, RB, NB, AL, WL>), dim3((unsigned)G), dim3(T), 0, s, a.ev0,
                               a.ev1, 0, a.st, (const TK*)a.K, a.n, a.p, a.ldk, a.rows, a.v, a.vsub, a.g, a.ysub,
                               a.rvec, a.tout, (ACC*)a.wpart, a.ldw, a.spart, a.interleave, a.v32);
     else
-        hipLaunchKernelGGL((k_fused<TK, ACC, T, CPT, RB, NB, AL>), dim3((unsigned)G), dim3(T), 0, s, a.st,
+        hipLaunchKernelGGL((k_fused<TK, ACC, T, CPT, RB, NB, AL, WL>), dim3((unsigned)G), dim3(T), 0, s, a.st,
                            (const TK*)a.K, a.n, a.p, a.ldk, a.rows, a.v, a.vsub, a.g, a.ysub, a.rvec, a.tout,
                            (ACC*)a.wpart, a.ldw, a.spart, a.interleave, a.v32);
 }
 
-template <typename TK, typename ACC, int T, int CPT, int RB, int NB>
+template <typename TK, typename ACC, int T, int CPT, int RB, int NB, bool WL = false>
 void launch_fused_t(bool aligned, hipStream_t s, int64_t G, const FusedArgs& a) {
-    if (aligned) launch_fused_one<TK, ACC, T, CPT, RB, NB, true>(s, G, a);
-    else launch_fused_one<TK, ACC, T, CPT, RB, NB, false>(s, G, a);
+    if (aligned) launch_fused_one<TK, ACC, T, CPT, RB, NB, true, WL>(s, G, a);
+    else launch_fused_one<TK, ACC, T, CPT, RB, NB, false, WL>(s, G, a);
 }
 
 template <typename TK, typename ACC>
@@ -203,6 +204,8 @@ void launch_fused_dt(int cfg, bool aligned, hipStream_t s, int64_t G, const Fuse
         GPL1_FUSED_CASE(7, 512, 4, 1, 3)
         GPL1_FUSED_CASE(8, 512, 8, 1, 3)
         GPL1_FUSED_CASE(9, 1024, 4, 1, 3)
+        case 10: launch_fused_t<TK, ACC, 1024, 4, 1, 2, true>(aligned, s, G, a); break;
+        case 11: launch_fused_t<TK, ACC, 1024, 2, 1, 3, true>(aligned, s, G, a); break;
     }
 #undef GPL1_FUSED_CASE
 }

@@ -501,10 +501,13 @@ struct FusedBlock {
     // LDS (stage: y_i and r_i staged in, t_i buffered out) so that no global
     // access sits on the per-row path: vmcnt is in order, and waiting for a
     // scalar load would also wait for the prefetched rows of K.
+    // With `wl` (LDS, thread-private slots) the partial w is accumulated there
+    // instead of in registers.
     __device__ __forceinline__ static void process(const KVec<TK> (&buf)[RB][CPT], const ACC (&dv)[CPT][VEC],
                                                    ACC (&w)[CPT][VEC], double (*red)[RB][NW], int bi,
                                                    int64_t row0, int64_t r1, int kl, const double* s_y,
-                                                   const double* s_r, double* s_t, double& tt, double& tr) {
+                                                   const double* s_r, double* s_t, double& tt, double& tr,
+                                                   ACC* wl = nullptr) {
         const int lane = threadIdx.x & (WAVE - 1), wid = threadIdx.x / WAVE;
         double part[RB];
 #pragma unroll
@@ -535,10 +538,19 @@ struct FusedBlock {
                     tr += t * s_r[kl + r];
                 }
                 const ACC ta = (ACC)t;
+                if (wl) {
 #pragma unroll
-                for (int c = 0; c < CPT; ++c)
+                    for (int c = 0; c < CPT; ++c) {
+                        ACC* wp = wl + ((int64_t)c * T + threadIdx.x) * VEC;
 #pragma unroll
-                    for (int e = 0; e < VEC; ++e) w[c][e] += (ACC)buf[r][c].get(e) * ta;
+                        for (int e = 0; e < VEC; ++e) wp[e] += (ACC)buf[r][c].get(e) * ta;
+                    }
+                } else {
+#pragma unroll
+                    for (int c = 0; c < CPT; ++c)
+#pragma unroll
+                        for (int e = 0; e < VEC; ++e) w[c][e] += (ACC)buf[r][c].get(e) * ta;
+                }
             }
         }
     }
@@ -550,7 +562,7 @@ struct FusedBlock {
 // Body of the fused pass for workgroup `wg` of `ngroups` (the slab index and
 // slab count of one problem); `wrow` and `sp` are this workgroup's partial
 // vector and partial dots.
-template <typename TK, typename ACC, int T, int CPT, int RB, int NB, bool ALIGNED>
+template <typename TK, typename ACC, int T, int CPT, int RB, int NB, bool ALIGNED, bool WL = false>
 __device__ __forceinline__ void fused_body(const TK* __restrict__ K, int64_t n, int64_t p, int64_t ldk,
                                            int64_t rows_per_wg, const double* __restrict__ v,
                                            const double* __restrict__ vsub, const double* __restrict__ g,
@@ -583,6 +595,10 @@ __device__ __forceinline__ void fused_body(const TK* __restrict__ K, int64_t n, 
     if (NB > 2 && first + step < lim) FB::template load<ALIGNED>(B, K, ldk, p, first + step, lim);
 
     ACC dv[CPT][VEC], w[CPT][VEC];
+    // WL: the partial w lives in LDS (thread-private float4/double2 slots),
+    // which frees its registers for wide workgroups
+    __shared__ __attribute__((aligned(16))) ACC wls[WL ? CPT * T * VEC : 1];
+    ACC* wl = WL ? wls : nullptr;
     // the multiplied vector: its float copy when the caller has one (ACC is
     // float then, so the products are the same), else v - vsub in double
 #pragma unroll
@@ -594,6 +610,7 @@ __device__ __forceinline__ void fused_body(const TK* __restrict__ K, int64_t n, 
             if (v32) dv[c][e] = j < p ? (ACC)v32[j] : (ACC)0;
             else dv[c][e] = j < p ? (ACC)(vsub ? v[j] - vsub[j] : v[j]) : (ACC)0;
             w[c][e] = 0;
+            if constexpr (WL) wls[((int64_t)c * T + tid) * VEC + e] = 0;
         }
     }
     double tt = 0.0, tr = 0.0;
@@ -627,7 +644,7 @@ __device__ __forceinline__ void fused_body(const TK* __restrict__ K, int64_t n, 
     int64_t blk = 0;    // row-block counter
     auto run = [&](const KVec<TK> (&buf)[RB][CPT], int64_t row) {
         if (kl == FCH || chunk_first < 0) stage(blk);
-        FB::process(buf, dv, w, red, bi, row, lim, kl, s_y, s_r, s_t, tt, tr);
+        FB::process(buf, dv, w, red, bi, row, lim, kl, s_y, s_r, s_t, tt, tr, wl);
         bi ^= 1;
         kl += RB;
         ++blk;
@@ -680,7 +697,7 @@ __device__ __forceinline__ void fused_body(const TK* __restrict__ K, int64_t n, 
         const int64_t col = ((int64_t)c * T + tid) * VEC;
         if (col < ldw) {
 #pragma unroll
-            for (int e = 0; e < VEC; ++e) wrow[col + e] = w[c][e];
+            for (int e = 0; e < VEC; ++e) wrow[col + e] = WL ? wls[((int64_t)c * T + tid) * VEC + e] : w[c][e];
         }
     }
     if (tid == 0) {
@@ -692,7 +709,7 @@ __device__ __forceinline__ void fused_body(const TK* __restrict__ K, int64_t n, 
     }
 }
 
-template <typename TK, typename ACC, int T, int CPT, int RB, int NB, bool ALIGNED>
+template <typename TK, typename ACC, int T, int CPT, int RB, int NB, bool ALIGNED, bool WL = false>
 __global__ __launch_bounds__(T) void k_fused(const GPState* __restrict__ st, const TK* __restrict__ K,
                                                 int64_t n, int64_t p, int64_t ldk, int64_t rows_per_wg,
                                                 const double* __restrict__ v, const double* __restrict__ vsub,
@@ -702,7 +719,7 @@ __global__ __launch_bounds__(T) void k_fused(const GPState* __restrict__ st, con
                                                 double* __restrict__ spart, int interleave,
                                                 const float* __restrict__ v32) {
     if (!st->live) return;
-    fused_body<TK, ACC, T, CPT, RB, NB, ALIGNED>(K, n, p, ldk, rows_per_wg, v, vsub, g, ysub, rvec, tout,
+    fused_body<TK, ACC, T, CPT, RB, NB, ALIGNED, WL>(K, n, p, ldk, rows_per_wg, v, vsub, g, ysub, rvec, tout,
                                                  wpart + (int64_t)blockIdx.x * ldw, ldw,
                                                  spart + (int64_t)SPART * blockIdx.x, interleave,
                                                  (int64_t)blockIdx.x, (int64_t)gridDim.x, v32);

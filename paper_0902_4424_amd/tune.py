@@ -21,7 +21,7 @@ TABLE = os.path.join(PKG, "tuned.json")
 # configuration covers T * CPT * (16 / element size) columns.  Shape 6 spills
 # registers and is tried only when nothing else covers p.
 CFG_COVER = {1: (256, 1), 2: (256, 2), 3: (256, 4), 4: (512, 4), 5: (512, 8), 6: (1024, 8),
-             7: (256, 4), 8: (512, 4), 9: (512, 8), 10: (1024, 4)}
+             7: (256, 4), 8: (512, 4), 9: (512, 8), 10: (1024, 4), 11: (1024, 4), 12: (1024, 2)}
 ESIZE = {"f64": 8, "f32": 4, "bf16": 2}
 GRIDS = (64, 128, 192, 256, 384, 512)
 

@@ -307,3 +307,22 @@ def test_fp64_trajectory_matches_oracle(H, k):
     say(f"   x rel err {err:.2e}, f rel diff {abs(res['f'] - ref['f']) / ref['f']:.2e}")
     assert err <= 1e-10
     assert abs(res["f"] - ref["f"]) <= 1e-10 * ref["f"]
+
+
+def test_every_fused_shape_matches_oracle(H):
+    """Every fused-kernel shape the autotuner may choose (threads, column
+    chunks, row blocks, buffers, partial w in registers or LDS) and both row
+    orders give the oracle's solution at the FP32 bar."""
+    from paper_0902_4424_amd import tune
+    inst = instances.gaussian_instance(1024, 4096, 50, dtype="f32", seed=15)
+    ref = gpss(inst.K64, inst.y64, inst.rho, tol=0.0, max_iter=100000)
+    K, y = _K_tensor(inst), _dev(inst.y_store)
+    shapes = [c for c, (T, cpt) in tune.CFG_COVER.items() if T * cpt * 4 >= 4096]
+    assert {10, 11, 12} <= set(shapes)
+    for cfg in shapes:
+        for grid, il in ((64, 0), (256, 1)):
+            x, res = H.solve(K, y, inst.rho, tol=0.0, max_iter=5000, refresh_every=50,
+                             fused_cfg=cfg, fused_grid=grid, fused_interleave=il)
+            gap, err, _ = _gap_err(inst, x.cpu().numpy(), ref)
+            assert gap <= 1e-6 and err <= 1e-4, (cfg, grid, il, gap, err)
+    say(f"   {len(shapes)} shapes x 2 grids match")
