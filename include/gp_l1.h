@@ -88,6 +88,11 @@ typedef struct {
                                  instead (result.x0_rejected = 1).  Shared-K batches test it on the
                                  device in their first residual pass, gp_l1_solve with two extra
                                  residual passes; uneven batches return GP_E_UNSUPPORTED. */
+    int32_t graph;            /* gp_l1_solve: 1 = replay a captured HIP graph of one chunk of
+                                 iterations (refresh_every iterations, or chunk when refresh_every is
+                                 0; iterations outside whole chunks run as plain launches).  The
+                                 graph is kept in the handle while the problem's arguments are
+                                 unchanged.  Results are identical to graph = 0.  Not with profile. */
 } gp_opts;
 
 typedef struct {
@@ -108,7 +113,7 @@ typedef struct {
 typedef struct gp_handle_s* gp_handle;
 
 /* Fill `o` with the paper's GPSS parameters, max_iter = 100000,
- * f_target = -1 (off), f_targets = NULL, x0_fallback = 0, refresh_every = 0,
+ * f_target = -1 (off), f_targets = NULL, x0_fallback = 0, graph = 0, refresh_every = 0,
  * backtrack_cap = 60, chunk = 64, automatic kernel shapes. */
 void gp_opts_default(gp_opts* o);
 

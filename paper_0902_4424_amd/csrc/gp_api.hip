@@ -118,6 +118,7 @@ int check_opts(gp_handle h, const gp_opts& o) {
     if (o.chunk < 1) return fail(h, GP_E_ARG, "opts.chunk must be >= 1");
     if (std::isnan(o.f_target)) return fail(h, GP_E_ARG, "opts.f_target is NaN");
     if (o.profile < 0) return fail(h, GP_E_ARG, "opts.profile must be >= 0");
+    if (o.graph && o.profile) return fail(h, GP_E_ARG, "opts.graph and opts.profile exclude each other");
     return GP_OK_TOL;
 }
 
@@ -342,6 +343,7 @@ void gp_opts_default(gp_opts* o) {
     o->fused_interleave = 0;
     o->f_targets = nullptr;
     o->x0_fallback = 0;
+    o->graph = 0;
 }
 
 int gp_create(gp_handle* out, int device) {
@@ -369,6 +371,9 @@ int gp_destroy(gp_handle h) {
     if (h->ws) (void)hipFree(h->ws);
     if (h->host_state) (void)hipHostFree(h->host_state);
     for (hipEvent_t ev : h->events) (void)hipEventDestroy(ev);
+    if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
+    if (h->gevent) (void)hipEventDestroy(h->gevent);
+    if (h->gstream) (void)hipStreamDestroy(h->gstream);
     delete h;
     return GP_OK_TOL;
 }
@@ -448,6 +453,19 @@ int gp_l1_solve(gp_handle h, gp_dtype kdtype, const void* K, int64_t n, int64_t 
     rc = ensure_workspace(h, P.bytes);
     if (rc) return rc;
     hipStream_t s = (hipStream_t)stream;
+    const hipStream_t user_stream = s;
+    if (o.graph && !s) {
+        // a graph cannot be captured on the null stream: run on the handle's
+        // own stream, ordered after the caller's work
+        if (!h->gstream && (e = hipStreamCreateWithFlags(&h->gstream, hipStreamNonBlocking)) != hipSuccess)
+            return hip_fail(h, e, "graph stream");
+        if (!h->gevent && (e = hipEventCreateWithFlags(&h->gevent, hipEventDisableTiming)) != hipSuccess)
+            return hip_fail(h, e, "graph event");
+        e = hipEventRecord(h->gevent, user_stream);
+        if (e == hipSuccess) e = hipStreamWaitEvent(h->gstream, h->gevent, 0);
+        if (e != hipSuccess) return hip_fail(h, e, "graph stream order");
+        s = h->gstream;
+    }
     char* ws = (char*)h->ws;
     GPState* st = (GPState*)(ws + P.o_state);
     double* x = (double*)(ws + P.o_x);
@@ -511,9 +529,47 @@ int gp_l1_solve(gp_handle h, gp_dtype kdtype, const void* K, int64_t n, int64_t 
     e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(h, e, "init launch");
 
+    // graph mode: chunks of gch iterations starting at multiples of gch, each
+    // ending with the refresh that the plain schedule puts there
+    const int gch = o.refresh_every > 0 ? o.refresh_every : o.chunk;
+    auto graph_chunk = [&]() -> int {
+        const std::vector<int64_t> key = {(int64_t)kdtype, (int64_t)(uintptr_t)K, n, p, ldk, P.cfg, P.G,
+                                          aligned ? 1 : 0, il, (int64_t)(uintptr_t)h->ws, gch,
+                                          o.refresh_every, (int64_t)(uintptr_t)s};
+        if (!h->gexec || h->gkey != key) {
+            if (h->gexec) { (void)hipGraphExecDestroy(h->gexec); h->gexec = nullptr; }
+            hipGraph_t gr = nullptr;
+            hipError_t ce = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+            if (ce != hipSuccess) return hip_fail(h, ce, "graph capture");
+            for (int k = 0; k < gch; ++k) {
+                launch_proj(s, st, PM_ITER, p, x, g, d, upart, P.GU, vb, d32);
+                launch_fused(kdtype, P.cfg, aligned, s, P.G, fa_iter);
+                launch_update(kdtype, s, st, UM_ITER, spart, (int)P.G, wpart, P.ldw, p, n, x, g, d, r, q, upart);
+            }
+            if (o.refresh_every > 0) refresh();
+            ce = hipStreamEndCapture(s, &gr);
+            if (ce == hipSuccess) ce = hipGraphInstantiate(&h->gexec, gr, nullptr, nullptr, 0);
+            if (gr) (void)hipGraphDestroy(gr);
+            if (ce != hipSuccess) { h->gexec = nullptr; return hip_fail(h, ce, "graph instantiate"); }
+            h->gkey = key;
+        }
+        const hipError_t le = hipGraphLaunch(h->gexec, s);
+        return le == hipSuccess ? 0 : hip_fail(h, le, "graph launch");
+    };
+
     int it = 0;
     while (it < o.max_iter) {
-        const int end = std::min(o.max_iter, it + o.chunk);
+        if (o.graph && it % gch == 0 && it + gch < o.max_iter) {
+            rc = graph_chunk();
+            if (rc) return rc;
+            it += gch;
+            e = hipMemcpyAsync(h->host_state, st, sizeof(GPState), hipMemcpyDeviceToHost, s);
+            if (e == hipSuccess) e = hipStreamSynchronize(s);
+            if (e != hipSuccess) return hip_fail(h, e, "status poll");
+            if (h->host_state->done || h->host_state->stop_req) break;
+            continue;
+        }
+        const int end = o.graph ? std::min(o.max_iter, (it / gch + 1) * gch) : std::min(o.max_iter, it + o.chunk);
         for (; it < end; ++it) {
             launch_proj(s, st, PM_ITER, p, x, g, d, upart, P.GU, vb, d32);
             // every profile-th iteration's fused launch is bracketed by events

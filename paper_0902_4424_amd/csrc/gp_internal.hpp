@@ -17,6 +17,12 @@ struct gp_handle_s {
     void* extra = nullptr;               // batched-solver resources
     std::vector<hipEvent_t> events;      // profiling: start/stop pairs of fused launches
     int ev_used = 0;
+    // graph mode of the single-problem solver: a captured chunk of iterations,
+    // kept while the launch arguments it was captured with stay the same
+    hipStream_t gstream = nullptr;       // capture stream when the caller passes the null stream
+    hipEvent_t gevent = nullptr;         // orders it with the caller's stream
+    hipGraphExec_t gexec = nullptr;
+    std::vector<int64_t> gkey;           // the arguments of the captured chunk
 };
 
 namespace gpl1 {

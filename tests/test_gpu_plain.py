@@ -326,3 +326,42 @@ def test_every_fused_shape_matches_oracle(H):
             gap, err, _ = _gap_err(inst, x.cpu().numpy(), ref)
             assert gap <= 1e-6 and err <= 1e-4, (cfg, grid, il, gap, err)
     say(f"   {len(shapes)} shapes x 2 grids match")
+
+
+def test_graph_mode_matches_plain(H):
+    """Replaying captured chunks of iterations gives bit-identical results to
+    plain launches: on the caller's null stream and on a stream of its own,
+    with and without periodic refreshes, with a ragged last chunk, after a
+    switch to another problem (re-capture) and back, and with plain solves
+    in between the replays."""
+    say("[solve] graph mode vs plain launches")
+    a = instances.gaussian_instance(512, 2048, 20, dtype="f32", seed=5)
+    b = instances.gaussian_instance(300, 1100, 9, dtype="f64", seed=6)
+    Ka, ya = _K_tensor(a), _dev(a.y_store)
+    Kb, yb = _K_tensor(b), _dev(b.y_store)
+    side = torch.cuda.Stream()
+    cases = [
+        (Ka, ya, a.rho, dict(tol=0.0, max_iter=300), None),
+        (Ka, ya, a.rho, dict(tol=0.0, max_iter=203, refresh_every=25), None),
+        (Kb, yb, b.rho, dict(tol=1e-12, max_iter=5000, chunk=16), None),
+        (Ka, ya, a.rho, dict(tol=0.0, max_iter=300), side),
+        (Ka, ya, a.rho, dict(tol=1e-9, max_iter=100000), None),
+    ]
+    want = []
+    for K, y, rho, kw, s in cases:
+        with torch.cuda.stream(s or torch.cuda.current_stream()):
+            want.append(H.solve(K, y, rho, stream=s, **kw))
+        torch.cuda.synchronize()
+    for rep in range(3):
+        for i, (K, y, rho, kw, s) in enumerate(cases):
+            with torch.cuda.stream(s or torch.cuda.current_stream()):
+                x, r = H.solve(K, y, rho, stream=s, graph=1, **kw)
+                xp, rp = H.solve(K, y, rho, stream=s, **kw)   # plain solve between replays
+            torch.cuda.synchronize()
+            x0, r0 = want[i]
+            assert torch.equal(x, x0) and r == r0, (rep, i, r, r0)
+            assert torch.equal(xp, x0) and rp == r0
+    say(f"   {len(cases)} cases x 3 replays bit-identical")
+    with pytest.raises(gpl1.GPError) as e:
+        H.solve(Ka, ya, a.rho, graph=1, profile=4)
+    assert e.value.code == -1
