@@ -31,10 +31,11 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 ITERS = 500
 REFRESH = 50
-# the fused launch of every 8th iteration is timed with HIP events inside the
-# timed solves; an event pair on the stream costs a few microseconds, so timing
-# every launch would slow the iterations being measured
-PROFILE_EVERY = 8
+# the fused launch of every 16th iteration is timed with HIP events inside the
+# timed solves; a launch that stamps events leaves about 11 us of idle time
+# around it on the GPU, so timing every launch would slow the iterations being
+# measured (every 16th: under 1 us per iteration)
+PROFILE_EVERY = 16
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fused_traffic_gauss_4096x16384.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_0902_4424_amd", "csrc", f)
                   for f in ("gp_kernels.hpp", "gp_device.hpp")]

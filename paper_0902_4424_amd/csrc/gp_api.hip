@@ -220,42 +220,39 @@ void launch_fused(gp_dtype dt, int cfg, bool aligned, hipStream_t s, int64_t G, 
 // Projection shape: 256 threads when p fits 16 register slots of each
 // (fewer waves make the workgroup reductions of the threshold passes
 // cheaper), else 1024 threads with up to 22 slots, else the buffered path.
-int proj_threads(int64_t p) { return p <= 256 * 16 ? 256 : PROJ_T; }
+// Shape of the single-workgroup projection: threads T and register slots per
+// thread (pairs of neighbours, so at least 2; 0 streams through vbuf).  Eight
+// waves measured fastest from p = 4096 to 16384: fewer waves make each
+// threshold pass's workgroup reduction cheaper, more waves share the slots'
+// arithmetic.  x and g stay in registers while T * slots <= 16384.
+struct ProjShape { int T, vpt; };
 
-int proj_vpt(int64_t p) {
-    // register slots per thread (pairs of neighbours, so at least 2)
-    const int T = proj_threads(p);
-    const int64_t per = (p + T - 1) / T;
-    if (per <= 2) return 2;
-    if (per <= 4) return 4;
-    if (per <= 8) return 8;
-    if (per <= 16) return 16;
-    if (per <= 22) return 22;
-    return 0;
+ProjShape proj_shape(int64_t p) {
+    if (p <= 512 * 32) {
+        const int64_t per = (p + 511) / 512;
+        int v = 2;
+        while (v < per) v *= 2;
+        return {512, v};
+    }
+    if (p <= 1024 * 22) return {1024, 22};
+    return {1024, 0};
 }
 
 void launch_proj(hipStream_t s, GPState* st, int mode, int64_t p, double* x, const double* g, double* dout,
                  const double* upart, int GU, double* vbuf, float* d32) {
-    const int v = proj_vpt(p);
-    if (proj_threads(p) == 256) {
-        switch (v) {
-#define GPL1_PROJ_CASE(V) \
-    case V: hipLaunchKernelGGL((k_proj<V, 256>), dim3(1), dim3(256), 0, s, st, mode, p, x, g, dout, upart, GU, vbuf, d32); break;
-            GPL1_PROJ_CASE(2)
-            GPL1_PROJ_CASE(4)
-            GPL1_PROJ_CASE(8)
-            GPL1_PROJ_CASE(16)
-#undef GPL1_PROJ_CASE
-        }
-        return;
-    }
-    switch (v) {
-#define GPL1_PROJ_CASE(V) \
-    case V: hipLaunchKernelGGL((k_proj<V, PROJ_T>), dim3(1), dim3(PROJ_T), 0, s, st, mode, p, x, g, dout, upart, GU, vbuf, d32); break;
-        GPL1_PROJ_CASE(8)      // p in (4096, 8192]
-        GPL1_PROJ_CASE(16)
-        GPL1_PROJ_CASE(22)
-        GPL1_PROJ_CASE(0)
+    const ProjShape sh = proj_shape(p);
+    switch (sh.T * 100 + sh.vpt) {
+#define GPL1_PROJ_CASE(T, V) \
+    case T * 100 + V: \
+        hipLaunchKernelGGL((k_proj<V, T>), dim3(1), dim3(T), 0, s, st, mode, p, x, g, dout, upart, GU, vbuf, d32); \
+        break;
+        GPL1_PROJ_CASE(512, 2)
+        GPL1_PROJ_CASE(512, 4)
+        GPL1_PROJ_CASE(512, 8)
+        GPL1_PROJ_CASE(512, 16)
+        GPL1_PROJ_CASE(512, 32)
+        GPL1_PROJ_CASE(1024, 22)
+        GPL1_PROJ_CASE(1024, 0)
 #undef GPL1_PROJ_CASE
     }
 }
@@ -484,9 +481,15 @@ int gp_l1_solve(gp_handle h, gp_dtype kdtype, const void* K, int64_t n, int64_t 
     const bool aligned = (ldk % vec == 0) && (((uintptr_t)K) % 16 == 0);
     const bool f64v = kdtype == GP_F64;
 
-    hipLaunchKernelGGL(k_init_state, dim3(1), dim3(1), 0, s, st, make_params(o, rho, tol));
-    if (f64v) { launch_to_f64<double>(s, y, y64, n); launch_to_f64<double>(s, x0, x, p); }
-    else { launch_to_f64<float>(s, y, y64, n); launch_to_f64<float>(s, x0, x, p); }
+    {
+        const unsigned sg = (unsigned)((std::max(n, p) + 255) / 256);
+        if (f64v)
+            hipLaunchKernelGGL(k_setup<double>, dim3(sg), dim3(256), 0, s, st, make_params(o, rho, tol),
+                               (const double*)y, y64, n, (const double*)x0, x, p);
+        else
+            hipLaunchKernelGGL(k_setup<float>, dim3(sg), dim3(256), 0, s, st, make_params(o, rho, tol),
+                               (const float*)y, y64, n, (const float*)x0, x, p);
+    }
     if (x0) launch_proj(s, st, PM_INIT_X0, p, x, nullptr, nullptr, nullptr, 0, vb, nullptr);
     // r = K x - y, g = 2 K^T r, f = ||r||^2
     // d holds h = P(x - alpha g) between the projection and the update
@@ -557,16 +560,29 @@ int gp_l1_solve(gp_handle h, gp_dtype kdtype, const void* K, int64_t n, int64_t 
         return le == hipSuccess ? 0 : hip_fail(h, le, "graph launch");
     };
 
+    // status poll after a chunk: the finishing kernel goes first, so a poll
+    // that sees the solve stopped already holds its result (and x_out)
+    auto poll = [&](bool last) -> int {
+        if (f64v)
+            hipLaunchKernelGGL(k_finish<double>, dim3(1), dim3(PROJ_T), 0, s, st, x, g, p, last ? 1 : 0,
+                               (double*)x_out);
+        else
+            hipLaunchKernelGGL(k_finish<float>, dim3(1), dim3(PROJ_T), 0, s, st, x, g, p, last ? 1 : 0,
+                               (float*)x_out);
+        hipError_t pe = hipGetLastError();
+        if (pe == hipSuccess) pe = hipMemcpyAsync(h->host_state, st, sizeof(GPState), hipMemcpyDeviceToHost, s);
+        if (pe == hipSuccess) pe = hipStreamSynchronize(s);
+        return pe == hipSuccess ? 0 : hip_fail(h, pe, "status poll");
+    };
+    bool finished = false;
     int it = 0;
     while (it < o.max_iter) {
         if (o.graph && it % gch == 0 && it + gch < o.max_iter) {
             rc = graph_chunk();
             if (rc) return rc;
             it += gch;
-            e = hipMemcpyAsync(h->host_state, st, sizeof(GPState), hipMemcpyDeviceToHost, s);
-            if (e == hipSuccess) e = hipStreamSynchronize(s);
-            if (e != hipSuccess) return hip_fail(h, e, "status poll");
-            if (h->host_state->done || h->host_state->stop_req) break;
+            if ((rc = poll(false))) return rc;
+            if (h->host_state->done) { finished = true; break; }
             continue;
         }
         const int end = o.graph ? std::min(o.max_iter, (it / gch + 1) * gch) : std::min(o.max_iter, it + o.chunk);
@@ -587,19 +603,10 @@ int gp_l1_solve(gp_handle h, gp_dtype kdtype, const void* K, int64_t n, int64_t 
         }
         e = hipGetLastError();
         if (e != hipSuccess) return hip_fail(h, e, "iteration launch");
-        if (it < o.max_iter) {
-            e = hipMemcpyAsync(h->host_state, st, sizeof(GPState), hipMemcpyDeviceToHost, s);
-            if (e == hipSuccess) e = hipStreamSynchronize(s);
-            if (e != hipSuccess) return hip_fail(h, e, "status poll");
-            if (h->host_state->done || h->host_state->stop_req) break;
-        }
+        if ((rc = poll(it >= o.max_iter))) return rc;
+        if (h->host_state->done) { finished = true; break; }
     }
-    hipLaunchKernelGGL(k_finish, dim3(1), dim3(PROJ_T), 0, s, st, x, g, p);
-    if (f64v) launch_from_f64<double>(s, x, x_out, p);
-    else launch_from_f64<float>(s, x, x_out, p);
-    e = hipMemcpyAsync(h->host_state, st, sizeof(GPState), hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (e != hipSuccess) return hip_fail(h, e, "final sync");
+    if (!finished && (rc = poll(true))) return rc;
     fill_result(*h->host_state, res);
     res->x0_rejected = x0_rejected;
     if (o.profile) {

@@ -155,36 +155,58 @@ __device__ __forceinline__ double wave_max(double v) {
     return fmax(fmax(readlane_d(v, 0), readlane_d(v, 16)), fmax(readlane_d(v, 32), readlane_d(v, 48)));
 }
 
-// Workgroup sum of one double per thread.  `lds` holds T/64 doubles.  Every
-// thread receives the same value (wave partials added in wave order).
+// Sum (maximum) over groups of N neighbouring lanes, N in {1, 2, 4, 8, 16}:
+// the first log2(N) steps of the wave_sum butterfly; every lane of a group
+// holds the group's result.
+template <int N>
+__device__ __forceinline__ double group_sum(double v) {
+    static_assert(N == 1 || N == 2 || N == 4 || N == 8 || N == 16, "groups of 1 to 16 lanes");
+    if (N > 1) v += dpp_d<DPP_XOR1>(v);
+    if (N > 2) v += dpp_d<DPP_XOR2>(v);
+    if (N > 4) v += dpp_d<DPP_HALF_MIRROR>(v);
+    if (N > 8) v += dpp_d<DPP_MIRROR>(v);
+    return v;
+}
+template <int N>
+__device__ __forceinline__ double group_max(double v) {
+    static_assert(N == 1 || N == 2 || N == 4 || N == 8 || N == 16, "groups of 1 to 16 lanes");
+    if (N > 1) v = fmax(v, dpp_d<DPP_XOR1>(v));
+    if (N > 2) v = fmax(v, dpp_d<DPP_XOR2>(v));
+    if (N > 4) v = fmax(v, dpp_d<DPP_HALF_MIRROR>(v));
+    if (N > 8) v = fmax(v, dpp_d<DPP_MIRROR>(v));
+    return v;
+}
+
+// The workgroup reductions below post one value per wave into LDS and then
+// combine the T/64 posts lane-parallel: lane l of every wave reads post
+// l mod T/64 and a group butterfly over the first T/64 lanes forms the total,
+// which lane 0 hands to the whole wave.  Every thread receives the same value.
+
+// Workgroup sum of one double per thread.  `lds` holds T/64 doubles.
 template <int T>
 __device__ __forceinline__ double block_sum(double v, double* lds) {
+    constexpr int NWV = T / WAVE;
     v = wave_sum(v);
     const int lane = threadIdx.x & (WAVE - 1), wid = threadIdx.x / WAVE;
     __syncthreads();
     if (lane == 0) lds[wid] = v;
     __syncthreads();
-    double s = 0.0;
-#pragma unroll
-    for (int i = 0; i < T / WAVE; ++i) s += lds[i];
-    return s;
+    return readlane_d(group_sum<NWV>(lds[lane & (NWV - 1)]), 0);
 }
 
 template <int T>
 __device__ __forceinline__ double block_max(double v, double* lds) {
+    constexpr int NWV = T / WAVE;
     v = wave_max(v);
     const int lane = threadIdx.x & (WAVE - 1), wid = threadIdx.x / WAVE;
     __syncthreads();
     if (lane == 0) lds[wid] = v;
     __syncthreads();
-    double s = lds[0];
-#pragma unroll
-    for (int i = 1; i < T / WAVE; ++i) s = fmax(s, lds[i]);
-    return s;
+    return readlane_d(group_max<NWV>(lds[lane & (NWV - 1)]), 0);
 }
 
 // NS sums and NM maxima in one pass (one LDS exchange).  `lds` holds
-// (NS + NM) * T/64 doubles.  Every thread receives the same values.
+// (NS + NM) * T/64 doubles.
 template <int T, int NS, int NM>
 __device__ __forceinline__ void block_reduce(double (&s)[NS], double (&mx)[NM], double* lds) {
     constexpr int NWV = T / WAVE;
@@ -201,56 +223,40 @@ __device__ __forceinline__ void block_reduce(double (&s)[NS], double (&mx)[NM], 
         for (int i = 0; i < NM; ++i) lds[(NS + i) * NWV + wid] = mx[i];
     }
     __syncthreads();
+    const int l = lane & (NWV - 1);
 #pragma unroll
-    for (int i = 0; i < NS; ++i) {
-        double a = 0.0;
+    for (int i = 0; i < NS; ++i) s[i] = readlane_d(group_sum<NWV>(lds[i * NWV + l]), 0);
 #pragma unroll
-        for (int w = 0; w < NWV; ++w) a += lds[i * NWV + w];
-        s[i] = a;
-    }
-#pragma unroll
-    for (int i = 0; i < NM; ++i) {
-        double a = lds[(NS + i) * NWV];
-#pragma unroll
-        for (int w = 1; w < NWV; ++w) a = fmax(a, lds[(NS + i) * NWV + w]);
-        mx[i] = a;
-    }
+    for (int i = 0; i < NM; ++i) mx[i] = readlane_d(group_max<NWV>(lds[(NS + i) * NWV + l]), 0);
 }
 
-// Sum of (count, value) pairs in one pass (two LDS slots per wave).
-template <int T>
-__device__ __forceinline__ void block_sum2(int& c, double& v, double* lds) {
-    c = wave_sum(c);
-    v = wave_sum(v);
-    const int lane = threadIdx.x & (WAVE - 1), wid = threadIdx.x / WAVE;
-    __syncthreads();
-    if (lane == 0) { lds[2 * wid] = (double)c; lds[2 * wid + 1] = v; }
-    __syncthreads();
-    double cs = 0.0, vs = 0.0;
-#pragma unroll
-    for (int i = 0; i < T / WAVE; ++i) { cs += lds[2 * i]; vs += lds[2 * i + 1]; }
-    c = (int)cs;
-    v = vs;
+// Number of lanes of the wave for which `pred` holds (the same in every
+// lane).  Call from uniform control flow.
+__device__ __forceinline__ int wave_count(bool pred) {
+    return __builtin_popcountll(__builtin_amdgcn_ballot_w64(pred));
 }
 
-// block_sum2 for a loop of reductions with one barrier each: successive
-// calls alternate between two slot sets of `slots` (4 * T/64 doubles, used
-// by nothing else), so a wave writing the slots of call k + 1 never meets a
-// wave still reading those of call k - 1 (it passed call k's barrier first).
+// Workgroup sum of (count, value) pairs for a loop of reductions with one
+// barrier each.  `c` is a wave's count (the same in all its lanes, e.g. from
+// wave_count), `v` a value per lane.  Successive calls alternate between two
+// slot sets of `slots` (4 * T/64 doubles, used by nothing else), so a wave
+// writing the slots of call k + 1 never meets a wave still reading those of
+// call k - 1 (it passed call k's barrier first).
 template <int T>
 __device__ __forceinline__ void block_sum2_alt(int& c, double& v, double* slots, int parity) {
     constexpr int NWV = T / WAVE;
-    c = wave_sum(c);
+    // the count is formed here, not sunk into the posting lane's branch
+    // (which would keep every ballot mask of the caller alive until then)
+    asm volatile("" ::"s"(c));
     v = wave_sum(v);
     const int lane = threadIdx.x & (WAVE - 1), wid = threadIdx.x / WAVE;
     double* sl = slots + (parity & 1) * 2 * NWV;
     if (lane == 0) { sl[2 * wid] = (double)c; sl[2 * wid + 1] = v; }
     __syncthreads();
-    double cs = 0.0, vs = 0.0;
-#pragma unroll
-    for (int i = 0; i < NWV; ++i) { cs += sl[2 * i]; vs += sl[2 * i + 1]; }
-    c = (int)cs;
-    v = vs;
+    const int l = lane & (NWV - 1);
+    const double2 cv = *reinterpret_cast<const double2*>(sl + 2 * l);
+    c = (int)readlane_d(group_sum<NWV>(cv.x), 0);
+    v = readlane_d(group_sum<NWV>(cv.y), 0);
 }
 
 }  // namespace gpl1

@@ -145,7 +145,7 @@ __device__ __forceinline__ void l1_threshold_regs(const double (&vr)[NV], int64_
                                                   double* lds, double& m, double& t, bool& inside,
                                                   int& passes) {
     const int tid = threadIdx.x;
-    __shared__ double slots[4 * (T / WAVE)];   // the passes' reductions (one barrier each)
+    __shared__ __align__(16) double slots[4 * (T / WAVE)];   // the passes' reductions (one barrier each)
     double Sm_s[1] = {0.0}, Sm_m[1] = {0.0};
 #pragma unroll
     for (int e = 0; e < NV; ++e) {
@@ -171,7 +171,9 @@ __device__ __forceinline__ void l1_threshold_regs(const double (&vr)[NV], int64_
         for (int e = 0; e < NV; ++e) {
             const int j = 2 * ((e / 2) * T + tid) + (e & 1);
             const double b = fabs(vr[e]) - m;
-            if (j < p && b > t) { ++c; sum += b; }
+            const bool a = j < p && b > t;
+            c += wave_count(a);
+            if (a) sum += b;
         }
         block_sum2_alt<T>(c, sum, slots, passes);
         ++passes;
@@ -198,17 +200,19 @@ __global__ __launch_bounds__(T) void k_proj(GPState* __restrict__ st, int mode, 
                                                  const double* __restrict__ upart, int GU,
                                                  double* __restrict__ vbuf, float* __restrict__ d32) {
     constexpr int NV = VPT > 0 ? VPT : 1;
+    static_assert(NV <= 32, "the sign mask of the shifted slots has 32 bits");
     __shared__ double lds[3 * (T / WAVE)];
-    __shared__ double slots[4 * (T / WAVE)];   // the threshold passes' reductions
+    __shared__ __align__(16) double slots[4 * (T / WAVE)];   // the threshold passes' reductions
     __shared__ double sh_alpha, sh_mu;
     __shared__ GPState S;
     const int tid = threadIdx.x;
     // x and g are requested first so that their latency overlaps the state
     // load and the steplength rule; v = x - alpha g is formed once alpha is
-    // known (up to 16 slots per thread; beyond that g would not fit in
-    // registers and both are read after the steplength rule).  g is not read
-    // in the modes that have none.
-    constexpr bool PREF = VPT > 0 && VPT <= 16;
+    // known (up to 32 slots per thread and 16384 per workgroup, where x and
+    // g fit in the registers that T threads leave per lane; beyond that both
+    // are read after the steplength rule).  g is not read in the modes that
+    // have none.
+    constexpr bool PREF = VPT > 0 && VPT <= 32 && VPT * T <= 16384;
     // x kept per thread in LDS (slot e of thread tid at e*T + tid) for the
     // float copy of d at the end, instead of a second read from memory
     __shared__ double xkeep[PREF ? NV * T : 1];
@@ -356,13 +360,17 @@ __global__ __launch_bounds__(T) void k_proj(GPState* __restrict__ st, int mode, 
             double sum = 0.0;
             if (VPT > 0) {
 #pragma unroll
-                for (int e = 0; e < NV; ++e)
-                    if (vr[e] > t) { ++c; sum += vr[e]; }
+                for (int e = 0; e < NV; ++e) {
+                    const bool a = vr[e] > t;
+                    c += wave_count(a);
+                    if (a) sum += vr[e];
+                }
             } else {
                 for (int64_t j = tid; j < p; j += T) {
                     const double b = fabs(vbuf[j]) - m;
                     if (b > t) { ++c; sum += b; }
                 }
+                c = wave_sum(c);
             }
             block_sum2_alt<T>(c, sum, slots, passes);
             ++passes;
@@ -395,7 +403,38 @@ __global__ __launch_bounds__(T) void k_proj(GPState* __restrict__ st, int mode, 
     if (mode == PM_ITER) {
         // h = P(x - alpha g); the direction d = h - x and its dots are formed
         // by the multi-workgroup kernels that read h next
-        if (VPT > 0) {
+        if (keep_x && shifted) {
+            // the usual case, without branches: x from LDS, h from the
+            // shifted slots (slots past p hold b = -inf and give h = 0)
+            auto hs = [&](int e) {
+                const double a = fmax(vr[e] - t, 0.0);
+                return ((neg >> e) & 1u) ? -a : a;
+            };
+            if ((int64_t)NV * T == p) {
+#pragma unroll
+                for (int e = 0; e < NV; e += 2) {
+                    const int j = 2 * ((e / 2) * T + tid);
+                    const double h0 = hs(e), h1 = hs(e + 1);
+                    const double x0 = xkeep[PREF ? e * T + tid : 0], x1 = xkeep[PREF ? (e + 1) * T + tid : 0];
+                    *reinterpret_cast<double2*>(dout + j) = make_double2(h0, h1);
+                    *reinterpret_cast<float2*>(d32 + j) = make_float2((float)(h0 - x0), (float)(h1 - x1));
+                }
+            } else {
+#pragma unroll
+                for (int e = 0; e < NV; e += 2) {
+                    const int j = 2 * ((e / 2) * T + tid);
+                    const double h0 = hs(e), h1 = hs(e + 1);
+                    const double x0 = xkeep[PREF ? e * T + tid : 0], x1 = xkeep[PREF ? (e + 1) * T + tid : 0];
+                    if (j + 1 < p) {
+                        *reinterpret_cast<double2*>(dout + j) = make_double2(h0, h1);
+                        *reinterpret_cast<float2*>(d32 + j) = make_float2((float)(h0 - x0), (float)(h1 - x1));
+                    } else if (j < p) {
+                        dout[j] = h0;
+                        d32[j] = (float)(h0 - x0);
+                    }
+                }
+            }
+        } else if (VPT > 0) {
 #pragma unroll
             for (int e = 0; e < NV; e += 2) {
                 const int j = 2 * ((e / 2) * T + tid);
@@ -907,7 +946,7 @@ __global__ __launch_bounds__(UPD_T) void k_update(GPState* __restrict__ st, int 
 // ---------------------------------------------------------------------------
 // small helpers
 // ---------------------------------------------------------------------------
-static __global__ void k_init_state(GPState* st, GPParams prm) {
+__device__ __forceinline__ void init_state(GPState* st, const GPParams& prm) {
     GPState s = {};
     s.prm = prm;
     s.live = 1;
@@ -917,6 +956,19 @@ static __global__ void k_init_state(GPState* st, GPParams prm) {
     s.hpos = 0;
     s.nhist = 0;
     *st = s;
+}
+
+static __global__ void k_init_state(GPState* st, GPParams prm) { init_state(st, prm); }
+
+// Start of a solve in one launch: the state, y and x0 widened to double
+// (x = 0 without x0).
+template <typename TV>
+__global__ void k_setup(GPState* __restrict__ st, GPParams prm, const TV* __restrict__ y, double* __restrict__ y64,
+                        int64_t n, const TV* __restrict__ x0, double* __restrict__ x, int64_t p) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y64[i] = (double)y[i];
+    if (i < p) x[i] = x0 ? (double)x0[i] : 0.0;
+    if (i == 0) init_state(st, prm);
 }
 
 template <typename TV>
@@ -931,14 +983,26 @@ __global__ void k_from_f64(const double* __restrict__ in, TV* __restrict__ out, 
     if (i < n) out[i] = (TV)in[i];
 }
 
-// Commit the last update and compute ||x||_1 and ||g||_inf for the result.
-static __global__ __launch_bounds__(PROJ_T) void k_finish(GPState* __restrict__ st, const double* __restrict__ x,
-                                                   const double* __restrict__ g, int64_t p) {
+// End of a solve: commit the last update, ||x||_1 and ||g||_inf for the
+// result, and x narrowed into the caller's output.  Launched after every
+// chunk of iterations; it does nothing unless the solve has stopped (done or
+// stop_req) or `force` is set (the iteration budget is spent), so the host's
+// status poll after a chunk already finds the finished result.
+template <typename TV>
+__global__ __launch_bounds__(PROJ_T) void k_finish(GPState* __restrict__ st, const double* __restrict__ x,
+                                                   const double* __restrict__ g, int64_t p, int force,
+                                                   TV* __restrict__ x_out) {
     __shared__ double lds[PROJ_T / WAVE];
+    __shared__ int go;
+    if (threadIdx.x == 0) go = force || st->done || st->stop_req;
+    __syncthreads();
+    if (!go) return;
     double l1 = 0.0, gm = 0.0;
     for (int64_t j = threadIdx.x; j < p; j += PROJ_T) {
-        l1 += fabs(x[j]);
+        const double xj = x[j];
+        l1 += fabs(xj);
         gm = fmax(gm, fabs(g[j]));
+        x_out[j] = (TV)xj;
     }
     l1 = block_sum<PROJ_T>(l1, lds);
     gm = block_max<PROJ_T>(gm, lds);
