@@ -119,6 +119,87 @@ __device__ __forceinline__ void ss_update(GPState* st, int k, double ss, double 
     }
 }
 
+// The projection's scalar step in an iteration: commit_pending, then (when the
+// last update left its dots) ss_update, with the same arithmetic.  Every field
+// it reads is loaded up front and the alpha^(2) window is kept in registers,
+// so the single thread that runs it waits for LDS once instead of once per
+// dependent access.
+__device__ __forceinline__ void iter_rule(GPState& S, bool need_ss, double dw, double ww) {
+    const int pending = S.pending, k_new = S.k_new, k0 = S.k, hpos0 = S.hpos, nhist0 = S.nhist;
+    const double f_new = S.f_new, lam = S.lam, dd = S.dd, tau = S.tau;
+    const double amin = S.prm.amin, amax = S.prm.amax;
+    const int Malpha = S.prm.Malpha, na2 = S.na2;
+    int a2k[MAX_RING];
+    double a2v[MAX_RING];
+#pragma unroll
+    for (int i = 0; i < MAX_RING; ++i) { a2k[i] = S.a2k[i]; a2v[i] = S.a2v[i]; }
+
+    int k = k0;
+    if (pending) {
+        int hpos = hpos0;
+        if (k_new != k0) {                  // a new iterate: push f into the ring
+            hpos = (hpos0 + 1) % MAX_M;
+            S.hpos = hpos;
+            S.nhist = nhist0 < MAX_M ? nhist0 + 1 : nhist0;
+        }
+        S.fhist[hpos] = f_new;
+        S.f = f_new;
+        S.k = k_new;
+        S.pending = 0;
+        k = k_new;
+    }
+    if (!need_ss) return;
+    S.ss_pending = 0;
+    // s = lam d, z = 2 lam w (w = K^T K d): s's = lam^2 d'd, s'z = 2 lam^2 d'w,
+    // z'z = 4 lam^2 w'w (equation (5))
+    const double l2 = lam * lam;
+    const double ss = l2 * dd, sz = 2.0 * l2 * dw, zz = 4.0 * l2 * ww;
+    if (!(sz > 0.0)) {
+        S.alpha = amax;
+        S.rule = 0;
+        return;
+    }
+    const double a1 = fmax(amin, fmin(ss / sz, amax));
+    const double a2 = zz > 0.0 ? fmax(amin, fmin(sz / zz, amax)) : amax;
+    const int first = k - Malpha > 1 ? k - Malpha : 1;
+    // keep the recorded entries of iterations >= first, in order
+    int nk[MAX_RING] = {}, m = 0;
+    double nv[MAX_RING] = {};
+#pragma unroll
+    for (int i = 0; i < MAX_RING; ++i) {
+        const bool keep = i < na2 && a2k[i] >= first;
+#pragma unroll
+        for (int o = 0; o < MAX_RING; ++o)
+            if (keep && m == o) { nk[o] = a2k[i]; nv[o] = a2v[i]; }
+        m += keep ? 1 : 0;
+    }
+    if (m == MAX_RING) {                    // cannot happen for M_alpha <= 3
+#pragma unroll
+        for (int o = 0; o + 1 < MAX_RING; ++o) { nk[o] = nk[o + 1]; nv[o] = nv[o + 1]; }
+        --m;
+    }
+#pragma unroll
+    for (int o = 0; o < MAX_RING; ++o)
+        if (o == m) { nk[o] = k; nv[o] = a2; }
+    const int nn = m + 1;
+#pragma unroll
+    for (int o = 0; o < MAX_RING; ++o) { S.a2k[o] = nk[o]; S.a2v[o] = nv[o]; }
+    S.na2 = nn;
+    if (a2 / a1 <= tau) {
+        double a = nv[0];
+#pragma unroll
+        for (int o = 1; o < MAX_RING; ++o)
+            if (o < nn) a = fmin(a, nv[o]);
+        S.alpha = a;
+        S.tau = tau * 0.9;
+        S.rule = 2;
+    } else {
+        S.alpha = a1;
+        S.tau = tau * 1.1;
+        S.rule = 1;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // k_proj: projection onto the l1 ball by a parallel threshold search.
 //
@@ -259,14 +340,7 @@ __global__ __launch_bounds__(T) void k_proj(GPState* __restrict__ st, int mode, 
         double none[1] = {0.0};
         if (need_ss) block_reduce<T, 2, 1>(dots, none, lds);
         if (tid == 0) {
-            commit_pending(&S);
-            if (need_ss) {
-                // s = lam d, z = 2 lam w (w = K^T K d): s's = lam^2 d'd,
-                // s'z = 2 lam^2 d'w, z'z = 4 lam^2 w'w (equation (5))
-                const double l2 = S.lam * S.lam;
-                ss_update(&S, S.k, l2 * S.dd, 2.0 * l2 * dots[0], 4.0 * l2 * dots[1]);
-                S.ss_pending = 0;
-            }
+            iter_rule(S, need_ss != 0, dots[0], dots[1]);
             sh_alpha = S.alpha;
             sh_mu = S.mu;
         }
@@ -780,16 +854,41 @@ __global__ __launch_bounds__(UPD_T) void k_update(GPState* __restrict__ st, int 
     constexpr int VU = 16 / (int)sizeof(ACC);   // columns per vector load
     constexpr int CQ = UPD_COLS / VU;           // column vectors per workgroup
     constexpr int NG = T / CQ;                  // partial groups
+    using V16 = typename std::conditional<VU == 4, float4, double2>::type;
     __shared__ double red[NG][UPD_COLS];
     __shared__ GPState S;
+    __shared__ double sh5[5];
     const int tid = threadIdx.x, lane = tid & (WAVE - 1);
-    state_load(S, st);
-    __syncthreads();
-    if (!S.live) return;
-
+    const bool colwg = (int)blockIdx.x < nbp;
+    // Everything this workgroup reads that does not depend on the state is
+    // requested before the state, so the latencies overlap: the first eight
+    // partial vectors per thread, this thread's x, h, g (or r, q) entries,
+    // and the fused kernel's partial dots.
+    const int cq = tid % CQ, grp = tid / CQ;
+    const int64_t c0 = (int64_t)blockIdx.x * UPD_COLS;
+    const ACC* src = wpart + c0 + cq * VU;
+    V16 w8[8];
+    const bool pre8 = colwg && grp + 7 * NG < GF;
+    if (pre8) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) w8[u] = *reinterpret_cast<const V16*>(src + (int64_t)(grp + u * NG) * ldw);
+    }
+    const int64_t jc = c0 + tid;
+    const bool colj = colwg && tid < UPD_COLS && jc < p;
+    double xj = 0.0, hj = 0.0, gj = 0.0;
+    if (colj) {
+        xj = x[jc];
+        if (mode == UM_ITER) { hj = h[jc]; gj = g[jc]; }
+    }
+    const int64_t ir = (int64_t)(blockIdx.x - nbp) * UPD_ROWS + tid;
+    const bool rowi = !colwg && ir < n;
+    double ri = 0.0, qi = 0.0;
+    if (rowi) {
+        qi = tq[ir];
+        if (mode == UM_ITER) ri = r[ir];
+    }
     // (q'q, r'q, g'd, d'd, ||d||_inf) or (r'r) from the fused kernel's
     // partials, fixed order
-    __shared__ double sh5[5];
     if (tid < WAVE) {
         double a = 0.0, b = 0.0, c = 0.0, e = 0.0, mx = 0.0;
         for (int i = lane; i < GF; i += WAVE) {
@@ -803,7 +902,9 @@ __global__ __launch_bounds__(UPD_T) void k_update(GPState* __restrict__ st, int 
         mx = wave_max(mx);
         if (lane == 0) { sh5[0] = a; sh5[1] = b; sh5[2] = c; sh5[3] = e; sh5[4] = mx; }
     }
+    state_load(S, st);
     __syncthreads();
+    if (!S.live) return;
     const double qq = sh5[0], rq = sh5[1], gd = sh5[2], dd = sh5[3], dmax = sh5[4];
     if (mode == UM_ITER && (dmax == 0.0 || !(gd < 0.0))) {
         // h == x, or no descent left at working precision: stationary
@@ -841,24 +942,30 @@ __global__ __launch_bounds__(UPD_T) void k_update(GPState* __restrict__ st, int 
         }
     }
 
-    if ((int)blockIdx.x < nbp) {
+    if (colwg) {
         // ---- columns: w_j = sum of the fused kernel's partials ----
-        const int cq = tid % CQ, grp = tid / CQ;
-        const int64_t c0 = (int64_t)blockIdx.x * UPD_COLS;
         double acc[VU];
 #pragma unroll
         for (int e = 0; e < VU; ++e) acc[e] = 0.0;
-        const ACC* src = wpart + c0 + cq * VU;
-        using V16 = typename std::conditional<VU == 4, float4, double2>::type;
         int gi = grp;
         // eight partial vectors in flight per thread, summed in index order
-        for (; gi + 7 * NG < GF; gi += 8 * NG) {
-            V16 w8[8];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) w8[u] = *reinterpret_cast<const V16*>(src + (int64_t)(gi + u * NG) * ldw);
+        // (the first eight were requested at the start)
+        if (pre8) {
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
                 const ACC* pw = reinterpret_cast<const ACC*>(&w8[u]);
+#pragma unroll
+                for (int e = 0; e < VU; ++e) acc[e] += (double)pw[e];
+            }
+            gi += 8 * NG;
+        }
+        for (; gi + 7 * NG < GF; gi += 8 * NG) {
+            V16 wn[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) wn[u] = *reinterpret_cast<const V16*>(src + (int64_t)(gi + u * NG) * ldw);
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const ACC* pw = reinterpret_cast<const ACC*>(&wn[u]);
 #pragma unroll
                 for (int e = 0; e < VU; ++e) acc[e] += (double)pw[e];
             }
@@ -879,17 +986,15 @@ __global__ __launch_bounds__(UPD_T) void k_update(GPState* __restrict__ st, int 
 #pragma unroll
                 for (int i = 0; i < NG; ++i) w += red[i][tid];
             }
-            const int64_t j = c0 + tid;
-            if (tid < UPD_COLS && j < p) {
+            if (colj) {
                 if (mode == UM_ITER) {
-                    const double xj = x[j];
-                    const double dj = h[j] - xj;
-                    x[j] = xj + lam * dj;
-                    g[j] += 2.0 * lam * w;
+                    const double dj = hj - xj;
+                    x[jc] = xj + lam * dj;
+                    g[jc] = gj + 2.0 * lam * w;
                     dw = dj * w;
                     ww = w * w;
                 } else {
-                    g[j] = 2.0 * w;
+                    g[jc] = 2.0 * w;
                 }
             }
             dw = wave_sum(dw);
@@ -903,8 +1008,7 @@ __global__ __launch_bounds__(UPD_T) void k_update(GPState* __restrict__ st, int 
         }
     } else {
         // ---- rows: r += lam q, or r = K x - y on a refresh ----
-        const int64_t i = (int64_t)(blockIdx.x - nbp) * UPD_ROWS + tid;
-        if (i < n) r[i] = mode == UM_ITER ? r[i] + lam * tq[i] : tq[i];
+        if (rowi) r[ir] = mode == UM_ITER ? ri + lam * qi : qi;
         if (tid == 0) {
             upart[4 * blockIdx.x] = 0.0;
             upart[4 * blockIdx.x + 1] = 0.0;
