@@ -221,19 +221,22 @@ void launch_fused(gp_dtype dt, int cfg, bool aligned, hipStream_t s, int64_t G, 
 // (fewer waves make the workgroup reductions of the threshold passes
 // cheaper), else 1024 threads with up to 22 slots, else the buffered path.
 // Shape of the single-workgroup projection: threads T and register slots per
-// thread (pairs of neighbours, so at least 2; 0 streams through vbuf).  Eight
-// waves measured fastest from p = 4096 to 16384: fewer waves make each
-// threshold pass's workgroup reduction cheaper, more waves share the slots'
-// arithmetic.  x and g stay in registers while T * slots <= 16384.
+// thread (pairs of neighbours, so at least 2; 0 streams through vbuf).
+// Measured (kernel durations of one process, p = 2048 to 16384): eight waves
+// up to p = 8192, where fewer waves make each threshold pass's workgroup
+// reduction cheaper; sixteen waves above, where the single workgroup's loads
+// of x and g and its stores of h and d dominate.  x and g stay in registers
+// while T * slots <= 16384.
 struct ProjShape { int T, vpt; };
 
 ProjShape proj_shape(int64_t p) {
-    if (p <= 512 * 32) {
+    if (p <= 512 * 16) {
         const int64_t per = (p + 511) / 512;
         int v = 2;
         while (v < per) v *= 2;
         return {512, v};
     }
+    if (p <= 1024 * 16) return {1024, 16};
     if (p <= 1024 * 22) return {1024, 22};
     return {1024, 0};
 }
@@ -249,8 +252,8 @@ void launch_proj(hipStream_t s, GPState* st, int mode, int64_t p, double* x, con
         GPL1_PROJ_CASE(512, 2)
         GPL1_PROJ_CASE(512, 4)
         GPL1_PROJ_CASE(512, 8)
-        GPL1_PROJ_CASE(512, 16)
-        GPL1_PROJ_CASE(512, 32)
+        GPL1_PROJ_CASE(512, 16)      // p in (4096, 8192]
+        GPL1_PROJ_CASE(1024, 16)     // p in (8192, 16384]
         GPL1_PROJ_CASE(1024, 22)
         GPL1_PROJ_CASE(1024, 0)
 #undef GPL1_PROJ_CASE

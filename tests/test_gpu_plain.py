@@ -192,8 +192,9 @@ def test_fp32_illconditioned(H):
     assert g_gpu <= max(10 * g_ora, 1e-6)
 
 
-# p covers every projection shape: 512 threads with 2..32 register slots
-# (ragged tails included), 1024 threads with 22 slots, and the streamed form
+# p covers every projection shape: 512 threads with 2..16 register slots,
+# 1024 threads with 16 and 22 slots (ragged tails included), and the
+# streamed form
 @pytest.mark.parametrize("p", [1, 3, 1001, 4097, 8191, 16383, 20001, 30001])
 def test_ragged_and_padded_shapes(H, p):
     say(f"[solve] ragged p={p}")
