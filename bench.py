@@ -66,6 +66,25 @@ def measured_traffic():
     return t.get("bytes_per_launch")
 
 
+def host_info():
+    """CPU model and core counts of the machine the bench runs on."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"cpu_model": model, "logical_cpus": os.cpu_count(), "usable_cpus": usable,
+            "blas_threads": blas_threads()}
+
+
 def blas_threads():
     try:
         from threadpoolctl import threadpool_info
@@ -573,6 +592,8 @@ def main():
     ap.add_argument("--no-configs", action="store_true",
                     help="skip the FP64 256x1024 and ill-conditioned 4096x4096 legs")
     ap.add_argument("--no-mall", action="store_true", help="skip the 512 MiB K check")
+    ap.add_argument("--no-cold", action="store_true",
+                    help="skip the solves timed after an Infinity Cache flush")
     ap.add_argument("--learned-train", type=int, default=100000,
                     help="training pairs of the learned leg")
     ap.add_argument("--learned-eval", type=int, default=10000,
@@ -671,6 +692,28 @@ def main():
                      "alg_bytes_per_launch": alg_bytes,
                      "avg_launch_us": round(avg_fused_s * 1e6, 2)},
     }
+
+    # ---- the same solves with the Infinity Cache flushed first -------------
+    # (outside the timed region above: a 512 MiB scratch write before each
+    # solve, then the solve alone is timed)
+    if not args.no_cold:
+        scratch = torch.empty(128 << 20, dtype=torch.float32, device=dev)
+        tcold = 0.0
+        icold = 0
+        for i in range(3):
+            scratch.fill_(float(i))
+            torch.cuda.synchronize()
+            t0c = time.perf_counter()
+            _, rc = H.solve(K, y, inst.rho, tol=0.0, opts=opts)
+            torch.cuda.synchronize()
+            tcold += time.perf_counter() - t0c
+            icold += rc["iters"]
+        del scratch
+        out["cold_cache"] = {"value": round(icold / tcold, 2), "unit": "iterations/s",
+                             "sample": "3 solves, each after a 512 MiB scratch write that evicts the "
+                                       "256 MB Infinity Cache"}
+        log(f"cold cache: {icold / tcold:.1f} it/s")
+    out["host"] = host_info()
 
     # ---- wall time to a 1e-6 relative objective gap ----------------------
     K64 = y64 = None
