@@ -261,16 +261,16 @@ void launch_proj(hipStream_t s, GPState* st, int mode, int64_t p, double* x, con
 }
 
 void launch_update(gp_dtype dt, hipStream_t s, GPState* st, int mode, const double* spart, int GF,
-                   const void* wpart, int64_t ldw, int64_t p, int64_t n, double* x, double* g, const double* h,
+                   const void* wpart, int64_t ldw, int64_t p, int64_t n, double* x, double* g,
                    double* r, const double* tq, double* upart) {
     const int nbp = (int)((p + UPD_COLS - 1) / UPD_COLS);
     const int nbn = (int)((n + UPD_ROWS - 1) / UPD_ROWS);
     if (dt == GP_F64)
         hipLaunchKernelGGL(k_update<double>, dim3(nbp + nbn), dim3(UPD_T), 0, s, st, mode, spart, GF,
-                           (const double*)wpart, ldw, p, n, nbp, x, g, h, r, tq, upart);
+                           (const double*)wpart, ldw, p, n, nbp, x, g, r, tq, upart);
     else
         hipLaunchKernelGGL(k_update<float>, dim3(nbp + nbn), dim3(UPD_T), 0, s, st, mode, spart, GF,
-                           (const float*)wpart, ldw, p, n, nbp, x, g, h, r, tq, upart);
+                           (const float*)wpart, ldw, p, n, nbp, x, g, r, tq, upart);
 }
 
 template <typename TV>
@@ -495,14 +495,17 @@ int gp_l1_solve(gp_handle h, gp_dtype kdtype, const void* K, int64_t n, int64_t 
     }
     if (x0) launch_proj(s, st, PM_INIT_X0, p, x, nullptr, nullptr, nullptr, 0, vb, nullptr);
     // r = K x - y, g = 2 K^T r, f = ||r||^2
-    // d holds h = P(x - alpha g) between the projection and the update
+    // an iteration stores no h: the projection leaves (alpha, m, t, mode) in
+    // the state and the float copy of d, and the fused and update kernels
+    // recompute h from x and g; d only parks P(x0) during the x0 check
     const int il = o.fused_interleave;
     const FusedArgs fa_refresh{st, K, n, p, ldk, P.rows, x, nullptr, nullptr, y64, nullptr, q, wpart, P.ldw, spart, il,
                                nullptr};
-    const FusedArgs fa_iter{st, K, n, p, ldk, P.rows, d, x, g, nullptr, r, q, wpart, P.ldw, spart, il, d32};
+    // iteration: h is recomputed from x and g inside the fused kernel (v NULL)
+    const FusedArgs fa_iter{st, K, n, p, ldk, P.rows, nullptr, x, g, nullptr, r, q, wpart, P.ldw, spart, il, d32};
     auto refresh = [&]() {
         launch_fused(kdtype, P.cfg, aligned, s, P.G, fa_refresh);
-        launch_update(kdtype, s, st, UM_REFRESH, spart, (int)P.G, wpart, P.ldw, p, n, x, g, d, r, q, upart);
+        launch_update(kdtype, s, st, UM_REFRESH, spart, (int)P.G, wpart, P.ldw, p, n, x, g, r, q, upart);
     };
     int x0_rejected = 0;
     if (x0 && o.x0_fallback) {
@@ -550,7 +553,7 @@ int gp_l1_solve(gp_handle h, gp_dtype kdtype, const void* K, int64_t n, int64_t 
             for (int k = 0; k < gch; ++k) {
                 launch_proj(s, st, PM_ITER, p, x, g, d, upart, P.GU, vb, d32);
                 launch_fused(kdtype, P.cfg, aligned, s, P.G, fa_iter);
-                launch_update(kdtype, s, st, UM_ITER, spart, (int)P.G, wpart, P.ldw, p, n, x, g, d, r, q, upart);
+                launch_update(kdtype, s, st, UM_ITER, spart, (int)P.G, wpart, P.ldw, p, n, x, g, r, q, upart);
             }
             if (o.refresh_every > 0) refresh();
             ce = hipStreamEndCapture(s, &gr);
@@ -601,7 +604,7 @@ int gp_l1_solve(gp_handle h, gp_dtype kdtype, const void* K, int64_t n, int64_t 
             } else {
                 launch_fused(kdtype, P.cfg, aligned, s, P.G, fa_iter);
             }
-            launch_update(kdtype, s, st, UM_ITER, spart, (int)P.G, wpart, P.ldw, p, n, x, g, d, r, q, upart);
+            launch_update(kdtype, s, st, UM_ITER, spart, (int)P.G, wpart, P.ldw, p, n, x, g, r, q, upart);
             if (o.refresh_every > 0 && (it + 1) % o.refresh_every == 0 && it + 1 < o.max_iter) refresh();
         }
         e = hipGetLastError();

@@ -274,6 +274,26 @@ __device__ __forceinline__ double l1_hval(double vj, double m, double t, bool in
     return vj < 0.0 ? -a : a;
 }
 
+// Scalars with which the iteration's projection formed h, read once by the
+// kernels that use h after it.
+struct ProjH {
+    double alpha, m, t;
+    int mode;
+};
+__device__ __forceinline__ ProjH proj_h_params(const GPState* st) {
+    return ProjH{st->alpha, st->pm, st->pt, st->hmode};
+}
+// h_j of the iteration's projection, recomputed from x_j and g_j with the
+// projection's own operations (so the same bits): v = x - alpha g as one
+// fused multiply-add, then the shifted soft threshold.
+__device__ __forceinline__ double proj_h(double xj, double gj, const ProjH& P) {
+    const double v = fma(-P.alpha, gj, xj);
+    if (P.mode == 1) return v;
+    if (P.mode == 2) return 0.0;
+    const double a = fmax((fabs(v) - P.m) - P.t, 0.0);
+    return v < 0.0 ? -a : a;
+}
+
 template <int VPT, int T>
 __global__ __launch_bounds__(T) void k_proj(GPState* __restrict__ st, int mode, int64_t p,
                                                  double* __restrict__ x, const double* __restrict__ g,
@@ -362,7 +382,7 @@ __global__ __launch_bounds__(T) void k_proj(GPState* __restrict__ st, int mode, 
         if (PREF) {
             if (use_g) {
 #pragma unroll
-                for (int e = 0; e < NV; ++e) vr[e] -= alpha * gr[PREF ? e : 0];
+                for (int e = 0; e < NV; ++e) vr[e] = fma(-alpha, gr[PREF ? e : 0], vr[e]);
             }
         } else {
 #pragma unroll
@@ -372,10 +392,10 @@ __global__ __launch_bounds__(T) void k_proj(GPState* __restrict__ st, int mode, 
                     const double2 x2 = *reinterpret_cast<const double2*>(x + j);
                     double2 g2 = make_double2(0.0, 0.0);
                     if (use_g) g2 = *reinterpret_cast<const double2*>(g + j);
-                    vr[e] = x2.x - alpha * g2.x;
-                    vr[e + 1] = x2.y - alpha * g2.y;
+                    vr[e] = fma(-alpha, g2.x, x2.x);
+                    vr[e + 1] = fma(-alpha, g2.y, x2.y);
                 } else {
-                    vr[e] = j < p ? (use_g ? x[j] - alpha * g[j] : x[j]) : 0.0;
+                    vr[e] = j < p ? (use_g ? fma(-alpha, g[j], x[j]) : x[j]) : 0.0;
                     if (NV > 1) vr[e + 1] = 0.0;
                 }
             }
@@ -388,7 +408,7 @@ __global__ __launch_bounds__(T) void k_proj(GPState* __restrict__ st, int mode, 
         }
     } else {
         for (int64_t j = tid; j < p; j += T) {
-            const double vj = use_g ? x[j] - alpha * g[j] : x[j];
+            const double vj = use_g ? fma(-alpha, g[j], x[j]) : x[j];
             vbuf[j] = vj;
             Sm_s[0] += fabs(vj);
             Sm_m[0] = fmax(Sm_m[0], fabs(vj));
@@ -475,8 +495,9 @@ __global__ __launch_bounds__(T) void k_proj(GPState* __restrict__ st, int mode, 
 
     // -- outputs ------------------------------------------------------------
     if (mode == PM_ITER) {
-        // h = P(x - alpha g); the direction d = h - x and its dots are formed
-        // by the multi-workgroup kernels that read h next
+        // h = P(x - alpha g).  Only the float copy of d = h - x is stored (for
+        // the products); the kernels that need h itself recompute it from x,
+        // g and (alpha, m, t, mode) with the same operations (proj_h).
         if (keep_x && shifted) {
             // the usual case, without branches: x from LDS, h from the
             // shifted slots (slots past p hold b = -inf and give h = 0)
@@ -490,7 +511,6 @@ __global__ __launch_bounds__(T) void k_proj(GPState* __restrict__ st, int mode, 
                     const int j = 2 * ((e / 2) * T + tid);
                     const double h0 = hs(e), h1 = hs(e + 1);
                     const double x0 = xkeep[PREF ? e * T + tid : 0], x1 = xkeep[PREF ? (e + 1) * T + tid : 0];
-                    *reinterpret_cast<double2*>(dout + j) = make_double2(h0, h1);
                     *reinterpret_cast<float2*>(d32 + j) = make_float2((float)(h0 - x0), (float)(h1 - x1));
                 }
             } else {
@@ -499,44 +519,35 @@ __global__ __launch_bounds__(T) void k_proj(GPState* __restrict__ st, int mode, 
                     const int j = 2 * ((e / 2) * T + tid);
                     const double h0 = hs(e), h1 = hs(e + 1);
                     const double x0 = xkeep[PREF ? e * T + tid : 0], x1 = xkeep[PREF ? (e + 1) * T + tid : 0];
-                    if (j + 1 < p) {
-                        *reinterpret_cast<double2*>(dout + j) = make_double2(h0, h1);
-                        *reinterpret_cast<float2*>(d32 + j) = make_float2((float)(h0 - x0), (float)(h1 - x1));
-                    } else if (j < p) {
-                        dout[j] = h0;
-                        d32[j] = (float)(h0 - x0);
-                    }
+                    if (j + 1 < p) *reinterpret_cast<float2*>(d32 + j) = make_float2((float)(h0 - x0), (float)(h1 - x1));
+                    else if (j < p) d32[j] = (float)(h0 - x0);
                 }
             }
-        } else if (VPT > 0) {
+        } else if (d32 && VPT > 0) {
 #pragma unroll
             for (int e = 0; e < NV; e += 2) {
                 const int j = 2 * ((e / 2) * T + tid);
                 if (NV > 1 && j + 1 < p) {
                     const double h0 = hreg(e), h1 = hreg(e + 1);
-                    *reinterpret_cast<double2*>(dout + j) = make_double2(h0, h1);
                     if (keep_x) {
                         const double x0 = xkeep[PREF ? e * T + tid : 0], x1 = xkeep[PREF ? (e + 1) * T + tid : 0];
                         *reinterpret_cast<float2*>(d32 + j) = make_float2((float)(h0 - x0), (float)(h1 - x1));
-                    } else if (d32) {
+                    } else {
                         const double2 x2 = *reinterpret_cast<const double2*>(x + j);
                         *reinterpret_cast<float2*>(d32 + j) = make_float2((float)(h0 - x2.x), (float)(h1 - x2.y));
                     }
                 } else if (j < p) {
-                    const double h0 = hreg(e);
-                    dout[j] = h0;
-                    if (d32) d32[j] = (float)(h0 - (keep_x ? xkeep[PREF ? e * T + tid : 0] : x[j]));
+                    d32[j] = (float)(hreg(e) - (keep_x ? xkeep[PREF ? e * T + tid : 0] : x[j]));
                 }
             }
-        } else {
-            for (int64_t j = tid; j < p; j += T) {
-                const double h0 = hval(vbuf[j]);
-                dout[j] = h0;
-                if (d32) d32[j] = (float)(h0 - x[j]);
-            }
+        } else if (d32) {
+            for (int64_t j = tid; j < p; j += T) d32[j] = (float)(hval(vbuf[j]) - x[j]);
         }
         if (tid == 0) {
             S.mu = inside ? 0.0 : m + t;
+            S.pm = m;
+            S.pt = t;
+            S.hmode = inside ? 1 : (rho > 0.0 ? 0 : 2);
             S.michelot_iters = passes;
             S.michelot_total += passes;
             S.live = 1;
@@ -682,8 +693,11 @@ __device__ __forceinline__ void fused_body(const TK* __restrict__ K, int64_t n, 
                                            const double* __restrict__ ysub, const double* __restrict__ rvec,
                                            double* __restrict__ tout, ACC* __restrict__ wrow, int64_t ldw,
                                            double* __restrict__ sp, int interleave, int64_t wg, int64_t ngroups,
-                                           const float* __restrict__ v32 = nullptr) {
+                                           const float* __restrict__ v32 = nullptr, ProjH ph = ProjH{}) {
     using FB = FusedBlock<TK, ACC, T, CPT, RB>;
+    // h_j: given (v), or, with v NULL in an iteration, recomputed from
+    // x = vsub and g as the projection formed it
+    auto hval_at = [&](int64_t j) -> double { return v ? v[j] : proj_h(vsub[j], g[j], ph); };
     constexpr int VEC = FB::VEC;
     constexpr int NW = FB::NW;
     constexpr int FCH = 256;    // rows staged per chunk (a multiple of RB)
@@ -721,7 +735,7 @@ __device__ __forceinline__ void fused_body(const TK* __restrict__ K, int64_t n, 
         for (int e = 0; e < VEC; ++e) {
             const int64_t j = col + e;
             if (v32) dv[c][e] = j < p ? (ACC)v32[j] : (ACC)0;
-            else dv[c][e] = j < p ? (ACC)(vsub ? v[j] - vsub[j] : v[j]) : (ACC)0;
+            else dv[c][e] = j < p ? (ACC)(vsub ? hval_at(j) - vsub[j] : v[j]) : (ACC)0;
             w[c][e] = 0;
             if constexpr (WL) wls[((int64_t)c * T + tid) * VEC + e] = 0;
         }
@@ -798,7 +812,7 @@ __device__ __forceinline__ void fused_body(const TK* __restrict__ K, int64_t n, 
         const int64_t c0 = wg * cs;
         const int64_t c1 = c0 + cs < p ? c0 + cs : p;
         for (int64_t j = c0 + tid; j < c1; j += T) {
-            const double dj = v[j] - vsub[j];
+            const double dj = hval_at(j) - vsub[j];
             dsum[0] += g[j] * dj;
             dsum[1] += dj * dj;
             dmx[0] = fmax(dmx[0], fabs(dj));
@@ -832,10 +846,11 @@ __global__ __launch_bounds__(T) void k_fused(const GPState* __restrict__ st, con
                                                 double* __restrict__ spart, int interleave,
                                                 const float* __restrict__ v32) {
     if (!st->live) return;
+    const ProjH ph = v ? ProjH{} : proj_h_params(st);
     fused_body<TK, ACC, T, CPT, RB, NB, ALIGNED, WL>(K, n, p, ldk, rows_per_wg, v, vsub, g, ysub, rvec, tout,
                                                  wpart + (int64_t)blockIdx.x * ldw, ldw,
                                                  spart + (int64_t)SPART * blockIdx.x, interleave,
-                                                 (int64_t)blockIdx.x, (int64_t)gridDim.x, v32);
+                                                 (int64_t)blockIdx.x, (int64_t)gridDim.x, v32, ph);
 }
 
 // ---------------------------------------------------------------------------
@@ -847,7 +862,7 @@ __global__ __launch_bounds__(UPD_T) void k_update(GPState* __restrict__ st, int 
                                                   const double* __restrict__ spart, int GF,
                                                   const ACC* __restrict__ wpart, int64_t ldw, int64_t p,
                                                   int64_t n, int nbp, double* __restrict__ x,
-                                                  double* __restrict__ g, const double* __restrict__ h,
+                                                  double* __restrict__ g,
                                                   double* __restrict__ r, const double* __restrict__ tq,
                                                   double* __restrict__ upart) {
     constexpr int T = UPD_T;
@@ -875,10 +890,10 @@ __global__ __launch_bounds__(UPD_T) void k_update(GPState* __restrict__ st, int 
     }
     const int64_t jc = c0 + tid;
     const bool colj = colwg && tid < UPD_COLS && jc < p;
-    double xj = 0.0, hj = 0.0, gj = 0.0;
+    double xj = 0.0, gj = 0.0;
     if (colj) {
         xj = x[jc];
-        if (mode == UM_ITER) { hj = h[jc]; gj = g[jc]; }
+        if (mode == UM_ITER) gj = g[jc];
     }
     const int64_t ir = (int64_t)(blockIdx.x - nbp) * UPD_ROWS + tid;
     const bool rowi = !colwg && ir < n;
@@ -988,7 +1003,8 @@ __global__ __launch_bounds__(UPD_T) void k_update(GPState* __restrict__ st, int 
             }
             if (colj) {
                 if (mode == UM_ITER) {
-                    const double dj = hj - xj;
+                    // h_j as the projection formed it
+                    const double dj = proj_h(xj, gj, ProjH{S.alpha, S.pm, S.pt, S.hmode}) - xj;
                     x[jc] = xj + lam * dj;
                     g[jc] = gj + 2.0 * lam * w;
                     dw = dj * w;

@@ -48,6 +48,8 @@ struct GPState {
     int32_t rule;              // last SS branch: 0 alpha_max, 1 BB1, 2 window min
     // written by the projection kernel
     double gd, dd, dmax, mu;
+    double pm, pt;             // the iteration's projection: m = max|v| and t = mu - m
+    int32_t hmode;             // h = sgn(v) max((|v| - m) - t, 0) (0), h = v (1, inside), h = 0 (2, rho = 0)
     // written by the update kernel (block 0)
     double lam, f_new, rel;
     int32_t k_new, pending, ss_pending, nb;
