@@ -217,9 +217,6 @@ void launch_fused(gp_dtype dt, int cfg, bool aligned, hipStream_t s, int64_t G, 
     else launch_fused_dt<bf16_t, float>(cfg, aligned, s, G, a);
 }
 
-// Projection shape: 256 threads when p fits 16 register slots of each
-// (fewer waves make the workgroup reductions of the threshold passes
-// cheaper), else 1024 threads with up to 22 slots, else the buffered path.
 // Shape of the single-workgroup projection: threads T and register slots per
 // thread (pairs of neighbours, so at least 2; 0 streams through vbuf).
 // Measured (kernel durations of one process, p = 2048 to 16384): eight waves

@@ -32,6 +32,8 @@ namespace gpl1 {
 constexpr int BV_T = 1024;   // per-problem workgroups
 constexpr int BV_FT = 256;   // fused-pass workgroups
 constexpr int BV_ROWS = 64;  // rows per work item
+constexpr int BV_RB = 1;     // rows per block in the fused pass (4 measured slower)
+constexpr int BV_NB = 2;     // register buffers (3 measured the same)
 
 struct VarInst {
     const void* K;
@@ -105,11 +107,11 @@ __global__ __launch_bounds__(BV_FT) void k_bv_fused(const VarInst* __restrict__ 
     double* sp = D.spart + (int64_t)SPART * it.slab;
     const double* v = refresh ? D.x : D.d;
     if (D.aligned)
-        fused_body<TK, ACC, BV_FT, CPT, 1, 2, true>((const TK*)D.K, D.n, D.p, D.ldk, BV_ROWS, v, nullptr, nullptr,
+        fused_body<TK, ACC, BV_FT, CPT, BV_RB, BV_NB, true>((const TK*)D.K, D.n, D.p, D.ldk, BV_ROWS, v, nullptr, nullptr,
                                                      refresh ? D.y : nullptr, refresh ? nullptr : D.r, D.q, wrow,
                                                      D.ldw, sp, 0, it.slab, D.nitems);
     else
-        fused_body<TK, ACC, BV_FT, CPT, 1, 2, false>((const TK*)D.K, D.n, D.p, D.ldk, BV_ROWS, v, nullptr, nullptr,
+        fused_body<TK, ACC, BV_FT, CPT, BV_RB, BV_NB, false>((const TK*)D.K, D.n, D.p, D.ldk, BV_ROWS, v, nullptr, nullptr,
                                                       refresh ? D.y : nullptr, refresh ? nullptr : D.r, D.q, wrow,
                                                       D.ldw, sp, 0, it.slab, D.nitems);
 }
