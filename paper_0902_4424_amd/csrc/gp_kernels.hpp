@@ -2,7 +2,9 @@
 //
 //   k_proj   (1 workgroup)  : steplength rule (Algorithm 2), v = x - alpha g,
 //                             threshold search for P_Omega, h = P(v)
-//                             (Algorithm 1, projection).
+//                             (Algorithm 1, projection).  Stores the float
+//                             copy of d = h - x and the scalars from which
+//                             the other kernels recompute h (proj_h).
 //   k_fused  (G workgroups) : d = h - x (Algorithm 1, direction), then one
 //                             read of K serves both products: every workgroup
 //                             owns a slab of rows, forms q_i = K_i d for its
