@@ -68,7 +68,23 @@ __device__ __forceinline__ void load_kvec(const TK* rowp, int64_t col, int64_t p
         out.raw = *reinterpret_cast<const uint4*>(rowp + col);
         return;
     }
-    // ragged tail or unaligned rows: element loads, zero beyond p
+    if (!ALIGNED && col + VEC <= p) {
+        // rows that are not 16-byte aligned: the widest loads the address
+        // allows (the alignment is the row's, the same in every lane)
+        const uintptr_t a = reinterpret_cast<uintptr_t>(rowp + col);
+        if ((a & 7) == 0) {
+            const uint2 lo = reinterpret_cast<const uint2*>(rowp + col)[0];
+            const uint2 hi = reinterpret_cast<const uint2*>(rowp + col)[1];
+            out.raw = make_uint4(lo.x, lo.y, hi.x, hi.y);
+            return;
+        }
+        if ((a & 3) == 0) {
+            const uint32_t* q = reinterpret_cast<const uint32_t*>(rowp + col);
+            out.raw = make_uint4(q[0], q[1], q[2], q[3]);
+            return;
+        }
+    }
+    // ragged tail or 2-byte aligned rows: element loads, zero beyond p
     uint32_t w[4] = {0u, 0u, 0u, 0u};
     const int esz = (int)sizeof(TK);
 #pragma unroll
