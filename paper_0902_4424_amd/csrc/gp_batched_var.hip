@@ -48,7 +48,8 @@ struct VarInst {
     double* wpart64;                 // same for FP64 K
     double* spart;                   // nitems x SPART partial dots
     double ftarget;                  // this problem's f_target
-    int32_t aligned;
+    int32_t aligned;                 // rows 16-byte aligned
+    int32_t aligned8;                // rows 8-byte aligned (bf16: read as 4-element chunks)
     int32_t pad_;
 };
 
@@ -106,14 +107,28 @@ __global__ __launch_bounds__(BV_FT) void k_bv_fused(const VarInst* __restrict__ 
     ACC* wrow = wp + (int64_t)it.slab * D.ldw;
     double* sp = D.spart + (int64_t)SPART * it.slab;
     const double* v = refresh ? D.x : D.d;
-    if (D.aligned)
-        fused_body<TK, ACC, BV_FT, CPT, BV_RB, BV_NB, true>((const TK*)D.K, D.n, D.p, D.ldk, BV_ROWS, v, nullptr, nullptr,
-                                                     refresh ? D.y : nullptr, refresh ? nullptr : D.r, D.q, wrow,
-                                                     D.ldw, sp, 0, it.slab, D.nitems);
-    else
-        fused_body<TK, ACC, BV_FT, CPT, BV_RB, BV_NB, false>((const TK*)D.K, D.n, D.p, D.ldk, BV_ROWS, v, nullptr, nullptr,
-                                                      refresh ? D.y : nullptr, refresh ? nullptr : D.r, D.q, wrow,
-                                                      D.ldw, sp, 0, it.slab, D.nitems);
+    const double* ys = refresh ? D.y : nullptr;
+    const double* rs = refresh ? nullptr : D.r;
+    if (D.aligned) {
+        fused_body<TK, ACC, BV_FT, CPT, BV_RB, BV_NB, true>((const TK*)D.K, D.n, D.p, D.ldk, BV_ROWS, v, nullptr,
+                                                             nullptr, ys, rs, D.q, wrow, D.ldw, sp, 0, it.slab,
+                                                             D.nitems);
+        return;
+    }
+    if constexpr (std::is_same<TK, bf16_t>::value) {
+        // 8-byte aligned bf16 rows (odd n with p = 4n, say): four-element
+        // chunks keep every wave's loads contiguous; twice the chunks cover
+        // the same columns
+        if (D.aligned8) {
+            fused_body<bf16x4_t, ACC, BV_FT, 2 * CPT, BV_RB, BV_NB, true>(
+                (const bf16x4_t*)D.K, D.n, D.p, D.ldk, BV_ROWS, v, nullptr, nullptr, ys, rs, D.q, wrow, D.ldw, sp,
+                0, it.slab, D.nitems);
+            return;
+        }
+    }
+    fused_body<TK, ACC, BV_FT, CPT, BV_RB, BV_NB, false>((const TK*)D.K, D.n, D.p, D.ldk, BV_ROWS, v, nullptr,
+                                                          nullptr, ys, rs, D.q, wrow, D.ldw, sp, 0, it.slab,
+                                                          D.nitems);
 }
 
 // line search, updates, steplength rule (iteration) or r, g, f (refresh)
@@ -373,6 +388,7 @@ int solve_batched_var_lockstep(gp_handle h, gp_dtype kdtype, const gp_instance* 
         D.item0 = total_items;
         D.ldw = (S.p + 63) / 64 * 64;
         D.aligned = (S.ldk % vec == 0) && (((uintptr_t)S.K) % 16 == 0);
+        D.aligned8 = (S.ldk * esz % 8 == 0) && (((uintptr_t)S.K) % 8 == 0);
         for (int64_t i = 0; i < D.nitems; ++i) hitems.push_back(VarItem{(int32_t)b, (int32_t)i});
         total_items += D.nitems;
         ox[(size_t)b] = take(8 * (3 * S.p + 3 * S.n));

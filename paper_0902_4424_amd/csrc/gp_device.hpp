@@ -11,6 +11,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace gpl1 {
 
 constexpr int WAVE = 64;
@@ -19,11 +21,15 @@ constexpr int WAVE = 64;
 // K storage types.  bf16 is carried as raw uint16 bits.
 // ---------------------------------------------------------------------------
 struct bf16_t { uint16_t bits; };
+// bf16 K whose rows are 8-byte but not 16-byte aligned, read four elements
+// (8 bytes) per chunk so that a wave's loads stay contiguous
+struct bf16x4_t { uint16_t bits; };
 
 template <typename TK> struct KTraits;
-template <> struct KTraits<double> { using acc = double; static constexpr int VEC = 2; };
-template <> struct KTraits<float>  { using acc = float;  static constexpr int VEC = 4; };
-template <> struct KTraits<bf16_t> { using acc = float;  static constexpr int VEC = 8; };
+template <> struct KTraits<double>   { using acc = double; static constexpr int VEC = 2; };
+template <> struct KTraits<float>    { using acc = float;  static constexpr int VEC = 4; };
+template <> struct KTraits<bf16_t>   { using acc = float;  static constexpr int VEC = 8; };
+template <> struct KTraits<bf16x4_t> { using acc = float;  static constexpr int VEC = 4; };
 
 __device__ __forceinline__ float bf16_to_float(uint32_t bits16) {
     return __uint_as_float(bits16 << 16);
@@ -43,6 +49,17 @@ template <typename TK> struct KVec {
     static constexpr int VEC = KTraits<TK>::VEC;
     uint4 raw;
     __device__ __forceinline__ ACC get(int e) const;
+    __device__ __forceinline__ void clear() { raw = make_uint4(0u, 0u, 0u, 0u); }
+};
+// An 8-byte chunk of four bf16 elements.
+template <> struct KVec<bf16x4_t> {
+    static constexpr int VEC = 4;
+    uint2 raw;
+    __device__ __forceinline__ float get(int e) const {
+        const uint32_t w = (e >> 1) == 0 ? raw.x : raw.y;
+        return (e & 1) ? __uint_as_float(w & 0xffff0000u) : __uint_as_float(w << 16);
+    }
+    __device__ __forceinline__ void clear() { raw = make_uint2(0u, 0u); }
 };
 template <> __device__ __forceinline__ double KVec<double>::get(int e) const {
     uint32_t lo = e == 0 ? raw.x : raw.z;
@@ -63,46 +80,63 @@ template <> __device__ __forceinline__ float KVec<bf16_t>::get(int e) const {
 // then a full chunk is one 16-byte load.  Elements at col >= p read as 0.
 template <typename TK, bool ALIGNED>
 __device__ __forceinline__ void load_kvec(const TK* rowp, int64_t col, int64_t p, KVec<TK>& out) {
-    constexpr int VEC = KTraits<TK>::VEC;
-    if (ALIGNED && col + VEC <= p) {
-        out.raw = *reinterpret_cast<const uint4*>(rowp + col);
-        return;
-    }
-    if (!ALIGNED && col + VEC <= p) {
-        // rows that are not 16-byte aligned: the widest loads the address
-        // allows (the alignment is the row's, the same in every lane)
-        const uintptr_t a = reinterpret_cast<uintptr_t>(rowp + col);
-        if ((a & 7) == 0) {
-            const uint2 lo = reinterpret_cast<const uint2*>(rowp + col)[0];
-            const uint2 hi = reinterpret_cast<const uint2*>(rowp + col)[1];
-            out.raw = make_uint4(lo.x, lo.y, hi.x, hi.y);
+    if constexpr (std::is_same<TK, bf16x4_t>::value) {
+        // four bf16; ALIGNED: the row start is 8-byte aligned (ldk % 4 == 0)
+        if (ALIGNED && col + 4 <= p) {
+            out.raw = *reinterpret_cast<const uint2*>(rowp + col);
             return;
         }
-        if ((a & 3) == 0) {
-            const uint32_t* q = reinterpret_cast<const uint32_t*>(rowp + col);
-            out.raw = make_uint4(q[0], q[1], q[2], q[3]);
-            return;
-        }
-    }
-    // ragged tail or 2-byte aligned rows: element loads, zero beyond p
-    uint32_t w[4] = {0u, 0u, 0u, 0u};
-    const int esz = (int)sizeof(TK);
+        uint32_t w[2] = {0u, 0u};
 #pragma unroll
-    for (int e = 0; e < VEC; ++e) {
-        if (col + e < p) {
-            if (esz == 8) {
-                uint64_t b = reinterpret_cast<const uint64_t*>(rowp)[col + e];
-                w[e * 2] = (uint32_t)b;
-                w[e * 2 + 1] = (uint32_t)(b >> 32);
-            } else if (esz == 4) {
-                w[e] = reinterpret_cast<const uint32_t*>(rowp)[col + e];
-            } else {
-                uint32_t b = reinterpret_cast<const uint16_t*>(rowp)[col + e];
+        for (int e = 0; e < 4; ++e) {
+            if (col + e < p) {
+                const uint32_t b = reinterpret_cast<const uint16_t*>(rowp)[col + e];
                 w[e >> 1] |= (e & 1) ? (b << 16) : b;
             }
         }
+        out.raw = make_uint2(w[0], w[1]);
+    } else {
+        constexpr int VEC = KTraits<TK>::VEC;
+        if (ALIGNED && col + VEC <= p) {
+            out.raw = *reinterpret_cast<const uint4*>(rowp + col);
+            return;
+        }
+        if (!ALIGNED && col + VEC <= p) {
+            // rows that are not 16-byte aligned: the widest loads the address
+            // allows (the alignment is the row's, the same in every lane)
+            const uintptr_t a = reinterpret_cast<uintptr_t>(rowp + col);
+            if ((a & 7) == 0) {
+                const uint2 lo = reinterpret_cast<const uint2*>(rowp + col)[0];
+                const uint2 hi = reinterpret_cast<const uint2*>(rowp + col)[1];
+                out.raw = make_uint4(lo.x, lo.y, hi.x, hi.y);
+                return;
+            }
+            if ((a & 3) == 0) {
+                const uint32_t* q = reinterpret_cast<const uint32_t*>(rowp + col);
+                out.raw = make_uint4(q[0], q[1], q[2], q[3]);
+                return;
+            }
+        }
+        // ragged tail or 2-byte aligned rows: element loads, zero beyond p
+        uint32_t w[4] = {0u, 0u, 0u, 0u};
+        const int esz = (int)sizeof(TK);
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) {
+            if (col + e < p) {
+                if (esz == 8) {
+                    uint64_t b = reinterpret_cast<const uint64_t*>(rowp)[col + e];
+                    w[e * 2] = (uint32_t)b;
+                    w[e * 2 + 1] = (uint32_t)(b >> 32);
+                } else if (esz == 4) {
+                    w[e] = reinterpret_cast<const uint32_t*>(rowp)[col + e];
+                } else {
+                    uint32_t b = reinterpret_cast<const uint16_t*>(rowp)[col + e];
+                    w[e >> 1] |= (e & 1) ? (b << 16) : b;
+                }
+            }
+        }
+        out.raw = make_uint4(w[0], w[1], w[2], w[3]);
     }
-    out.raw = make_uint4(w[0], w[1], w[2], w[3]);
 }
 
 // ---------------------------------------------------------------------------

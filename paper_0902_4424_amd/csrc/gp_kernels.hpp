@@ -618,7 +618,7 @@ struct FusedBlock {
             for (int c = 0; c < CPT; ++c) {
                 const int64_t col = ((int64_t)c * T + threadIdx.x) * VEC;
                 if (row < r1 && col < p) load_kvec<TK, ALIGNED>(K + row * ldk, col, p, buf[r][c]);
-                else buf[r][c].raw = make_uint4(0u, 0u, 0u, 0u);
+                else buf[r][c].clear();
             }
         }
     }

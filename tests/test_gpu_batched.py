@@ -218,9 +218,13 @@ def _check_var(insts, X, res, idx, gap_tol, err_tol):
 def test_var_small_matches_oracle(H, dtype):
     say(f"[batched-var] 7 uneven problems {dtype}")
     rng = np.random.default_rng(77)
+    ns = rng.integers(16, 300, size=7)
+    # odd and even n: with p = 4n, bf16 rows are 8-byte aligned for odd n
+    # (read as four-element chunks) and 16-byte aligned for even n
+    assert (ns % 2 == 1).any() and (ns % 2 == 0).any()
     insts = [instances.gaussian_instance(int(n), 4 * int(n), max(1, int(n) // 20), sigma=1e-2,
                                          dtype=dtype, seed=900 + i)
-             for i, n in enumerate(rng.integers(16, 300, size=7))]
+             for i, n in enumerate(ns)]
     X, res = H.solve_batched_var(_var_problems(insts, dtype), tol=1e-13, max_iter=5000,
                                  refresh_every=0 if dtype == "f64" else 50)
     tol = (1e-10, 1e-6) if dtype == "f64" else (1e-6, 1e-4)
@@ -234,6 +238,9 @@ def test_var_uneven_sampled(H):
                                  refresh_every=50)
     assert all(r["status"] >= 0 for r in res)
     big = int(np.argmax([i.n for i in insts]))
+    # problems 0 and 17 have odd n (8-byte aligned bf16 rows), 40 and the
+    # largest even n
+    assert insts[0].n % 2 == 1 and insts[17].n % 2 == 1 and insts[40].n % 2 == 0
     _check_var(insts, X, res, [0, 17, 40, big], 1e-6, 1e-4)
 
 
