@@ -32,7 +32,7 @@ namespace gpl1 {
 constexpr int BV_T = 1024;   // per-problem workgroups
 constexpr int BV_FT = 256;   // fused-pass workgroups
 constexpr int BV_ROWS = 64;  // rows per work item (32: the same, 256: 30 % slower)
-constexpr int BV_RB = 1;     // rows per block in the fused pass (4 measured slower)
+constexpr int BV_RB = 1;     // rows per block in the fused pass (2 measured the same, 4 slower)
 constexpr int BV_NB = 2;     // register buffers (3 measured the same)
 
 struct VarInst {
