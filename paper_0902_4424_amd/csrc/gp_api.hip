@@ -548,7 +548,7 @@ int gp_l1_solve(gp_handle h, gp_dtype kdtype, const void* K, int64_t n, int64_t 
             hipError_t ce = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
             if (ce != hipSuccess) return hip_fail(h, ce, "graph capture");
             for (int k = 0; k < gch; ++k) {
-                launch_proj(s, st, PM_ITER, p, x, g, d, upart, P.GU, vb, d32);
+                launch_proj(s, st, PM_ITER, p, x, g, nullptr, upart, P.GU, vb, d32);
                 launch_fused(kdtype, P.cfg, aligned, s, P.G, fa_iter);
                 launch_update(kdtype, s, st, UM_ITER, spart, (int)P.G, wpart, P.ldw, p, n, x, g, r, q, upart);
             }
@@ -590,7 +590,7 @@ int gp_l1_solve(gp_handle h, gp_dtype kdtype, const void* K, int64_t n, int64_t 
         }
         const int end = o.graph ? std::min(o.max_iter, (it / gch + 1) * gch) : std::min(o.max_iter, it + o.chunk);
         for (; it < end; ++it) {
-            launch_proj(s, st, PM_ITER, p, x, g, d, upart, P.GU, vb, d32);
+            launch_proj(s, st, PM_ITER, p, x, g, nullptr, upart, P.GU, vb, d32);
             // every profile-th iteration's fused launch is bracketed by events
             if (o.profile > 0 && it % o.profile == 0) {
                 FusedArgs fa = fa_iter;
