@@ -17,7 +17,7 @@ import time
 PKG = os.path.dirname(os.path.abspath(__file__))
 TABLE = os.path.join(PKG, "tuned.json")
 
-# (threads, chunks per thread) of the library's configurations 1..10; a
+# (threads, chunks per thread) of the library's configurations 1..12; a
 # configuration covers T * CPT * (16 / element size) columns.  Shape 6 spills
 # registers and is tried only when nothing else covers p.
 CFG_COVER = {1: (256, 1), 2: (256, 2), 3: (256, 4), 4: (512, 4), 5: (512, 8), 6: (1024, 8),
