@@ -102,7 +102,7 @@ __global__ void k_bs_pack_f32(const float* __restrict__ K, int64_t n, int64_t p,
 
 struct BsPtrs {
     GPState* st; int32_t* done;
-    double *X, *G, *H, *R, *Y, *Qv;          // B x p (X, G, H) and B x n (R, Y, Qv), ld = p / n
+    double *X, *G, *R, *Y, *Qv;              // B x p (X, G) and B x n (R, Y, Qv), ld = p / n
     uint16_t *Dsp, *Qsp;                      // GEMM right operands: 3 planes of Bpad x ppad / npad
     const float *Qpart, *Wpart;               // GEMM partial outputs
     int64_t n, p, npad, ppad, plD, plQ;       // plane strides of Dsp / Qsp
@@ -173,7 +173,7 @@ __global__ __launch_bounds__(T) void k_bs_rows(BsPtrs P, int mode) {
     const int b = P.list ? P.list[blockIdx.x] : (int)blockIdx.x, tid = threadIdx.x;
     GPState* st = P.st + b;
     if (P.done[b]) return;
-    const int64_t n = P.n, p = P.p;
+    const int64_t n = P.n;
     double* r = P.R + b * n;
     const double* y = P.Y + b * n;
     double* qv = P.Qv + b * n;
@@ -287,7 +287,9 @@ __global__ __launch_bounds__(T) void k_bs_rows(BsPtrs P, int mode) {
 // W = K^T Q), the steplength rule, the projection, the next direction
 // d = P(x - alpha g) - x and its dots, d split for the next K D.  Every
 // thread keeps its elements of x and g in registers (pairs of neighbours), so
-// each vector is read and written once per iteration.
+// each vector is read and written once per iteration.  h is not stored: the
+// projection leaves (alpha, m, t, mode) in the problem's state, and the next
+// launch recomputes h from the x and g it reads with the same operations.
 // Modes: BC_INIT (g = 2 W at x0, then alpha_0 and the first projection);
 // BC_ITER (step, rule, projection); BC_ITER_NOPROJ (step and rule only, x
 // split for the residual refresh that follows); BC_REFRESH_PROJ (g = 2 W at
@@ -302,7 +304,6 @@ __global__ __launch_bounds__(T) void k_bs_cols(BsPtrs P, int mode) {
     const int64_t p = P.p;
     double* x = P.X + b * p;
     double* g = P.G + b * p;
-    double* hd = P.H + b * p;
     const bool iter = mode == BC_ITER || mode == BC_ITER_NOPROJ;
     const int step_pending = iter ? st->ss_pending : 0;
     const int col_done = P.done[b];
@@ -316,25 +317,26 @@ __global__ __launch_bounds__(T) void k_bs_cols(BsPtrs P, int mode) {
     double xr[NV], gr[NV];
     if (step_pending) {
         const double lam = st->lam;
+        // the last projection's scalars, read before the rule below replaces alpha
+        const ProjH ph = proj_h_params(st);
         double acc[2] = {0.0, 0.0}, none[1] = {0.0};
 #pragma unroll
         for (int e = 0; e < NV; e += 2) {
             const int64_t j = 2 * ((e / 2) * T + tid);
-            double xo[2] = {0.0, 0.0}, go[2] = {0.0, 0.0}, ho[2] = {0.0, 0.0}, w[2] = {0.0, 0.0};
+            double xo[2] = {0.0, 0.0}, go[2] = {0.0, 0.0}, w[2] = {0.0, 0.0};
             if (j + 1 < p) {      // 16-byte loads for the pair
                 const double2 x2 = *reinterpret_cast<const double2*>(x + j);
                 const double2 g2 = *reinterpret_cast<const double2*>(g + j);
-                const double2 h2 = *reinterpret_cast<const double2*>(hd + j);
-                xo[0] = x2.x; xo[1] = x2.y; go[0] = g2.x; go[1] = g2.y; ho[0] = h2.x; ho[1] = h2.y;
+                xo[0] = x2.x; xo[1] = x2.y; go[0] = g2.x; go[1] = g2.y;
                 w[0] = wval(j);
                 w[1] = wval(j + 1);
             } else if (j < p) {
-                xo[0] = x[j]; go[0] = g[j]; ho[0] = hd[j];
+                xo[0] = x[j]; go[0] = g[j];
                 w[0] = wval(j);
             }
 #pragma unroll
             for (int u = 0; u < 2; ++u) {
-                const double dj = ho[u] - xo[u];                 // hd holds the last h
+                const double dj = proj_h(xo[u], go[u], ph) - xo[u];   // the last h, recomputed
                 xr[e + u] = xo[u] + lam * dj;
                 gr[e + u] = go[u] + 2.0 * lam * w[u];
                 acc[0] += dj * w[u];                             // d'w
@@ -401,7 +403,7 @@ __global__ __launch_bounds__(T) void k_bs_cols(BsPtrs P, int mode) {
     }
     const double mu_prev = mode == BC_INIT ? 0.0 : sh[1];
 #pragma unroll
-    for (int e = 0; e < NV; ++e) vr[e] = xr[e] - alpha * gr[e];
+    for (int e = 0; e < NV; ++e) vr[e] = fma(-alpha, gr[e], xr[e]);   // as proj_h forms it
     // warm start from the previous threshold when it lies below max|v|
     double mloc = 0.0;
 #pragma unroll
@@ -416,7 +418,6 @@ __global__ __launch_bounds__(T) void k_bs_cols(BsPtrs P, int mode) {
         if (j < p) {
             const double h = l1_hval(vr[e], m, t, inside, rho);
             const double dj = h - xr[e];
-            hd[j] = h;
             split3(dj, P.Dsp, P.plD, b * P.ppad + j);
             sums[0] += gr[e] * dj;
             sums[1] += dj * dj;
@@ -430,6 +431,10 @@ __global__ __launch_bounds__(T) void k_bs_cols(BsPtrs P, int mode) {
         st->dd = sums[1];
         st->dmax = mx[0];
         st->mu = inside ? 0.0 : m + t;
+        // what the next launch needs to recompute h (alpha is already st->alpha)
+        st->pm = m;
+        st->pt = t;
+        st->hmode = inside ? 1 : (rho > 0.0 ? 0 : 2);
         st->michelot_total += passes;
         if (mx[0] == 0.0 || !(sums[0] < 0.0)) { st->status = ST_STATIONARY; st->done = 1; P.done[b] = 1; }
     }
@@ -458,11 +463,14 @@ __global__ __launch_bounds__(BS_T) void k_bs_finish(BsPtrs P, void* __restrict__
 
 namespace {
 
-// Column-kernel shape: the fewest threads (256, 512 or 1024) that hold p in
-// at most 16 register slots each, so that several problems share a CU and
-// one problem's reductions overlap another's loads.
+// Column-kernel shape: 256 threads up to p = 2048 and 512 threads up to
+// p = 8192, 1024 beyond; each thread holds its elements in at most 16
+// register slots, and up to p = 4096 in at most 8 (512 x 8 needs 102
+// registers, four waves per SIMD, against 180 and two for 256 x 16), so that
+// several problems share a CU and one problem's reductions overlap another's
+// loads.
 int bs_cols_t(int64_t p) {
-    if ((p + 255) / 256 <= 16) return 256;
+    if ((p + 255) / 256 <= 8) return 256;
     if ((p + 511) / 512 <= 16) return 512;
     return 1024;
 }
@@ -496,8 +504,8 @@ int bs_nv(int64_t p) {
 void launch_cols(int T, int nv, int64_t B, hipStream_t s, const BsPtrs& P, int mode) {
 #define GPL1_BS_COLS(TT, NN) \
     if (T == TT && nv == NN) { hipLaunchKernelGGL((k_bs_cols<TT, NN>), dim3((unsigned)B), dim3(TT), 0, s, P, mode); return; }
-    GPL1_BS_COLS(256, 2) GPL1_BS_COLS(256, 4) GPL1_BS_COLS(256, 8) GPL1_BS_COLS(256, 16)
-    GPL1_BS_COLS(512, 16) GPL1_BS_COLS(1024, 16)
+    GPL1_BS_COLS(256, 2) GPL1_BS_COLS(256, 4) GPL1_BS_COLS(256, 8)
+    GPL1_BS_COLS(512, 8) GPL1_BS_COLS(512, 16) GPL1_BS_COLS(1024, 16)
 #undef GPL1_BS_COLS
 }
 
@@ -537,7 +545,7 @@ int solve_batched_shared_mfma(gp_handle h, gp_dtype kdtype, const void* K, int64
     size_t off = 0;
     auto take = [&](size_t bytes) { size_t o2 = off; off += (bytes + 255) / 256 * 256; return o2; };
     const size_t o_st = take(sizeof(GPState) * B), o_done = take(sizeof(int32_t) * B);
-    const size_t o_X = take(8 * B * p), o_G = take(8 * B * p), o_H = take(8 * B * p);
+    const size_t o_X = take(8 * B * p), o_G = take(8 * B * p);
     const size_t o_R = take(8 * B * n), o_Y = take(8 * B * n), o_Qv = take(8 * B * n);
     const size_t o_Kp = take(2 * nK * kpl), o_Kt = take(2 * nK * kpl);
     // GEMM right operands and outputs get one extra row (index bpad) that
@@ -552,7 +560,7 @@ int solve_batched_shared_mfma(gp_handle h, gp_dtype kdtype, const void* K, int64
     BsPtrs P;
     P.st = (GPState*)(ws + o_st);
     P.done = (int32_t*)(ws + o_done);
-    P.X = (double*)(ws + o_X); P.G = (double*)(ws + o_G); P.H = (double*)(ws + o_H);
+    P.X = (double*)(ws + o_X); P.G = (double*)(ws + o_G);
     P.R = (double*)(ws + o_R); P.Y = (double*)(ws + o_Y); P.Qv = (double*)(ws + o_Qv);
     uint16_t* Kp = (uint16_t*)(ws + o_Kp);
     uint16_t* Kt = (uint16_t*)(ws + o_Kt);
