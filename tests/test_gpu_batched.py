@@ -56,7 +56,10 @@ def _check_columns(batch, X, res, cols, tight_iters=100000, gap_tol=1e-6, err_to
     assert worst_gap <= gap_tol and worst_err <= err_tol
 
 
-@pytest.mark.parametrize("n,p,B", [(256, 1024, 5), (200, 700, 3), (130, 260, 129)])
+# p = 3001 and 5001 take the 512-thread column kernel with 8 and 16 slots
+# per thread, both with a ragged last pair
+@pytest.mark.parametrize("n,p,B", [(256, 1024, 5), (200, 700, 3), (130, 260, 129), (300, 3001, 5),
+                                   (260, 5001, 3)])
 def test_shared_small_matches_oracle(H, n, p, B):
     say(f"[batched-shared] n={n} p={p} B={B} bf16")
     batch = instances.shared_batch(n, p, B, max(1, n // 20), dtype="bf16", seed=31 + n,
@@ -123,7 +126,7 @@ def test_shared_large_sampled(H):
     _check_columns(batch, X, res, [0, 31, 63], tight_iters=20000)
 
 
-@pytest.mark.parametrize("n,p,B", [(256, 1024, 4), (190, 650, 130)])
+@pytest.mark.parametrize("n,p,B", [(256, 1024, 4), (190, 650, 130), (300, 3001, 4)])
 def test_shared_f32_matches_oracle(H, n, p, B):
     say(f"[batched-shared] FP32 K as three bf16 planes n={n} p={p} B={B}")
     batch = instances.shared_batch(n, p, B, max(1, n // 20), dtype="f32", seed=61 + n,
