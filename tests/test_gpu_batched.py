@@ -71,6 +71,21 @@ def test_shared_small_matches_oracle(H, n, p, B):
     _check_columns(batch, X, res, cols)
 
 
+@pytest.mark.parametrize("n,p", [(128, 2048), (128, 2049), (160, 4096), (160, 4097), (256, 8192),
+                                 (256, 8193)])
+def test_shared_column_shape_boundaries(H, n, p):
+    """Both sides of every switch of the per-problem kernel's shape (256 x 8,
+    512 x 8, 512 x 16 and 1024 x 16 threads x slots) meet the FP32-path bar."""
+    say(f"[batched-shared] shape boundary n={n} p={p} B=2 bf16")
+    batch = instances.shared_batch(n, p, 2, max(1, n // 20), dtype="bf16", seed=31 + n,
+                                   rhs_seed_base=900 + p)
+    Y = torch.from_numpy(batch.Y_store).to(DEV)
+    X, res = H.solve_batched_shared(_kt(batch), Y, batch.rho, tol=1e-12, max_iter=3000,
+                                    refresh_every=50)
+    assert all(r["status"] >= 0 for r in res)
+    _check_columns(batch, X, res, [0, 1])
+
+
 def test_shared_refresh_and_warm_start(H):
     say("[batched-shared] refresh every 7, warm start from the answer")
     batch = instances.shared_batch(256, 1024, 4, 12, dtype="bf16", seed=8, rhs_seed_base=80)
