@@ -216,6 +216,24 @@ def test_ragged_and_padded_shapes(H, p):
     assert (f2 - ref["f"]) / scale <= 1e-6
 
 
+# bf16 rows of p + 3 elements are 8-byte (p = 1001, 4097) or 4-byte (16383)
+# aligned, unpadded rows of odd p only 2-byte aligned: every load width of
+# the fused kernel's unaligned path
+@pytest.mark.parametrize("p", [1001, 4097, 16383])
+def test_bf16_ragged_and_unaligned_rows(H, p):
+    say(f"[solve] bf16 ragged p={p}, padded and unpadded rows")
+    n = 37
+    inst = instances.gaussian_instance(n, p, 3, dtype="bf16", seed=300 + p)
+    ref = gpss(inst.K64, inst.y64, inst.rho, tol=1e-13, max_iter=20000)
+    scale = max(ref["f"], 1e-3 * float(inst.y64 @ inst.y64))
+    Kp = np.zeros((n, p + 3), dtype=np.uint16)
+    Kp[:, :p] = inst.K_store
+    for Kt in (_dev(Kp.view(np.int16))[:, :p], _dev(inst.K_store.view(np.int16))):
+        x, res = H.solve(Kt, _dev(inst.y_store), inst.rho, tol=1e-13, max_iter=20000)
+        _, _, fx = _gap_err(inst, x.cpu().numpy(), ref)
+        assert (fx - ref["f"]) / scale <= 1e-6, (fx, ref["f"], res)
+
+
 def test_special_cases(H):
     say("[solve] special cases")
     inst = instances.gaussian_instance(64, 256, 5, dtype="f64", seed=9)
