@@ -166,7 +166,9 @@ __global__ __launch_bounds__(BS_T) void k_bs_init(BsPtrs P, GPParams prm, const 
 // ---------------------------------------------------------------------------
 // row side: t = sum of the K-products; refresh (r = t - y) or the line search
 // ---------------------------------------------------------------------------
-template <int T>
+// RPT > 0: n <= RPT * T, and an iteration keeps each thread's q_i and r_i in
+// registers between the dots and the update; RPT = 0 parks q in Qv instead.
+template <int T, int RPT>
 __global__ __launch_bounds__(T) void k_bs_rows(BsPtrs P, int mode) {
     __shared__ double lds[3 * (T / WAVE)];
     __shared__ double sh[4];
@@ -221,11 +223,26 @@ __global__ __launch_bounds__(T) void k_bs_rows(BsPtrs P, int mode) {
     }
     // iteration: q = K d, its dots, the Armijo step, then r, x updates
     double acc[2] = {0.0, 0.0}, none[1] = {0.0};
-    for (int64_t i = tid; i < n; i += T) {
-        const double qi = tval(i);
-        qv[i] = qi;
-        acc[0] += qi * qi;
-        acc[1] += r[i] * qi;
+    double qreg[RPT > 0 ? RPT : 1], rreg[RPT > 0 ? RPT : 1];
+    if constexpr (RPT > 0) {
+#pragma unroll
+        for (int k = 0; k < RPT; ++k) {
+            const int64_t i = tid + (int64_t)k * T;
+            qreg[k] = rreg[k] = 0.0;
+            if (i < n) {
+                qreg[k] = tval(i);
+                rreg[k] = r[i];
+                acc[0] += qreg[k] * qreg[k];
+                acc[1] += rreg[k] * qreg[k];
+            }
+        }
+    } else {
+        for (int64_t i = tid; i < n; i += T) {
+            const double qi = tval(i);
+            qv[i] = qi;
+            acc[0] += qi * qi;
+            acc[1] += r[i] * qi;
+        }
     }
     block_reduce<T, 2, 1>(acc, none, lds);
     if (tid == 0) {
@@ -273,10 +290,21 @@ __global__ __launch_bounds__(T) void k_bs_rows(BsPtrs P, int mode) {
     __syncthreads();
     if (sh[1] != 0.0) return;
     const double lam = sh[0];
-    for (int64_t i = tid; i < n; i += T) {
-        const double qi = qv[i];
-        r[i] += lam * qi;
-        split3(qi, P.Qsp, P.plQ, b * P.npad + i);
+    if constexpr (RPT > 0) {
+#pragma unroll
+        for (int k = 0; k < RPT; ++k) {
+            const int64_t i = tid + (int64_t)k * T;
+            if (i < n) {
+                r[i] = rreg[k] + lam * qreg[k];
+                split3(qreg[k], P.Qsp, P.plQ, b * P.npad + i);
+            }
+        }
+    } else {
+        for (int64_t i = tid; i < n; i += T) {
+            const double qi = qv[i];
+            r[i] += lam * qi;
+            split3(qi, P.Qsp, P.plQ, b * P.npad + i);
+        }
     }
     // the p-space part of the step (x += lam d) is applied by the column
     // kernel, which reads x anyway
@@ -617,7 +645,12 @@ int solve_batched_shared_mfma(gp_handle h, gp_dtype kdtype, const void* K, int64
         gemm_planes(Kt, npad, ppad, P.Qsp, npad, P.plQ, S2, kc2, Wpart, ppad, P.sW);
     };
     auto rows = [&](int mode) {
-        hipLaunchKernelGGL(k_bs_rows<256>, dim3((unsigned)live), dim3(256), 0, s, P, mode);
+        if (n <= 4 * 256)
+            hipLaunchKernelGGL((k_bs_rows<256, 4>), dim3((unsigned)live), dim3(256), 0, s, P, mode);
+        else if (n <= 8 * 256)
+            hipLaunchKernelGGL((k_bs_rows<256, 8>), dim3((unsigned)live), dim3(256), 0, s, P, mode);
+        else
+            hipLaunchKernelGGL((k_bs_rows<256, 0>), dim3((unsigned)live), dim3(256), 0, s, P, mode);
     };
     auto cols = [&](int mode) {
         launch_cols(ct, cnv, live, s, P, mode);
