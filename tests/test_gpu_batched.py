@@ -72,10 +72,12 @@ def test_shared_small_matches_oracle(H, n, p, B):
 
 
 @pytest.mark.parametrize("n,p", [(128, 2048), (128, 2049), (160, 4096), (160, 4097), (256, 8192),
-                                 (256, 8193)])
+                                 (256, 8193), (1024, 600), (1025, 600), (2048, 600), (2049, 600)])
 def test_shared_column_shape_boundaries(H, n, p):
-    """Both sides of every switch of the per-problem kernel's shape (256 x 8,
-    512 x 8, 512 x 16 and 1024 x 16 threads x slots) meet the FP32-path bar."""
+    """Both sides of every switch of the per-problem kernels' shapes (columns:
+    256 x 8, 512 x 8, 512 x 16 and 1024 x 16 threads x slots; rows: 4 or 8
+    rows per thread in registers, or q parked in memory above n = 2048) meet
+    the FP32-path bar."""
     say(f"[batched-shared] shape boundary n={n} p={p} B=2 bf16")
     batch = instances.shared_batch(n, p, 2, max(1, n // 20), dtype="bf16", seed=31 + n,
                                    rhs_seed_base=900 + p)
