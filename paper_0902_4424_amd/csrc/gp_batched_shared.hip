@@ -529,11 +529,21 @@ int bs_nv(int64_t p) {
         case 16: { constexpr int NVc = 16; STMT; } break; \
     }
 
+// the (threads, slots) shapes of k_bs_cols that are compiled
+#define GPL1_BS_COLS_SHAPES(X) X(256, 2) X(256, 4) X(256, 8) X(512, 8) X(512, 16) X(1024, 16)
+
+bool cols_shape_ok(int T, int nv) {
+#define GPL1_BS_OK(TT, NN) \
+    if (T == TT && nv == NN) return true;
+    GPL1_BS_COLS_SHAPES(GPL1_BS_OK)
+#undef GPL1_BS_OK
+    return false;
+}
+
 void launch_cols(int T, int nv, int64_t B, hipStream_t s, const BsPtrs& P, int mode) {
 #define GPL1_BS_COLS(TT, NN) \
     if (T == TT && nv == NN) { hipLaunchKernelGGL((k_bs_cols<TT, NN>), dim3((unsigned)B), dim3(TT), 0, s, P, mode); return; }
-    GPL1_BS_COLS(256, 2) GPL1_BS_COLS(256, 4) GPL1_BS_COLS(256, 8)
-    GPL1_BS_COLS(512, 8) GPL1_BS_COLS(512, 16) GPL1_BS_COLS(1024, 16)
+    GPL1_BS_COLS_SHAPES(GPL1_BS_COLS)
 #undef GPL1_BS_COLS
 }
 
@@ -558,7 +568,7 @@ int solve_batched_shared_mfma(gp_handle h, gp_dtype kdtype, const void* K, int64
     const int nK = kdtype == GP_F32 ? 3 : 1;   // bf16 planes of K
     const int nv = bs_nv(p);
     const int ct = bs_cols_t(p), cnv = bs_nv_t(p, ct);
-    if (nv == 0 || B > (1 << 20)) return GP_E_UNSUPPORTED;
+    if (nv == 0 || !cols_shape_ok(ct, cnv) || B > (1 << 20)) return GP_E_UNSUPPORTED;
     const int64_t npad = rup(n, BS_PAD), ppad = rup(p, BS_PAD), bpad = rup(B, BS_PAD);
     // split-K chunks of about 1024 (multiples of 32) per GEMM
     auto chunk_of = [](int64_t kd) {
