@@ -19,8 +19,7 @@ methods for l1-constrained signal recovery by steplength selection rules"):
                     the lambda <-> rho relation of Section 1.
 """
 from .projection import project_l1, project_l1_mu, soft_threshold
-from .gpss import (GPSSParams, gpss, objective, gradient, ss_update,
-                   STATUS_NAMES)
+from .gpss import GPSSParams, gpss, ss_update, STATUS_NAMES
 
 __all__ = ["project_l1", "project_l1_mu", "soft_threshold", "GPSSParams",
-           "gpss", "objective", "gradient", "ss_update", "STATUS_NAMES"]
+           "gpss", "ss_update", "STATUS_NAMES"]

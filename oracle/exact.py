@@ -84,10 +84,3 @@ def lambda_of_rho(K, y, x):
     """lambda = ||K^T (y - K x)||_inf at a solution x of problem (2)."""
     return float(np.abs(K.T @ (y - K @ x)).max())
 
-
-def frank_wolfe_gap(K, y, x, rho):
-    """Upper bound on f(x) - f* for feasible x, valid at any size:
-    by convexity f(x) - f(u) <= grad f(x)^T (x - u) for all u in the ball, and
-    the maximum over u of -grad f^T u is rho ||grad f||_inf."""
-    g = 2.0 * (K.T @ (K @ x - y))
-    return float(g @ x + rho * np.abs(g).max())

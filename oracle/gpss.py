@@ -58,15 +58,6 @@ class GPSSParams:
     backtrack_cap: int = 60
 
 
-def objective(K, y, x):
-    r = K @ x - y
-    return float(r @ r)
-
-
-def gradient(K, y, x):
-    return 2.0 * (K.T @ (K @ x - y))
-
-
 def _clamp(a, p: GPSSParams):
     return max(p.alpha_min, min(a, p.alpha_max))
 
@@ -165,7 +156,7 @@ def gpss(K, y, rho, x0=None, *, tol=1e-10, max_iter=100000, f_target=None,
         rel = (f - ft) / f
         if trace:
             rec.append(dict(k=k, f=f, f_new=ft, alpha=alpha_used, lam=lam,
-                            nb=nb, gd=gd, ss=ss, sz=sz, zz=zz, rule=rule,
+                            nb=nb, gd=gd, fmax=fmax, ss=ss, sz=sz, zz=zz, rule=rule,
                             tau=st.tau, alpha_next=alpha,
                             l1=float(np.abs(x_new).sum())))
         x, r, g, f = x_new, r_new, g_new, ft

@@ -152,6 +152,45 @@ def test_gpss_backtracking_hand_example():
     assert out["x"][0] == 0.5 and out["f"] == 0.0
 
 
+def test_gpss_nonmonotone_hand_example():
+    """Algorithm 1, step 4 with M > 1 (tests/golden/nonmonotone_hand_example.txt):
+    at k = 1 the BB1 step raises f from 28.39 to 29.09.  With M = 1 the trial
+    is rejected and one reduction gives lambda = 1/2; with M = 2 or 3 the
+    window still holds f0 = 30 and the increase is accepted at lambda = 1.
+    At k = 2 the window of M = 2 has dropped f0, the one of M = 3 has not."""
+    g = _golden("nonmonotone_hand_example.txt")
+    K, y, rho = np.diag([1.0, 3.0, 5.0]), np.array([5.0, 2.0, 1.0]), 100.0
+    runs = {M: gpss(K, y, rho, tol=0.0, max_iter=3, trace=True,
+                    params=GPSSParams(M=M))["trace"] for M in (1, 2, 3)}
+    for M, tr in runs.items():
+        assert tr[0]["f"] == pytest.approx(g["C.f0"][0], rel=1e-15)
+        assert tr[0]["alpha"] == pytest.approx(g["C.alpha0"][0], rel=1e-15)
+        assert tr[0]["lam"] == 1.0 and tr[0]["fmax"] == g["C.f0"][0]
+        assert tr[0]["f_new"] == pytest.approx(g["C.f1"][0], rel=1e-14)
+        assert tr[1]["alpha"] == pytest.approx(g["C.alpha1"][0], rel=1e-13)
+        assert tr[1]["gd"] == pytest.approx(g["C.gd1"][0], rel=1e-13)
+        for r in tr:
+            assert r["l1"] < rho
+    # M = 1: monotone Armijo, one reduction
+    r = runs[1][1]
+    assert r["fmax"] == pytest.approx(g["C.f1"][0], rel=1e-14)
+    assert (r["lam"], r["nb"]) == (0.5, 1)
+    assert r["f_new"] == pytest.approx(g["C.f2_M1"][0], rel=1e-13)
+    np.testing.assert_allclose(gpss(K, y, rho, tol=0.0, max_iter=2)["x"], g["C.x2_M1"],
+                               rtol=1e-13)
+    # M = 2, 3: the increase is accepted at lambda = 1
+    for M in (2, 3):
+        r = runs[M][1]
+        assert r["fmax"] == pytest.approx(g["C.fmax1_M2"][0], rel=1e-15)
+        assert (r["lam"], r["nb"]) == (1.0, 0)
+        assert r["f_new"] == pytest.approx(g["C.f2_M2"][0], rel=1e-13)
+        assert r["f_new"] > r["f"]
+        x2 = gpss(K, y, rho, tol=0.0, max_iter=2, params=GPSSParams(M=M))["x"]
+        np.testing.assert_allclose(x2, g["C.x2_M2"], rtol=1e-13)
+    assert runs[2][2]["fmax"] == pytest.approx(g["C.fmax2_M2"][0], rel=1e-13)
+    assert runs[3][2]["fmax"] == pytest.approx(g["C.fmax2_M3"][0], rel=1e-15)
+
+
 # --------------------------------------------------------------------------
 # full solutions against exact references
 # --------------------------------------------------------------------------

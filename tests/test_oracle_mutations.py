@@ -91,6 +91,17 @@ def _pins(mods):
     gp.ss_update(5, 10.0, 1.0, 1 / 0.9, st, P)
     a, _ = gp.ss_update(6, 10.0, 1.0, 1 / 0.95, st, P)
     ok &= np.isclose(a, 0.8) and np.isclose(st.tau, 0.5 * 0.9 * 1.1 * 0.9 * 0.9)
+    # nonmonotone window (test_gpss_nonmonotone_hand_example): at k = 1 the
+    # window of M = 2 still holds f0 = 30 and accepts the rise to 29.09; at
+    # k = 2 it holds only f1, f2
+    K, y = np.diag([1.0, 3.0, 5.0]), np.array([5.0, 2.0, 1.0])
+    tr1 = gp.gpss(K, y, 100.0, tol=0.0, max_iter=2, trace=True,
+                  params=gp.GPSSParams(M=1))["trace"]
+    ok &= tr1[1]["lam"] == 0.5 and tr1[1]["nb"] == 1
+    tr2 = gp.gpss(K, y, 100.0, tol=0.0, max_iter=3, trace=True,
+                  params=gp.GPSSParams(M=2))["trace"]
+    ok &= tr2[1]["lam"] == 1.0 and np.isclose(tr2[1]["f_new"], 29.091255602545022, rtol=1e-13)
+    ok &= np.isclose(tr2[2]["fmax"], 29.091255602545022, rtol=1e-13)
     return bool(ok)
 
 
@@ -109,6 +120,10 @@ MUTATIONS = [
     ("gpss", "z = g_new - g\n", "z = g - g_new\n"),                         # sign of z
     ("gpss", "alpha = p.alpha_max if nrm == 0.0 else _clamp(1.0 / nrm, p)",
              "alpha = p.alpha_max if nrm == 0.0 else _clamp(nrm, p)"),     # alpha_0
+    ("gpss", "fmax = max(f_hist[-p.M:])", "fmax = f_hist[-1]"),         # memory M ignored
+    ("gpss", "fmax = max(f_hist[-p.M:])", "fmax = max(f_hist[-(p.M + 1):])"),  # window too long
+    ("gpss", "fmax = max(f_hist[-p.M:])", "fmax = max(f_hist[-p.M:][1:] or f_hist[-1:])"),  # too short
+    ("gpss", "f_hist.append(f)", "f_hist.append(f_hist[-1])"),             # stale history
     ("projection", "t = (cw[jstar] - rho) / (jstar + 1)", "t = (cw[jstar] - rho) / (jstar + 2)"),
     ("projection", "positive = w - (cw - rho) / j > 0", "positive = w - (cw + rho) / j > 0"),
 ]
