@@ -12,6 +12,9 @@ methods for l1-constrained signal recovery by steplength selection rules"):
   * projection.py - Euclidean projection onto the l1 ball (sort based).
   * gpss.py       - Algorithm 1 (gradient projection) driven by Algorithm 2
                     (adaptive Barzilai-Borwein alternation), Section 3.
+  * fom.py        - the comparison methods of Section 2: ISTA (item 1),
+                    FISTA (item 2, equation (3)) and projected steepest
+                    descent (item 5).
   * lista.py      - unrolled soft-thresholding network (ISTA of Section 2,
                     item 1, with learned matrices) forward and backward pass.
   * exact.py      - exact references used to pin the above: brute-force

@@ -21,7 +21,7 @@ def _load_mutant(module, old, new):
     pkg.__path__ = [os.path.join(ROOT, "oracle")]
     sys.modules["oracle_mut"] = pkg
     mods = {}
-    for name in ("projection", "gpss"):
+    for name in ("projection", "gpss", "fom"):
         path = os.path.join(ROOT, "oracle", f"{name}.py")
         src = open(path).read()
         if name == module:
@@ -102,6 +102,18 @@ def _pins(mods):
                   params=gp.GPSSParams(M=2))["trace"]
     ok &= tr2[1]["lam"] == 1.0 and np.isclose(tr2[1]["f_new"], 29.091255602545022, rtol=1e-13)
     ok &= np.isclose(tr2[2]["fmax"], 29.091255602545022, rtol=1e-13)
+    # comparison methods (test_oracle_fom, tests/golden/fom_hand_examples.txt)
+    fm = mods["fom"]
+    K1, y1 = np.array([[0.5]]), np.array([1.0])
+    tr = fm.ista(K1, y1, 0.1, max_iter=3, trace=True)["trace"]
+    ok &= np.allclose([r["x"][0] for r in tr], [0.4, 0.7, 0.925], rtol=1e-14)
+    tr = fm.fista(K1, y1, 0.1, max_iter=3, trace=True)["trace"]
+    ok &= np.allclose([r["x"][0] for r in tr], [0.4, 0.7845260575375963, 1.1135701132020648], rtol=1e-13)
+    K2, y2 = np.diag([1.0, 0.5]), np.array([1.0, 1.0])
+    tr = fm.psd(K2, y2, 100.0, max_iter=2, trace=True)["trace"]
+    ok &= np.allclose(tr[1]["x"], [25 / 34, 25 / 17], rtol=1e-13)
+    tr = fm.psd(K2, y2, 1.0, max_iter=1, trace=True)["trace"]
+    ok &= np.allclose(tr[0]["x"], [27 / 34, 7 / 34], rtol=1e-13)
     return bool(ok)
 
 
@@ -124,6 +136,15 @@ MUTATIONS = [
     ("gpss", "fmax = max(f_hist[-p.M:])", "fmax = max(f_hist[-(p.M + 1):])"),  # window too long
     ("gpss", "fmax = max(f_hist[-p.M:])", "fmax = max(f_hist[-p.M:][1:] or f_hist[-1:])"),  # too short
     ("gpss", "f_hist.append(f)", "f_hist.append(f_hist[-1])"),             # stale history
+    ("fom", "z = x + ((t - 1.0) / t_next) * (x - x_prev)", "z = x + (t / t_next) * (x - x_prev)"),  # momentum
+    ("fom", "t_next = (1.0 + math.sqrt(1.0 + 4.0 * t * t)) / 2.0",
+            "t_next = (1.0 + math.sqrt(1.0 + 2.0 * t * t)) / 2.0"),           # t recursion
+    ("fom", "x = soft_threshold(x + tau * r, tau * lam)",
+            "x = soft_threshold(x + tau * r, 2.0 * tau * lam)"),             # ISTA threshold
+    ("fom", "r = K.T @ (y - K @ x)                      # the residual of step k",
+            "r = K.T @ (K @ x - y)"),                                        # residual sign
+    ("fom", "beta = rr / kk", "beta = kk / rr"),                              # PSD step inverted
+    ("fom", "x = project_l1(x + beta * r, rho)", "x = x + beta * r"),        # PSD without P
     ("projection", "t = (cw[jstar] - rho) / (jstar + 1)", "t = (cw[jstar] - rho) / (jstar + 2)"),
     ("projection", "positive = w - (cw - rho) / j > 0", "positive = w - (cw + rho) / j > 0"),
 ]
