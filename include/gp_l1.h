@@ -145,6 +145,31 @@ int gp_l1_solve(gp_handle h, gp_dtype kdtype, const void* K, int64_t n,
                 const void* x0, double tol, void* x_out, const gp_opts* opts,
                 gp_result* res, void* stream);
 
+/* Maximum workspace of gp_l1_solve_noalloc, in bytes (32 MiB). */
+#define GP_NOALLOC_SCRATCH_BYTES (32u << 20)
+
+/* gp_l1_solve without any device allocation, for callers that cannot
+ * allocate: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  Same arguments, kernels and results as gp_l1_solve; the
+ * solver's workspace is a fixed device array of GP_NOALLOC_SCRATCH_BYTES per
+ * device (created with the library's code object and held until the process
+ * ends; gp_create looks up its address), not the handle's growing workspace.
+ * The call makes no hipMalloc/hipFree or other allocating call.
+ * Limits: the workspace needed for (kdtype, n, p) must fit the scratch --
+ * about (36 + 4G) p + 24 n bytes for float or bf16 K and (36 + 8G) p + 24 n
+ * for double K, where G <= 256 is the number of row slabs the K pass uses
+ * (256 once K holds 32 MB or more), so a 4096 x 16384 float K fits --
+ * otherwise GP_E_UNSUPPORTED is returned before anything is launched;
+ * opts.graph and opts.profile must be 0 (GP_E_ARG).
+ * Every call on one device shares that device's scratch, which keeps the
+ * last call's contents (the solver initialises what it reads): calls that
+ * overlap in time on one device -- from two host threads, or on two streams
+ * without ordering between them -- race and give undefined results. */
+int gp_l1_solve_noalloc(gp_handle h, gp_dtype kdtype, const void* K, int64_t n,
+                        int64_t p, int64_t ldk, const void* y, double rho,
+                        const void* x0, double tol, void* x_out,
+                        const gp_opts* opts, gp_result* res, void* stream);
+
 /* B independent problems that share one K (B right-hand sides).
  * Y: device B x n (ldy >= n), rho: host array of B radii, X0: device B x p
  * (ldx >= p) or NULL, X_out: device B x p (ldx).  Each problem runs its own

@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 
@@ -17,7 +18,34 @@
 
 using namespace gpl1;
 
+// Fixed workspace of gp_l1_solve_noalloc: one copy per device, held until the
+// process ends.  Host code never uses this name as an address; it works with
+// the per-device address that gp_create looks up (scratch_ptr).
+static __device__ __align__(256) unsigned char scratch[GP_NOALLOC_SCRATCH_BYTES];
+
 namespace gpl1 {
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device `device`, looked up once.
+static int setup_scratch(int device) {
+    if (device < 0 || device >= kMaxDevices) return GP_E_UNSUPPORTED;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr[device]) return GP_OK_TOL;
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) { (void)hipGetLastError(); return GP_E_HIP; }
+    g_scratch_ptr[device] = ptr;
+    return GP_OK_TOL;
+}
+
+static void* scratch_ptr(int device) {
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return g_scratch_ptr[device];
+}
 
 const char* status_name(int s) {
     switch (s) {
@@ -358,6 +386,13 @@ int gp_create(gp_handle* out, int device) {
         delete h;
         return GP_E_HIP;
     }
+    // the allocation-free solve's scratch: its address on this device (the
+    // device is current here)
+    if (setup_scratch(device) != GP_OK_TOL) {
+        (void)hipHostFree(h->host_state);
+        delete h;
+        return GP_E_HIP;
+    }
     *out = h;
     return GP_OK_TOL;
 }
@@ -423,9 +458,16 @@ int gp_l1_project(gp_handle h, gp_dtype vdtype, const void* v, int64_t p, double
     return GP_OK_TOL;
 }
 
-int gp_l1_solve(gp_handle h, gp_dtype kdtype, const void* K, int64_t n, int64_t p, int64_t ldk, const void* y,
-                double rho, const void* x0, double tol, void* x_out, const gp_opts* opts, gp_result* res,
-                void* stream) {
+}  // extern "C"
+
+namespace gpl1 {
+
+// One problem.  `fixed_ws` NULL: the handle's workspace, grown on demand;
+// otherwise the caller-provided device buffer of `fixed_bytes` (nothing is
+// allocated, and shapes whose workspace does not fit are refused).
+static int solve_single(gp_handle h, gp_dtype kdtype, const void* K, int64_t n, int64_t p, int64_t ldk,
+                        const void* y, double rho, const void* x0, double tol, void* x_out, const gp_opts* opts,
+                        gp_result* res, void* stream, void* fixed_ws, size_t fixed_bytes) {
     if (!h) return GP_E_ARG;
     h->err.clear();
     if (!res) return fail(h, GP_E_ARG, "res must not be NULL");
@@ -445,10 +487,21 @@ int gp_l1_solve(gp_handle h, gp_dtype kdtype, const void* K, int64_t n, int64_t 
     Plan P = plan_single(kdtype, n, p, o);
     if (P.cfg < 0)
         return fail(h, GP_E_UNSUPPORTED, "p = " + std::to_string(p) + " exceeds the fused kernel's column capacity");
+    if (fixed_ws) {
+        if (o.graph || o.profile)
+            return fail(h, GP_E_ARG, "the allocation-free solve takes neither opts.graph nor opts.profile");
+        if (P.bytes > fixed_bytes)
+            return fail(h, GP_E_UNSUPPORTED, "n = " + std::to_string(n) + ", p = " + std::to_string(p) +
+                                                 " needs " + std::to_string(P.bytes) +
+                                                 " bytes of workspace; the fixed scratch holds " +
+                                                 std::to_string(fixed_bytes));
+    }
     hipError_t e = hipSetDevice(h->device);
     if (e != hipSuccess) return hip_fail(h, e, "hipSetDevice");
-    rc = ensure_workspace(h, P.bytes);
-    if (rc) return rc;
+    if (!fixed_ws) {
+        rc = ensure_workspace(h, P.bytes);
+        if (rc) return rc;
+    }
     hipStream_t s = (hipStream_t)stream;
     const hipStream_t user_stream = s;
     if (o.graph && !s) {
@@ -463,7 +516,7 @@ int gp_l1_solve(gp_handle h, gp_dtype kdtype, const void* K, int64_t n, int64_t 
         if (e != hipSuccess) return hip_fail(h, e, "graph stream order");
         s = h->gstream;
     }
-    char* ws = (char*)h->ws;
+    char* ws = fixed_ws ? (char*)fixed_ws : (char*)h->ws;
     GPState* st = (GPState*)(ws + P.o_state);
     double* x = (double*)(ws + P.o_x);
     double* g = (double*)(ws + P.o_g);
@@ -620,6 +673,29 @@ int gp_l1_solve(gp_handle h, gp_dtype kdtype, const void* K, int64_t n, int64_t 
     }
     if (res->status < 0) return fail(h, res->status, "solve ended with a non-finite value");
     return res->status;
+}
+
+}  // namespace gpl1
+
+extern "C" {
+
+int gp_l1_solve(gp_handle h, gp_dtype kdtype, const void* K, int64_t n, int64_t p, int64_t ldk, const void* y,
+                double rho, const void* x0, double tol, void* x_out, const gp_opts* opts, gp_result* res,
+                void* stream) {
+    return solve_single(h, kdtype, K, n, p, ldk, y, rho, x0, tol, x_out, opts, res, stream, nullptr, 0);
+}
+
+int gp_l1_solve_noalloc(gp_handle h, gp_dtype kdtype, const void* K, int64_t n, int64_t p, int64_t ldk,
+                        const void* y, double rho, const void* x0, double tol, void* x_out, const gp_opts* opts,
+                        gp_result* res, void* stream) {
+    if (!h) return GP_E_ARG;
+    void* ptr = scratch_ptr(h->device);
+    if (!ptr) {
+        if (res) { std::memset(res, 0, sizeof(*res)); res->status = GP_E_HIP; }
+        return fail(h, GP_E_HIP, "the fixed scratch of this device has no address (gp_create did not set it up)");
+    }
+    return solve_single(h, kdtype, K, n, p, ldk, y, rho, x0, tol, x_out, opts, res, stream, ptr,
+                        (size_t)GP_NOALLOC_SCRATCH_BYTES);
 }
 
 }  // extern "C"

@@ -20,7 +20,7 @@ STATUS = {0: "ok_tol", 1: "stationary", 2: "max_iter", 3: "reached_target",
           -3: "hip_error", -4: "out_of_memory", -5: "unsupported"}
 
 SYMBOLS = ("gp_opts_default", "gp_create", "gp_destroy", "gp_last_error",
-           "gp_l1_project", "gp_l1_solve", "gp_l1_solve_batched_shared",
+           "gp_l1_project", "gp_l1_solve", "gp_l1_solve_noalloc", "gp_l1_solve_batched_shared",
            "gp_l1_solve_batched_var", "gp_lista_create", "gp_lista_destroy",
            "gp_lista_init_from_K", "gp_lista_set_weights", "gp_lista_get_weights",
            "gp_lista_forward", "gp_lista_train_step", "gp_lista_gradients", "gp_lista_save",
@@ -85,6 +85,8 @@ def load():
     lib.gp_l1_solve.argtypes = [vp, i32, vp, i64, i64, i64, vp, dbl, vp, dbl, vp,
                                 C.POINTER(GPOpts), C.POINTER(GPResult), vp]
     lib.gp_l1_solve.restype = i32
+    lib.gp_l1_solve_noalloc.argtypes = lib.gp_l1_solve.argtypes
+    lib.gp_l1_solve_noalloc.restype = i32
     lib.gp_l1_solve_batched_shared.argtypes = [
         vp, i32, vp, i64, i64, i64, vp, i64, i64, C.POINTER(dbl), vp, i64, dbl,
         vp, C.POINTER(GPOpts), C.POINTER(GPResult), vp]
@@ -245,6 +247,16 @@ class Handle:
     # -- one problem ----------------------------------------------------
     def solve(self, K, y, rho: float, x0=None, tol: float = 1e-10, out=None,
               opts: GPOpts | None = None, stream=None, **kw):
+        """gp_l1_solve: the handle's workspace grows as needed."""
+        return self._solve(self.lib.gp_l1_solve, K, y, rho, x0, tol, out, opts, stream, kw)
+
+    def solve_noalloc(self, K, y, rho: float, x0=None, tol: float = 1e-10, out=None,
+                      opts: GPOpts | None = None, stream=None, **kw):
+        """gp_l1_solve_noalloc: the device's fixed scratch, no allocation in the
+        library (`out` should be given by callers that cannot allocate)."""
+        return self._solve(self.lib.gp_l1_solve_noalloc, K, y, rho, x0, tol, out, opts, stream, kw)
+
+    def _solve(self, fn, K, y, rho, x0, tol, out, opts, stream, kw):
         torch = _torch()
         _check_dev(K, y, x0)
         kdt = k_dtype(K)
@@ -257,12 +269,14 @@ class Handle:
             raise ValueError(f"y must be contiguous {vdt} of length {n}")
         if x0 is not None and (x0.dtype != vdt or x0.numel() != p or not x0.is_contiguous()):
             raise ValueError(f"x0 must be contiguous {vdt} of length {p}")
-        out = torch.empty(p, dtype=vdt, device=K.device) if out is None else out
+        if out is None:
+            out = torch.empty(p, dtype=vdt, device=K.device)
+        elif out.dtype != vdt or out.numel() != p or not out.is_contiguous() or not out.is_cuda:
+            raise ValueError(f"out must be a contiguous device {vdt} tensor of length {p}")
         o = opts if opts is not None else default_opts(**_tuned(kdt, n, p, kw))
         res = GPResult()
-        rc = self.lib.gp_l1_solve(self.h, kdt, _ptr(K), n, p, ldk, _ptr(y), float(rho),
-                                  _ptr(x0), float(tol), _ptr(out), C.byref(o),
-                                  C.byref(res), _stream(stream))
+        rc = fn(self.h, kdt, _ptr(K), n, p, ldk, _ptr(y), float(rho), _ptr(x0), float(tol),
+                _ptr(out), C.byref(o), C.byref(res), _stream(stream))
         self._raise(rc)
         return out, res.as_dict()
 

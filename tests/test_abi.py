@@ -82,6 +82,8 @@ def test_null_handle_is_rejected_without_gpu_work():
     res = gpl1.GPResult()
     assert lib.gp_l1_solve(None, 1, None, 1, 1, 1, None, 1.0, None, 0.0, None, None,
                            C.byref(res), None) == -1
+    assert lib.gp_l1_solve_noalloc(None, 1, None, 1, 1, 1, None, 1.0, None, 0.0, None, None,
+                                   C.byref(res), None) == -1
     assert lib.gp_destroy(None) == 0
     assert lib.gp_l1_project(None, 0, None, 0, 1.0, None, None, None) == -1
 
