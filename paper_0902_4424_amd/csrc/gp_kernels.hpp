@@ -73,6 +73,7 @@ __device__ __forceinline__ void commit_pending(GPState* st) {
         if (st->nhist < MAX_M) st->nhist++;
     } else {                                // same iterate, f recomputed (refresh)
         st->fhist[st->hpos] = st->f_new;
+        if (st->nhist == 0) st->nhist = 1;  // f(x^0): the first value of the window
     }
     st->f = st->f_new;
     st->k = st->k_new;
@@ -143,6 +144,8 @@ __device__ __forceinline__ void iter_rule(GPState& S, bool need_ss, double dw, d
             hpos = (hpos0 + 1) % MAX_M;
             S.hpos = hpos;
             S.nhist = nhist0 < MAX_M ? nhist0 + 1 : nhist0;
+        } else if (nhist0 == 0) {           // f(x^0): the first value of the window
+            S.nhist = 1;
         }
         S.fhist[hpos] = f_new;
         S.f = f_new;

@@ -184,6 +184,81 @@ def test_shared_per_problem_targets(H):
         H.solve_batched_shared(Kt, Y, batch.rho, f_targets=targets[:5])
 
 
+def _nonmono_batch():
+    # the ill-conditioned 32 x 32 operator on which M changes the path at
+    # k = 9, stored FP32, with three right-hand sides: the instance's own y
+    # and two more from fresh 5-sparse signals
+    inst = instances.illcond_instance(32, 5, dtype="f32", seed=4, cond=1e3)
+    rng = np.random.default_rng(44)
+    ys, rhos = [inst.y_store], [inst.rho]
+    for _ in range(2):
+        x = np.zeros(32)
+        x[rng.choice(32, 5, replace=False)] = rng.choice([-1.0, 1.0], 5)
+        ys.append((inst.K64 @ x + 1e-3 * rng.standard_normal(32)).astype(np.float32))
+        rhos.append(float(np.abs(x).sum()))
+    return inst, np.stack(ys), rhos
+
+
+@pytest.mark.parametrize("k", [12, 16])
+def test_shared_nonmonotone_trajectory(H, k):
+    """Line-search memory M = 1, 3, 5 in the shared-K batch (FP32 K as three
+    bf16 planes): after k iterations every column's backtrack count equals the
+    oracle's and its iterate is within the FP32 bar of the oracle's k-th
+    iterate; on the first column M changes the path (the iterates differ by
+    far more than that bar)."""
+    from oracle import GPSSParams
+    inst, Ys, rhos = _nonmono_batch()
+    Kt = torch.from_numpy(inst.K_store).to(DEV)
+    Y = torch.from_numpy(Ys).to(DEV)
+    xs = {}
+    for M in (1, 3, 5):
+        say(f"[batched-shared] nonmonotone M={M}, {k} iterations, 3 columns")
+        X, res = H.solve_batched_shared(Kt, Y, rhos, tol=0.0, max_iter=k, M=M)
+        Xn = X.cpu().double().numpy()
+        for b in range(3):
+            ref = gpss(inst.K64, Ys[b].astype(np.float64), rhos[b], tol=0.0, max_iter=k,
+                       params=GPSSParams(M=M))
+            assert res[b]["iters"] == ref["iters"] == k
+            assert res[b]["backtracks"] == ref["backtracks"], (M, b)
+            err = np.linalg.norm(Xn[b] - ref["x"]) / np.linalg.norm(ref["x"])
+            assert err <= 1e-4, (M, b, err)
+        xs[M] = Xn[0]
+    nx = np.linalg.norm(xs[1])
+    assert np.linalg.norm(xs[1] - xs[3]) > 1e-3 * nx
+    assert np.linalg.norm(xs[3] - xs[5]) > 1e-3 * nx
+
+
+@pytest.mark.parametrize("k", [10, 16])
+def test_var_nonmonotone_trajectory(H, k):
+    """M = 1, 3, 5 in the uneven batch (FP64): the hand-derived 3 x 3 example
+    of Algorithm 1 step 4, the ill-conditioned 32 x 32 problem and a Gaussian
+    problem in one batch; after k iterations iterates and backtrack counts
+    equal the oracle's."""
+    from oracle import GPSSParams
+    ill = instances.illcond_instance(32, 5, dtype="f64", seed=4, cond=1e3)
+    gau = instances.gaussian_instance(96, 384, 6, dtype="f64", seed=45)
+    Kc = np.diag([1.0, 3.0, 5.0])
+    yc = np.array([5.0, 2.0, 1.0])
+    cases = [(Kc, yc, 100.0), (ill.K64, ill.y64, ill.rho), (gau.K64, gau.y64, gau.rho)]
+    probs = [(torch.from_numpy(np.ascontiguousarray(K)).to(DEV), torch.from_numpy(y).to(DEV), r)
+             for K, y, r in cases]
+    xs = {}
+    for M in (1, 3, 5):
+        say(f"[batched-var] nonmonotone M={M}, {k} iterations")
+        X, res = H.solve_batched_var(probs, tol=0.0, max_iter=k, M=M)
+        for i, (K, y, r) in enumerate(cases):
+            ref = gpss(K, y, r, tol=0.0, max_iter=k, params=GPSSParams(M=M))
+            assert res[i]["iters"] == ref["iters"], (M, i)
+            assert res[i]["backtracks"] == ref["backtracks"], (M, i)
+            x = X[i].cpu().numpy()
+            err = np.linalg.norm(x - ref["x"]) / np.linalg.norm(ref["x"])
+            assert err <= 1e-10, (M, i, err)
+        xs[M] = X[1].cpu().numpy()
+    nx = np.linalg.norm(xs[1])
+    assert np.linalg.norm(xs[1] - xs[3]) > 1e-3 * nx
+    assert np.linalg.norm(xs[3] - xs[5]) > 1e-3 * nx
+
+
 @pytest.mark.parametrize("dtype", ["bf16", "f32"])
 def test_shared_active_set_is_exact(H, dtype):
     say(f"[batched-shared] finished problems dropped from the launches ({dtype}): same bits")

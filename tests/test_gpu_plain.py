@@ -300,6 +300,84 @@ def test_nonmonotone_memory(H):
     assert gap <= 1e-10 and err <= 1e-6
 
 
+def _golden(name):
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", name)
+    vals = {}
+    for line in open(path):
+        line = line.strip()
+        if not line or line.startswith("#"):
+            continue
+        k, v = line.split("=")
+        vals[k.strip()] = [float(t) for t in v.split()]
+    return vals
+
+
+@pytest.mark.parametrize("M", [1, 2, 3])
+def test_nonmonotone_hand_example_on_gpu(H, M):
+    """Algorithm 1 step 4 on the device, pinned by the hand-derived example
+    (tests/golden/nonmonotone_hand_example.txt): K = diag(1, 3, 5), y = (5, 2, 1),
+    rho = 100.  The second step raises f from 28.39 to 29.09; M = 1 rejects
+    it (one reduction to lambda = 1/2), M = 2 and 3 accept it (f0 = 30 is
+    still in the window)."""
+    say(f"[solve] hand nonmonotone example M={M}")
+    g = _golden("nonmonotone_hand_example.txt")
+    K = torch.tensor(np.diag([1.0, 3.0, 5.0]), device=DEV)
+    y = torch.tensor([5.0, 2.0, 1.0], dtype=torch.float64, device=DEV)
+    x1, r1 = H.solve(K, y, 100.0, tol=0.0, max_iter=1, M=M)
+    np.testing.assert_allclose(x1.cpu().numpy(), g["C.x1"], rtol=1e-14)
+    assert r1["f"] == pytest.approx(g["C.f1"][0], rel=1e-14) and r1["backtracks"] == 0
+    x2, r2 = H.solve(K, y, 100.0, tol=0.0, max_iter=2, M=M)
+    assert r2["iters"] == 2
+    if M == 1:
+        assert r2["backtracks"] == 1
+        assert r2["f"] == pytest.approx(g["C.f2_M1"][0], rel=1e-13)
+        np.testing.assert_allclose(x2.cpu().numpy(), g["C.x2_M1"], rtol=1e-13)
+    else:
+        assert r2["backtracks"] == 0
+        assert r2["f"] == pytest.approx(g["C.f2_M2"][0], rel=1e-13)
+        assert r2["f"] > r1["f"]
+        np.testing.assert_allclose(x2.cpu().numpy(), g["C.x2_M2"], rtol=1e-13)
+
+
+# An ill-conditioned 32 x 32 problem (singular values 1 .. 1e-3) on which the
+# line-search memory changes the path early: at k = 9 the step raises f by
+# 16 % (M = 3) or 3x (M = 5); M = 1 needs two reductions there, M = 3 one,
+# M = 5 none, and the iterates then stay apart by 1-10 %.
+def _nonmono_instance():
+    return instances.illcond_instance(32, 5, dtype="f64", seed=4, cond=1e3)
+
+
+@pytest.mark.parametrize("k", [8, 10, 12, 16, 20])
+def test_nonmonotone_trajectory_matches_oracle(H, k):
+    """Trajectory level for M = 1, 3, 5: after k accepted updates the FP64
+    iterate, objective and backtrack count equal the oracle's, and the three
+    memories give different iterates once the memory matters (k > 9)."""
+    from oracle import GPSSParams
+    inst = _nonmono_instance()
+    K, y = _K_tensor(inst), _dev(inst.y_store)
+    xs, bts = {}, {}
+    for M in (1, 3, 5):
+        say(f"[solve] FP64 nonmonotone trajectory M={M} after {k} iterations")
+        ref = gpss(inst.K64, inst.y64, inst.rho, tol=0.0, max_iter=k, params=GPSSParams(M=M))
+        x, res = H.solve(K, y, inst.rho, tol=0.0, max_iter=k, M=M)
+        assert res["iters"] == ref["iters"] == k
+        assert res["backtracks"] == ref["backtracks"]
+        xn = x.cpu().numpy()
+        err = np.linalg.norm(xn - ref["x"]) / np.linalg.norm(ref["x"])
+        assert err <= 1e-10, (M, err)
+        assert abs(res["f"] - ref["f"]) <= 1e-10 * ref["f"]
+        xs[M], bts[M] = xn, res["backtracks"]
+    nx = np.linalg.norm(xs[1])
+    if k > 9:
+        assert bts[1] > bts[3] > bts[5]
+        assert np.linalg.norm(xs[1] - xs[3]) > 1e-3 * nx
+        assert np.linalg.norm(xs[3] - xs[5]) > 1e-3 * nx
+    else:
+        assert bts[1] == bts[3] == bts[5]
+        assert np.array_equal(xs[1], xs[3]) and np.array_equal(xs[3], xs[5])
+
+
 def test_sampled_profiling(H):
     say("[solve] timing every k-th fused launch; x unchanged by it")
     inst = instances.gaussian_instance(512, 2048, 20, dtype="f32", seed=5)
