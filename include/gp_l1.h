@@ -51,7 +51,7 @@ typedef enum {
     GP_OK_TOL = 0,          /* relative objective change fell below tol        */
     GP_STATIONARY = 1,      /* P(x - alpha g) == x, or grad'd >= 0 in rounding  */
     GP_MAX_ITER = 2,        /* iteration budget used up                         */
-    GP_REACHED_TARGET = 3,  /* f(x) <= opts.f_target                            */
+    GP_REACHED_TARGET = 3,  /* f(x) <= opts.f_target, checked in double         */
     GP_BACKTRACK_LIMIT = 4, /* Armijo test failed after backtrack_cap reductions */
     GP_E_ARG = -1,          /* bad argument (sizes, rho, tol, null pointer)      */
     GP_E_NONFINITE = -2,    /* NaN/Inf in K, y or arising during the run         */
@@ -72,7 +72,14 @@ typedef struct {
     double tau1;          /* initial alternation threshold, (0,1)              */
     int32_t M_alpha;      /* alpha^(2) window = last M_alpha+1 iterations, 0..3 */
     int32_t max_iter;     /* iteration budget (>= 0)                           */
-    double f_target;      /* stop once f <= f_target (ignored if < 0)          */
+    double f_target;      /* stop once f <= f_target (ignored if < 0).  The iteration
+                             tracks f with FP32-accurate products, so a stop it
+                             proposes is checked: f is recomputed in double from
+                             the stored K, y and the returned x (narrowed to the
+                             vector dtype); if that exceeds f_target the problem
+                             iterates on with a lower internal target.  A result
+                             with GP_REACHED_TARGET therefore has result.f, the
+                             double value, <= f_target. */
     int32_t refresh_every;/* recompute r = Kx - y, g = 2K^T r every R iters (0 = never) */
     int32_t backtrack_cap;/* max reductions of the line-search step            */
     int32_t chunk;        /* iterations enqueued between host status polls     */
@@ -108,6 +115,8 @@ typedef struct {
     int32_t n_fused;      /* with opts.profile: number of fused launches timed  */
     int32_t proj_passes;  /* threshold-search passes summed over the iterations */
     int32_t x0_rejected;  /* 1 if opts.x0_fallback replaced x0 by 0            */
+    int32_t reopened;     /* stops at the target that the double check overturned */
+    int32_t reserved_;
 } gp_result;
 
 typedef struct gp_handle_s* gp_handle;

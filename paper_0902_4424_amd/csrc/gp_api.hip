@@ -15,6 +15,7 @@
 #include "gp_l1.h"
 #include "gp_kernels.hpp"
 #include "gp_internal.hpp"
+#include "gp_verify.hpp"
 
 using namespace gpl1;
 
@@ -336,8 +337,37 @@ Plan plan_single(gp_dtype dt, int64_t n, int64_t p, const gp_opts& o) {
     P.o_spart = take(sizeof(double) * SPART * P.G);
     P.o_upart = take(sizeof(double) * 4 * P.GU);
     P.o_wpart = take((size_t)wsz * P.ldw * P.G);
+    P.nvitems = (int)((n + VR_ROWS - 1) / VR_ROWS);
+    P.o_vprob = take(sizeof(VerProb));
+    P.o_vitem = take(sizeof(VerItem) * P.nvitems);
+    P.o_vpart = take(sizeof(double) * P.nvitems);
+    P.o_vidx = take(sizeof(int32_t) * 4);
     P.bytes = off;
     return P;
+}
+
+// Descriptor, row items and index arrays of the single problem's target
+// check, written on the device (no host buffer to keep alive).
+__global__ void k_verify_setup_single(VerProb* vp, VerItem* items, int32_t* idx, int nitems, VerProb prob) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) {
+        *vp = prob;
+        idx[0] = 0;          // the checked problem
+        idx[1] = 0;          // its items: [0, nitems)
+        idx[2] = nitems;
+    }
+    if (i < nitems) items[i] = VerItem{0, i};
+}
+
+void launch_verify_rows(gp_dtype dt, hipStream_t s, int nitems, const VerProb* vp, const VerItem* items,
+                        double* part) {
+    if (nitems <= 0) return;
+    if (dt == GP_F64)
+        hipLaunchKernelGGL(k_verify_rows<double>, dim3((unsigned)nitems), dim3(VR_T), 0, s, vp, items, part);
+    else if (dt == GP_F32)
+        hipLaunchKernelGGL(k_verify_rows<float>, dim3((unsigned)nitems), dim3(VR_T), 0, s, vp, items, part);
+    else
+        hipLaunchKernelGGL(k_verify_rows<bf16_t>, dim3((unsigned)nitems), dim3(VR_T), 0, s, vp, items, part);
 }
 
 }  // namespace gpl1
@@ -585,6 +615,19 @@ static int solve_single(gp_handle h, gp_dtype kdtype, const void* K, int64_t n, 
         refresh();
     }
     launch_proj(s, st, PM_ALPHA0, p, x, g, nullptr, nullptr, 0, vb, nullptr);
+    // target check set-up: rows of K against x (narrowed as returned) and y
+    const bool check_target = o.f_target >= 0.0;
+    VerProb* vprob = (VerProb*)(ws + P.o_vprob);
+    VerItem* vitems = (VerItem*)(ws + P.o_vitem);
+    double* vpart = (double*)(ws + P.o_vpart);
+    int32_t* vidx = (int32_t*)(ws + P.o_vidx);
+    if (check_target) {
+        const int esz_k = esize(kdtype);
+        const VerProb vp{K, ldk, n, p, x, y64, f64v ? 0 : 1,
+                         ((ldk * esz_k) % 16 == 0 && ((uintptr_t)K) % 16 == 0) ? 1 : 0};
+        hipLaunchKernelGGL(k_verify_setup_single, dim3((unsigned)((P.nvitems + 255) / 256)), dim3(256), 0, s, vprob,
+                           vitems, vidx, P.nvitems, vp);
+    }
     e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(h, e, "init launch");
 
@@ -630,6 +673,18 @@ static int solve_single(gp_handle h, gp_dtype kdtype, const void* K, int64_t n, 
         if (pe == hipSuccess) pe = hipStreamSynchronize(s);
         return pe == hipSuccess ? 0 : hip_fail(h, pe, "status poll");
     };
+    // after a poll that found the solve stopped at its target: recompute f in
+    // double and keep the stop (0) or reopen the solve (1); < 0: an error
+    auto check = [&]() -> int {
+        if (!check_target || !target_checkable(h->host_state->status) || h->host_state->tcheck) return 0;
+        launch_verify_rows(kdtype, s, P.nvitems, vprob, vitems, vpart);
+        hipLaunchKernelGGL(k_verify_decide, dim3(1), dim3(64), 0, s, st, vidx, vidx + 1, 1, vpart, 0);
+        hipError_t ce = hipGetLastError();
+        if (ce == hipSuccess) ce = hipMemcpyAsync(h->host_state, st, sizeof(GPState), hipMemcpyDeviceToHost, s);
+        if (ce == hipSuccess) ce = hipStreamSynchronize(s);
+        if (ce != hipSuccess) return hip_fail(h, ce, "target check");
+        return h->host_state->done ? 0 : 1;
+    };
     bool finished = false;
     int it = 0;
     while (it < o.max_iter) {
@@ -638,7 +693,13 @@ static int solve_single(gp_handle h, gp_dtype kdtype, const void* K, int64_t n, 
             if (rc) return rc;
             it += gch;
             if ((rc = poll(false))) return rc;
-            if (h->host_state->done) { finished = true; break; }
+            if (h->host_state->done) {
+                const int re = check();
+                if (re < 0) return re;
+                if (re) { it = h->host_state->k; continue; }
+                finished = true;
+                break;
+            }
             continue;
         }
         const int end = o.graph ? std::min(o.max_iter, (it / gch + 1) * gch) : std::min(o.max_iter, it + o.chunk);
@@ -660,9 +721,23 @@ static int solve_single(gp_handle h, gp_dtype kdtype, const void* K, int64_t n, 
         e = hipGetLastError();
         if (e != hipSuccess) return hip_fail(h, e, "iteration launch");
         if ((rc = poll(it >= o.max_iter))) return rc;
-        if (h->host_state->done) { finished = true; break; }
+        if (h->host_state->done) {
+            const int re = check();
+            if (re < 0) return re;
+            if (re) { it = h->host_state->k; continue; }
+            finished = true;
+            break;
+        }
     }
     if (!finished && (rc = poll(true))) return rc;
+    // the budget is spent: check the last stop; a target stop reopened here
+    // has no iterations left and ends at the budget
+    for (int guard = 0; guard < 2; ++guard) {
+        const int re = check();
+        if (re < 0) return re;
+        if (re == 0) break;
+        if ((rc = poll(true))) return rc;
+    }
     fill_result(*h->host_state, res);
     res->x0_rejected = x0_rejected;
     if (o.profile) {
@@ -712,5 +787,6 @@ void fill_result(const GPState& s, gp_result* res) {
     res->l1norm = s.l1;
     res->proj_passes = s.michelot_total;
     res->x0_rejected = s.x0_rejected;
+    res->reopened = s.reopened;
 }
 }  // namespace gpl1

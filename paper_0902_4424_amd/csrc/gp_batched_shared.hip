@@ -29,6 +29,7 @@
 #include "gp_internal.hpp"
 #include "gp_kernels.hpp"
 #include "gp_l1.h"
+#include "gp_verify.hpp"
 
 using namespace gpl1;
 
@@ -39,7 +40,9 @@ constexpr int BS_PAD = 128;         // GEMM tile: M, N padding
 constexpr int NSPL = 3;             // bf16 planes per FP32 operand
 
 enum BsRowMode : int32_t { BR_REFRESH = 0, BR_ITER = 1 };
-enum BsColMode : int32_t { BC_INIT = 0, BC_ITER = 1, BC_ITER_NOPROJ = 2, BC_REFRESH_PROJ = 3 };
+enum BsColMode : int32_t { BC_INIT = 0, BC_ITER = 1, BC_ITER_NOPROJ = 2, BC_REFRESH_PROJ = 3, BC_PROJ_ONLY = 4 };
+// P.done values: 0 running, 1 stopped, 2 stopped with a target (to be
+// checked), 3 reopened by the check (needs a projection before it runs on)
 
 __device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
     uint32_t u = __float_as_uint(f);
@@ -153,6 +156,7 @@ __global__ __launch_bounds__(BS_T) void k_bs_init(BsPtrs P, GPParams prm, const 
         s.prm = prm;
         s.prm.rho = rb;
         if (ftarget) s.prm.f_target = ftarget[b];
+        s.f_target0 = s.prm.f_target;
         s.tau = prm.tau1;
         s.alpha = prm.amax;
         s.status = ST_MAX_ITER;
@@ -266,7 +270,7 @@ __global__ __launch_bounds__(T) void k_bs_rows(BsPtrs P, int mode) {
         if (fail) {
             st->status = ST_BACKTRACK;
             st->done = 1;
-            P.done[b] = 1;
+            P.done[b] = st->f_target0 >= 0.0 ? 2 : 1;   // with a target: to be checked
         } else {
             const double fn = f + lam * (2.0 * rq + lam * qq);
             st->lam = lam;
@@ -281,10 +285,11 @@ __global__ __launch_bounds__(T) void k_bs_rows(BsPtrs P, int mode) {
             st->ss_pending = 1;
             int stop = 0;
             if (!isfinite(fn)) { st->status = ST_NONFINITE; stop = 1; }
-            else if (Pm.f_target >= 0.0 && fn <= Pm.f_target) { st->status = ST_TARGET; stop = 1; }
+            else if (Pm.f_target >= 0.0 && fn <= Pm.f_target) { st->status = ST_TARGET; stop = 2; }
             else if (Pm.tol > 0.0 && st->rel < Pm.tol) { st->status = ST_OK_TOL; stop = 1; }
             else if (st->k >= Pm.max_iter) { st->status = ST_MAX_ITER; stop = 1; }
-            if (stop) { st->done = 1; P.done[b] = 1; }
+            // a problem with a target is checked whatever ended it (2)
+            if (stop) { st->done = 1; P.done[b] = (st->f_target0 >= 0.0 && stop != 0 && isfinite(fn)) ? 2 : 1; }
         }
     }
     __syncthreads();
@@ -334,7 +339,7 @@ __global__ __launch_bounds__(T) void k_bs_cols(BsPtrs P, int mode) {
     double* g = P.G + b * p;
     const bool iter = mode == BC_ITER || mode == BC_ITER_NOPROJ;
     const int step_pending = iter ? st->ss_pending : 0;
-    const int col_done = P.done[b];
+    const int col_done = mode == BC_PROJ_ONLY ? 0 : P.done[b];
     if (col_done && !step_pending) return;
     auto wval = [&](int64_t j) {
         double sw = 0.0;
@@ -393,6 +398,15 @@ __global__ __launch_bounds__(T) void k_bs_cols(BsPtrs P, int mode) {
                 if (j < p) split3(xr[e], P.Dsp, P.plD, b * P.ppad + j);
                 if (j + 1 < p) split3(xr[e + 1], P.Dsp, P.plD, b * P.ppad + j + 1);
             }
+        }
+    } else if (mode == BC_PROJ_ONLY) {
+        // a problem reopened by the target check: its step and steplength are
+        // applied, x and g are current
+#pragma unroll
+        for (int e = 0; e < NV; ++e) {
+            const int64_t j = 2 * ((e / 2) * T + tid) + (e & 1);
+            xr[e] = j < p ? x[j] : 0.0;
+            gr[e] = j < p ? g[j] : 0.0;
         }
     } else {
         // BC_INIT / BC_REFRESH_PROJ: fresh gradient at the current x
@@ -464,7 +478,102 @@ __global__ __launch_bounds__(T) void k_bs_cols(BsPtrs P, int mode) {
         st->pt = t;
         st->hmode = inside ? 1 : (rho > 0.0 ? 0 : 2);
         st->michelot_total += passes;
-        if (mx[0] == 0.0 || !(sums[0] < 0.0)) { st->status = ST_STATIONARY; st->done = 1; P.done[b] = 1; }
+        if (mx[0] == 0.0 || !(sums[0] < 0.0)) {
+            st->status = ST_STATIONARY;
+            st->done = 1;
+            P.done[b] = st->f_target0 >= 0.0 ? 2 : 1;   // with a target: to be checked
+        } else if (mode == BC_PROJ_ONLY) {
+            st->done = 0;
+            P.done[b] = 0;
+        }
+    }
+}
+
+// Target check of the problems listed in `cand` (one workgroup each): f in
+// double from the padded transposed planes of K (Kt, ppad x npad; one bf16
+// plane for bf16 K, three for FP32 K, which add up exactly to the stored
+// value), y and x narrowed to float as returned.  Only the nonzero entries of
+// x are visited, each adding x_j times the contiguous column j of K to r.
+// The decision marks P.done (1 kept, 3 reopened) and kout[c] = the problem's
+// iteration count.  RPT > 0: n <= RPT * T, r in registers; RPT = 0: r in Qv.
+template <int T, int RPT>
+__global__ __launch_bounds__(T) void k_bs_verify(BsPtrs P, const uint16_t* __restrict__ Kt, int64_t ldkt,
+                                                 int64_t kts, int nK, const int32_t* __restrict__ cand,
+                                                 int32_t* __restrict__ kout) {
+    constexpr int NWV = T / WAVE;
+    __shared__ int32_t sj[T];
+    __shared__ double sv[T];
+    __shared__ int32_t wcnt[NWV];
+    __shared__ double lds[NWV];
+    const int b = cand[blockIdx.x], tid = threadIdx.x;
+    const int lane = tid & (WAVE - 1), wid = tid / WAVE;
+    const int64_t n = P.n, p = P.p;
+    const double* x = P.X + b * p;
+    const double* y = P.Y + b * n;
+    double* rq = P.Qv + b * n;
+    double r[RPT > 0 ? RPT : 1];
+#pragma unroll
+    for (int k = 0; k < (RPT > 0 ? RPT : 1); ++k) r[k] = 0.0;
+    if (RPT == 0)
+        for (int64_t i = tid; i < n; i += T) rq[i] = 0.0;
+    auto kval = [&](const uint16_t* col, int64_t i) {
+        double v = (double)bf16_bits_to_f32(col[i]);
+        if (nK == 3) v = (v + (double)bf16_bits_to_f32(col[kts + i])) + (double)bf16_bits_to_f32(col[2 * kts + i]);
+        return v;
+    };
+    for (int64_t j0 = 0; j0 < p; j0 += T) {
+        const int64_t j = j0 + tid;
+        const double xv = j < p ? (double)(float)x[j] : 0.0;
+        const bool nz = xv != 0.0;
+        // list the block's nonzeros in column order
+        const uint64_t mask = __builtin_amdgcn_ballot_w64(nz);
+        const int below = __builtin_popcountll(mask & ((1ull << lane) - 1ull));
+        __syncthreads();   // the previous block's list is consumed
+        if (lane == 0) wcnt[wid] = __builtin_popcountll(mask);
+        __syncthreads();
+        int base = 0, total = 0;
+#pragma unroll
+        for (int w = 0; w < NWV; ++w) {
+            base += w < wid ? wcnt[w] : 0;
+            total += wcnt[w];
+        }
+        if (nz) { sj[base + below] = (int32_t)j; sv[base + below] = xv; }
+        __syncthreads();
+        for (int c = 0; c < total; ++c) {
+            const uint16_t* col = Kt + (int64_t)sj[c] * ldkt;
+            const double xj = sv[c];
+            if constexpr (RPT > 0) {
+#pragma unroll
+                for (int k = 0; k < RPT; ++k) {
+                    const int64_t i = tid + (int64_t)k * T;
+                    if (i < n) r[k] = fma(kval(col, i), xj, r[k]);
+                }
+            } else {
+                for (int64_t i = tid; i < n; i += T) rq[i] = fma(kval(col, i), xj, rq[i]);
+            }
+        }
+    }
+    double acc = 0.0;
+    if constexpr (RPT > 0) {
+#pragma unroll
+        for (int k = 0; k < RPT; ++k) {
+            const int64_t i = tid + (int64_t)k * T;
+            if (i < n) {
+                const double d = r[k] - y[i];
+                acc += d * d;
+            }
+        }
+    } else {
+        for (int64_t i = tid; i < n; i += T) {
+            const double d = rq[i] - y[i];
+            acc += d * d;
+        }
+    }
+    const double f = block_sum<T>(acc, lds);
+    if (tid == 0) {
+        GPState* st = P.st + b;
+        P.done[b] = target_decide(st, f) ? 1 : 3;
+        kout[blockIdx.x] = st->k;
     }
 }
 
@@ -592,6 +701,7 @@ int solve_batched_shared_mfma(gp_handle h, gp_dtype kdtype, const void* K, int64
     const size_t o_Dsp = take(2 * NSPL * brows * ppad), o_Qsp = take(2 * NSPL * brows * npad);
     const size_t o_Qp = take(4 * (size_t)S1 * brows * npad), o_Wp = take(4 * (size_t)S2 * brows * ppad);
     const size_t o_rho = take(8 * B), o_ft = take(8 * B), o_list = take(4 * bpad);
+    const size_t o_cand = take(4 * B), o_kout = take(4 * B);
     int rc = ensure_workspace(h, off);
     if (rc) return rc;
     char* ws = (char*)h->ws;
@@ -612,6 +722,9 @@ int solve_batched_shared_mfma(gp_handle h, gp_dtype kdtype, const void* K, int64
     P.sQ = brows * npad; P.sW = brows * ppad;
     P.list = nullptr;
     int32_t* dlist = (int32_t*)(ws + o_list);
+    int32_t* dcand = (int32_t*)(ws + o_cand);
+    int32_t* dkout = (int32_t*)(ws + o_kout);
+    const bool check_target = o.f_target >= 0.0 || o.f_targets != nullptr;
     double* drho = (double*)(ws + o_rho);
     double* dft = o.f_targets ? (double*)(ws + o_ft) : nullptr;
 
@@ -673,12 +786,28 @@ int solve_batched_shared_mfma(gp_handle h, gp_dtype kdtype, const void* K, int64
     e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(h, e, "batched init launch");
 
-    std::vector<int32_t> hdone((size_t)B), hlist((size_t)bpad);
-    int it = 0;
-    while (it < o.max_iter) {
-        const int end = std::min(o.max_iter, it + o.chunk);
+    // target check of the problems that stopped at their target (P.done 2)
+    auto launch_verify = [&](int nc) {
+        const dim3 g((unsigned)nc);
+#define GPL1_BS_VER(TT, RR) \
+    hipLaunchKernelGGL((k_bs_verify<TT, RR>), g, dim3(TT), 0, s, P, Kt, npad, kpl, nK, dcand, dkout)
+        if (n <= 256) GPL1_BS_VER(256, 1);
+        else if (n <= 512) GPL1_BS_VER(256, 2);
+        else if (n <= 1024) GPL1_BS_VER(256, 4);
+        else if (n <= 2048) GPL1_BS_VER(256, 8);
+        else if (n <= 4096) GPL1_BS_VER(256, 16);
+        else if (n <= 16384) GPL1_BS_VER(1024, 16);
+        else GPL1_BS_VER(256, 0);
+#undef GPL1_BS_VER
+    };
+    std::vector<int32_t> hdone((size_t)B), hlist((size_t)bpad), hcand, hk;
+    // a problem that is never stopped has done exactly `it` iterations; one
+    // reopened by a target check at iteration k needs max_iter - k more
+    int it = 0, it_cap = o.max_iter;
+    while (it < it_cap) {
+        const int end = std::min(it_cap, it + o.chunk);
         for (; it < end; ++it) {
-            const bool refresh = o.refresh_every > 0 && (it + 1) % o.refresh_every == 0 && it + 1 < o.max_iter;
+            const bool refresh = o.refresh_every > 0 && (it + 1) % o.refresh_every == 0 && it + 1 < it_cap;
             gemm1();
             rows(BR_ITER);
             gemm2();
@@ -694,23 +823,57 @@ int solve_batched_shared_mfma(gp_handle h, gp_dtype kdtype, const void* K, int64
         }
         e = hipGetLastError();
         if (e != hipSuccess) return hip_fail(h, e, "batched iteration launch");
-        if (it < o.max_iter) {
-            e = hipMemcpyAsync(hdone.data(), P.done, 4 * B, hipMemcpyDeviceToHost, s);
-            if (e == hipSuccess) e = hipStreamSynchronize(s);
-            if (e != hipSuccess) return hip_fail(h, e, "batched status poll");
-            int64_t nlive = 0;
+        e = hipMemcpyAsync(hdone.data(), P.done, 4 * B, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return hip_fail(h, e, "batched status poll");
+        if (check_target) {
+            hcand.clear();
             for (int64_t b = 0; b < B; ++b)
-                if (!hdone[(size_t)b]) hlist[(size_t)nlive++] = (int32_t)b;
-            if (nlive == 0) break;
-            if (nlive < live) {
-                // compact: later launches cover the listed problems only
-                for (int64_t k = nlive; k < rup(nlive, GM_BN); ++k) hlist[(size_t)k] = (int32_t)bpad;
-                e = hipMemcpyAsync(dlist, hlist.data(), 4 * rup(nlive, GM_BN), hipMemcpyHostToDevice, s);
-                if (e == hipSuccess) e = hipStreamSynchronize(s);   // hlist is reused at the next poll
-                if (e != hipSuccess) return hip_fail(h, e, "batched active set");
-                live = nlive;
-                P.list = dlist;
+                if (hdone[(size_t)b] == 2) hcand.push_back((int32_t)b);
+            const int nc = (int)hcand.size();
+            if (nc > 0) {
+                e = hipMemcpyAsync(dcand, hcand.data(), 4 * nc, hipMemcpyHostToDevice, s);
+                if (e != hipSuccess) return hip_fail(h, e, "batched target check");
+                launch_verify(nc);
+                hk.resize((size_t)nc);
+                e = hipGetLastError();
+                if (e == hipSuccess) e = hipMemcpyAsync(hdone.data(), P.done, 4 * B, hipMemcpyDeviceToHost, s);
+                if (e == hipSuccess) e = hipMemcpyAsync(hk.data(), dkout, 4 * nc, hipMemcpyDeviceToHost, s);
+                if (e == hipSuccess) e = hipStreamSynchronize(s);
+                if (e != hipSuccess) return hip_fail(h, e, "batched target check");
+                // reopened problems: a fresh projection, then they run on
+                int nr = 0;
+                for (int c = 0; c < nc; ++c) {
+                    const int32_t b = hcand[(size_t)c];
+                    if (hdone[(size_t)b] != 3) continue;
+                    hcand[(size_t)nr++] = b;
+                    hdone[(size_t)b] = 0;
+                    it_cap = std::max(it_cap, it + (o.max_iter - hk[(size_t)c]));
+                }
+                if (nr > 0) {
+                    e = hipMemcpyAsync(dcand, hcand.data(), 4 * nr, hipMemcpyHostToDevice, s);
+                    if (e != hipSuccess) return hip_fail(h, e, "batched target check");
+                    BsPtrs Pr = P;
+                    Pr.list = dcand;
+                    launch_cols(ct, cnv, nr, s, Pr, BC_PROJ_ONLY);
+                    e = hipGetLastError();
+                    if (e == hipSuccess) e = hipStreamSynchronize(s);   // hcand is reused at the next poll
+                    if (e != hipSuccess) return hip_fail(h, e, "batched target check");
+                }
             }
+        }
+        int64_t nlive = 0;
+        for (int64_t b = 0; b < B; ++b)
+            if (!hdone[(size_t)b]) hlist[(size_t)nlive++] = (int32_t)b;
+        if (nlive == 0) break;
+        if (nlive != live) {
+            // compact: later launches cover the listed problems only
+            for (int64_t k = nlive; k < rup(nlive, GM_BN); ++k) hlist[(size_t)k] = (int32_t)bpad;
+            e = hipMemcpyAsync(dlist, hlist.data(), 4 * rup(nlive, GM_BN), hipMemcpyHostToDevice, s);
+            if (e == hipSuccess) e = hipStreamSynchronize(s);   // hlist is reused at the next poll
+            if (e != hipSuccess) return hip_fail(h, e, "batched active set");
+            live = nlive;
+            P.list = dlist;
         }
     }
     hipLaunchKernelGGL(k_bs_finish, dim3((unsigned)B), dim3(BS_T), 0, s, P, X_out, ldx, f64v);

@@ -24,6 +24,7 @@
 #include "gp_internal.hpp"
 #include "gp_kernels.hpp"
 #include "gp_l1.h"
+#include "gp_verify.hpp"
 
 using namespace gpl1;
 
@@ -85,6 +86,7 @@ __global__ __launch_bounds__(BV_T) void k_bv_init(const VarInst* __restrict__ I,
         s.prm = prm;
         s.prm.rho = D.rho;
         s.prm.f_target = D.ftarget;
+        s.f_target0 = D.ftarget;
         s.tau = prm.tau1;
         s.alpha = prm.amax;
         s.status = ST_MAX_ITER;
@@ -232,14 +234,16 @@ __global__ __launch_bounds__(T) void k_bv_update(const VarInst* __restrict__ I, 
 }
 
 // projection (alpha0 first on init), direction and its dots
+// `reproj`: only the problems that a target check reopened (their step and
+// steplength are applied; the direction is missing)
 template <int T, int NV>
 __global__ __launch_bounds__(T) void k_bv_proj(const VarInst* __restrict__ I, GPState* __restrict__ st_all,
-                                                  int init) {
+                                                  int init, int reproj) {
     __shared__ double lds[3 * (T / WAVE)];
     __shared__ double sh[4];
     const int b = blockIdx.x, tid = threadIdx.x;
     GPState* st = st_all + b;
-    if (st->done) return;
+    if (st->done || (reproj && !st->reproj)) return;
     const VarInst D = I[b];
     const int64_t p = D.p;
     const double rho = D.rho;
@@ -296,6 +300,7 @@ __global__ __launch_bounds__(T) void k_bv_proj(const VarInst* __restrict__ I, GP
         st->dmax = mx[0];
         st->mu = inside ? 0.0 : m + t;
         st->michelot_total += passes;
+        st->reproj = 0;
         if (!isfinite(m)) { st->status = ST_NONFINITE; st->done = 1; }
         else if (mx[0] == 0.0 || !(sums[0] < 0.0)) { st->status = ST_STATIONARY; st->done = 1; }
     }
@@ -396,6 +401,15 @@ int solve_batched_var_lockstep(gp_handle h, gp_dtype kdtype, const gp_instance* 
         osp[(size_t)b] = take(8 * SPART * D.nitems);
     }
     const size_t o_items = take(sizeof(VarItem) * hitems.size());
+    // target check: a descriptor per problem; candidates, item ranges, row
+    // items and partial sums for as many rows as the whole batch has
+    const bool check_target = o.f_target >= 0.0 || o.f_targets != nullptr;
+    int64_t vrows = 0;
+    for (int64_t b = 0; b < B; ++b) vrows += (inst[b].n + VR_ROWS - 1) / VR_ROWS;
+    const size_t o_vp = take(check_target ? sizeof(VerProb) * B : 0);
+    const size_t o_vc = take(check_target ? sizeof(int32_t) * (2 * B + 1) : 0);
+    const size_t o_vi = take(check_target ? sizeof(VerItem) * vrows : 0);
+    const size_t o_vs = take(check_target ? sizeof(double) * vrows : 0);
     int rc = ensure_workspace(h, off);
     if (rc) return rc;
     char* ws = (char*)h->ws;
@@ -415,9 +429,23 @@ int solve_batched_var_lockstep(gp_handle h, gp_dtype kdtype, const gp_instance* 
     GPState* st = (GPState*)(ws + o_st);
     VarInst* dI = (VarInst*)(ws + o_I);
     VarItem* ditems = (VarItem*)(ws + o_items);
+    VerProb* dvp = (VerProb*)(ws + o_vp);
+    int32_t* dvc = (int32_t*)(ws + o_vc);
+    VerItem* dvi = (VerItem*)(ws + o_vi);
+    double* dvs = (double*)(ws + o_vs);
+    std::vector<VerProb> hvp;
+    if (check_target) {
+        hvp.resize((size_t)B);
+        for (int64_t b = 0; b < B; ++b) {
+            const VarInst& D = hI[(size_t)b];
+            hvp[(size_t)b] = VerProb{D.K, D.ldk, D.n, D.p, D.x, D.y, f64v ? 0 : 1, D.aligned};
+        }
+    }
     hipError_t e = hipMemcpyAsync(dI, hI.data(), sizeof(VarInst) * B, hipMemcpyHostToDevice, s);
     if (e == hipSuccess)
         e = hipMemcpyAsync(ditems, hitems.data(), sizeof(VarItem) * hitems.size(), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && check_target)
+        e = hipMemcpyAsync(dvp, hvp.data(), sizeof(VerProb) * B, hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return hip_fail(h, e, "batched-var set-up");
     const GPParams prm = make_params(o, 0.0, tol);
     const unsigned nit = (unsigned)hitems.size();
@@ -430,46 +458,91 @@ int solve_batched_var_lockstep(gp_handle h, gp_dtype kdtype, const gp_instance* 
         if (f64v) hipLaunchKernelGGL((k_bv_update<double, BV_T>), dim3((unsigned)B), dim3(BV_T), 0, s, dI, st, refresh);
         else hipLaunchKernelGGL((k_bv_update<float, BV_T>), dim3((unsigned)B), dim3(BV_T), 0, s, dI, st, refresh);
     };
-    auto proj = [&](int init) {
+    auto proj = [&](int init, int reproj) {
         // 256 threads (several problems per CU) when the largest p fits 16 slots of each
         if (maxp <= 256 * 16) {
             GPL1_BV_NV_SWITCH(pnv, hipLaunchKernelGGL((k_bv_proj<256, NVc>), dim3((unsigned)B), dim3(256), 0, s, dI,
-                                                      st, init));
+                                                      st, init, reproj));
         } else {
             GPL1_BV_NV_SWITCH(nv, hipLaunchKernelGGL((k_bv_proj<BV_T, NVc>), dim3((unsigned)B), dim3(BV_T), 0, s,
-                                                     dI, st, init));
+                                                     dI, st, init, reproj));
         }
     };
     GPL1_BV_NV_SWITCH(nv, hipLaunchKernelGGL(k_bv_init<NVc>, dim3((unsigned)B), dim3(BV_T), 0, s, dI, st, prm,
                                              f64v ? 1 : 0));
     fused(1);
     update(1);
-    proj(1);
+    proj(1, 0);
     e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(h, e, "batched-var init launch");
     std::vector<GPState> hst((size_t)B);
-    int it = 0;
-    while (it < o.max_iter) {
-        const int end = std::min(o.max_iter, it + o.chunk);
+    std::vector<int32_t> hvc;
+    std::vector<VerItem> hvi;
+    // a problem that is never stopped has done exactly `it` iterations; one
+    // reopened by a target check at iteration k needs max_iter - k more
+    int it = 0, it_cap = o.max_iter;
+    auto read_states = [&]() -> int {
+        hipError_t pe = hipMemcpyAsync(hst.data(), st, sizeof(GPState) * B, hipMemcpyDeviceToHost, s);
+        if (pe == hipSuccess) pe = hipStreamSynchronize(s);
+        return pe == hipSuccess ? 0 : hip_fail(h, pe, "batched-var status poll");
+    };
+    while (it < it_cap) {
+        const int end = std::min(it_cap, it + o.chunk);
         for (; it < end; ++it) {
             fused(0);
             update(0);
-            if (o.refresh_every > 0 && (it + 1) % o.refresh_every == 0 && it + 1 < o.max_iter) {
+            if (o.refresh_every > 0 && (it + 1) % o.refresh_every == 0 && it + 1 < it_cap) {
                 fused(1);
                 update(1);
             }
-            proj(0);
+            proj(0, 0);
         }
         e = hipGetLastError();
         if (e != hipSuccess) return hip_fail(h, e, "batched-var iteration launch");
-        if (it < o.max_iter) {
-            e = hipMemcpyAsync(hst.data(), st, sizeof(GPState) * B, hipMemcpyDeviceToHost, s);
-            if (e == hipSuccess) e = hipStreamSynchronize(s);
-            if (e != hipSuccess) return hip_fail(h, e, "batched-var status poll");
-            bool all = true;
-            for (int64_t b = 0; b < B && all; ++b) all = hst[(size_t)b].done != 0;
-            if (all) break;
+        if ((rc = read_states())) return rc;
+        if (check_target) {
+            // problems stopped at their target and not yet checked
+            hvc.clear();
+            hvi.clear();
+            std::vector<int32_t> first;
+            for (int64_t b = 0; b < B; ++b) {
+                const GPState& S = hst[(size_t)b];
+                if (!(S.done && S.f_target0 >= 0.0 && target_checkable(S.status) && !S.tcheck)) continue;
+                hvc.push_back((int32_t)b);
+                first.push_back((int32_t)hvi.size());
+                const int64_t nb = (hI[(size_t)b].n + VR_ROWS - 1) / VR_ROWS;
+                for (int64_t k = 0; k < nb; ++k) hvi.push_back(VerItem{(int32_t)b, (int32_t)k});
+            }
+            const int nc = (int)hvc.size();
+            if (nc > 0) {
+                first.push_back((int32_t)hvi.size());
+                hvc.insert(hvc.end(), first.begin(), first.end());   // [cand | first]
+                e = hipMemcpyAsync(dvc, hvc.data(), sizeof(int32_t) * hvc.size(), hipMemcpyHostToDevice, s);
+                if (e == hipSuccess)
+                    e = hipMemcpyAsync(dvi, hvi.data(), sizeof(VerItem) * hvi.size(), hipMemcpyHostToDevice, s);
+                if (e != hipSuccess) return hip_fail(h, e, "batched-var target check");
+                const unsigned ni = (unsigned)hvi.size();
+                if (kdtype == GP_F64)
+                    hipLaunchKernelGGL(k_verify_rows<double>, dim3(ni), dim3(VR_T), 0, s, dvp, dvi, dvs);
+                else if (kdtype == GP_F32)
+                    hipLaunchKernelGGL(k_verify_rows<float>, dim3(ni), dim3(VR_T), 0, s, dvp, dvi, dvs);
+                else
+                    hipLaunchKernelGGL(k_verify_rows<bf16_t>, dim3(ni), dim3(VR_T), 0, s, dvp, dvi, dvs);
+                hipLaunchKernelGGL(k_verify_decide, dim3((unsigned)((nc + 63) / 64)), dim3(64), 0, s, st, dvc,
+                                   dvc + nc, nc, dvs, 1);
+                proj(0, 1);   // a direction for the reopened problems
+                e = hipGetLastError();
+                if (e != hipSuccess) return hip_fail(h, e, "batched-var target check");
+                std::vector<int32_t> kb((size_t)nc);
+                for (int c = 0; c < nc; ++c) kb[(size_t)c] = hst[(size_t)hvc[(size_t)c]].k;
+                if ((rc = read_states())) return rc;   // hvc and hvi were copied before this sync
+                for (int c = 0; c < nc; ++c)
+                    if (!hst[(size_t)hvc[(size_t)c]].done) it_cap = std::max(it_cap, it + (o.max_iter - kb[(size_t)c]));
+            }
         }
+        bool all = true;
+        for (int64_t b = 0; b < B && all; ++b) all = hst[(size_t)b].done != 0;
+        if (all) break;
     }
     hipLaunchKernelGGL(k_bv_finish, dim3((unsigned)B), dim3(BV_T), 0, s, dI, st, f64v ? 1 : 0);
     e = hipMemcpyAsync(hst.data(), st, sizeof(GPState) * B, hipMemcpyDeviceToHost, s);

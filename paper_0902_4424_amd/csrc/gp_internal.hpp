@@ -35,6 +35,10 @@ struct Plan {
     int64_t ldw;      // stride of the partial w vectors
     int nbp, GU;      // update kernel: column workgroups, all workgroups
     size_t o_state, o_x, o_g, o_d, o_vbuf, o_d32, o_r, o_q, o_y, o_spart, o_upart, o_wpart, bytes;
+    // exact check of an objective target: problem descriptor, row items,
+    // partial sums, the (one) checked problem and its item range
+    size_t o_vprob, o_vitem, o_vpart, o_vidx;
+    int nvitems;
 };
 
 int fail(gp_handle h, int code, const std::string& msg);

@@ -1074,6 +1074,7 @@ __global__ __launch_bounds__(UPD_T) void k_update(GPState* __restrict__ st, int 
 __device__ __forceinline__ void init_state(GPState* st, const GPParams& prm) {
     GPState s = {};
     s.prm = prm;
+    s.f_target0 = prm.f_target;
     s.live = 1;
     s.tau = prm.tau1;
     s.alpha = prm.amax;

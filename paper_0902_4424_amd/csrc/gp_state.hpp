@@ -60,6 +60,13 @@ struct GPState {
     int32_t michelot_total;    // diagnostics: passes summed over the iterations
     // final results
     double l1, gmax;
+    // exact check of an objective target (see gp_verify.hpp)
+    double f_target0;          // the caller's target (prm.f_target may be lowered below it)
+    double f_exact;            // f recomputed in double at the last check
+    int32_t tcheck;            // 1: a stop at the target passed the check
+    int32_t reopened;          // checks that failed and reopened the problem
+    int32_t reproj;            // uneven batches: reopened, needs a projection before its next sweep
+    int32_t pad_;
 };
 
 }  // namespace gpl1

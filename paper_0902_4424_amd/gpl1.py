@@ -45,7 +45,8 @@ class GPResult(C.Structure):
                 ("f", C.c_double), ("rel_change", C.c_double),
                 ("lambda_est", C.c_double), ("l1norm", C.c_double),
                 ("t_fused_ms", C.c_double), ("n_fused", C.c_int32),
-                ("proj_passes", C.c_int32), ("x0_rejected", C.c_int32)]
+                ("proj_passes", C.c_int32), ("x0_rejected", C.c_int32),
+                ("reopened", C.c_int32), ("reserved_", C.c_int32)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_}

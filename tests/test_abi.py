@@ -45,7 +45,7 @@ int main(void) {
   printf("%zu %zu %zu %zu %zu %zu %zu %zu\n", offsetof(gp_opts, theta), offsetof(gp_opts, M_alpha),
          offsetof(gp_opts, f_target), offsetof(gp_opts, chunk), offsetof(gp_opts, fused_grid),
          offsetof(gp_opts, f_targets), offsetof(gp_opts, x0_fallback), offsetof(gp_result, x0_rejected));
-  printf("%zu\n", offsetof(gp_opts, graph));
+  printf("%zu %zu\n", offsetof(gp_opts, graph), offsetof(gp_result, reopened));
   printf("%zu %zu %zu\n", offsetof(gp_result, f), offsetof(gp_result, lambda_est),
          offsetof(gp_result, l1norm));
   printf("%zu %zu\n", offsetof(gp_instance, n), offsetof(gp_instance, rho));
@@ -59,7 +59,8 @@ int main(void) {
     O, R, I = gpl1.GPOpts, gpl1.GPResult, gpl1.GPInstance
     want = [C.sizeof(O), C.sizeof(R), C.sizeof(I),
             O.theta.offset, O.M_alpha.offset, O.f_target.offset, O.chunk.offset,
-            O.fused_grid.offset, O.f_targets.offset, O.x0_fallback.offset, R.x0_rejected.offset, O.graph.offset, R.f.offset, R.lambda_est.offset, R.l1norm.offset,
+            O.fused_grid.offset, O.f_targets.offset, O.x0_fallback.offset, R.x0_rejected.offset, O.graph.offset,
+            R.reopened.offset, R.f.offset, R.lambda_est.offset, R.l1norm.offset,
             I.n.offset, I.rho.offset]
     assert vals == want
 
