@@ -212,6 +212,36 @@ int gp_l1_solve_batched_var(gp_handle h, gp_dtype kdtype,
                             const gp_opts* opts, gp_result* res, void* stream);
 
 /* ------------------------------------------------------------------------
+ * The comparison methods of Section 2 on the same device passes.
+ *
+ *   GP_ISTA  (item 1):  x <- S_{tau lam}[x + tau K^T (y - K x)]
+ *   GP_FISTA (item 2, equation (3)): the ISTA step taken from
+ *            z_k = x_k + ((t_k - 1)/t_{k+1}) (x_k - x_{k-1}), t_0 = 1,
+ *            t_{k+1} = (1 + sqrt(1 + 4 t_k^2)) / 2
+ *   GP_PSD   (item 5):  x <- P_Omega[x + beta r], r = K^T (y - K x),
+ *            beta = ||r||^2 / ||K r||^2
+ * with S_t[v] = sgn(v) max(|v| - t, 0).  ISTA and FISTA minimise the
+ * penalised functional (1), F(x) = ||K x - y||^2 + 2 lam ||x||_1 (tau = 1
+ * is the paper's form, valid for ||K|| < sqrt(2); in general tau < 2/||K||^2);
+ * PSD minimises f over the ball ||x||_1 <= rho, problem (2).
+ * ------------------------------------------------------------------------ */
+typedef enum { GP_ISTA = 0, GP_FISTA = 1, GP_PSD = 2 } gp_fom_method;
+
+/* Run `iters` iterations of `method` (fewer for PSD if r = 0 or K r = 0:
+ * GP_STATIONARY; otherwise GP_MAX_ITER).  K, y, x0 (NULL = 0; PSD projects an
+ * x0 outside the ball), x_out as in gp_l1_solve; param = lam for ISTA and
+ * FISTA, rho for PSD (finite, >= 0); tau = step scale of ISTA and FISTA
+ * (0 = 1, the paper's form), ignored by PSD.  opts: only the kernel-shape and
+ * chunk fields are used (NULL = automatic).  res (host): iters, f = the
+ * method's objective at the returned x (F for ISTA and FISTA, f for PSD)
+ * computed in double from the returned x, l1norm; lambda_est is not set.
+ * p <= 32768.  Errors as gp_l1_solve (GP_E_ARG for an unknown method). */
+int gp_fom_solve(gp_handle h, int32_t method, gp_dtype kdtype, const void* K,
+                 int64_t n, int64_t p, int64_t ldk, const void* y, double param,
+                 double tau, const void* x0, int32_t iters, void* x_out,
+                 const gp_opts* opts, gp_result* res, void* stream);
+
+/* ------------------------------------------------------------------------
  * Learned warm start: an unrolled soft-thresholding network.
  *
  * ISTA (Section 2, item 1) iterates x <- S_lam[x + K^T (y - K x)], i.e. an

@@ -192,14 +192,6 @@ int64_t pick_fused_grid(int64_t n, int64_t p, gp_dtype dt, int want) {
     return std::max<int64_t>(1, std::min(g, n));
 }
 
-// Arguments of one fused launch (see k_fused).
-struct FusedArgs {
-    const GPState* st; const void* K; int64_t n, p, ldk, rows;
-    const double *v, *vsub, *g, *ysub, *rvec; double* tout; void* wpart; int64_t ldw; double* spart;
-    int interleave;
-    const float* v32;   // float copy of the multiplied vector, or NULL
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;   // timing: recorded by the launch itself
-};
 
 template <typename TK, typename ACC, int T, int CPT, int RB, int NB, bool AL, bool WL>
 void launch_fused_one(hipStream_t s, int64_t G, const FusedArgs& a) {
@@ -344,19 +336,6 @@ Plan plan_single(gp_dtype dt, int64_t n, int64_t p, const gp_opts& o) {
     P.o_vidx = take(sizeof(int32_t) * 4);
     P.bytes = off;
     return P;
-}
-
-// Descriptor, row items and index arrays of the single problem's target
-// check, written on the device (no host buffer to keep alive).
-__global__ void k_verify_setup_single(VerProb* vp, VerItem* items, int32_t* idx, int nitems, VerProb prob) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i == 0) {
-        *vp = prob;
-        idx[0] = 0;          // the checked problem
-        idx[1] = 0;          // its items: [0, nitems)
-        idx[2] = nitems;
-    }
-    if (i < nitems) items[i] = VerItem{0, i};
 }
 
 void launch_verify_rows(gp_dtype dt, hipStream_t s, int nitems, const VerProb* vp, const VerItem* items,

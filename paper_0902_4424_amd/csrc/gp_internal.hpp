@@ -41,6 +41,22 @@ struct Plan {
     int nvitems;
 };
 
+// Arguments of one fused K / K^T launch (see k_fused).
+struct FusedArgs {
+    const GPState* st; const void* K; int64_t n, p, ldk, rows;
+    const double *v, *vsub, *g, *ysub, *rvec; double* tout; void* wpart; int64_t ldw; double* spart;
+    int interleave;
+    const float* v32;   // float copy of the multiplied vector, or NULL
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;   // timing: recorded by the launch itself
+};
+void launch_fused(gp_dtype dt, int cfg, bool aligned, hipStream_t s, int64_t G, const FusedArgs& a);
+Plan plan_single(gp_dtype dt, int64_t n, int64_t p, const gp_opts& o);
+int esize(gp_dtype dt);
+struct VerProb;
+struct VerItem;
+void launch_verify_rows(gp_dtype dt, hipStream_t s, int nitems, const VerProb* vp, const VerItem* items,
+                        double* part);
+
 int fail(gp_handle h, int code, const std::string& msg);
 int hip_fail(gp_handle h, hipError_t e, const char* where);
 int ensure_workspace(gp_handle h, size_t bytes);

@@ -121,6 +121,19 @@ __device__ __host__ __forceinline__ bool target_checkable(int status) {
            status == ST_BACKTRACK;
 }
 
+// Descriptor, row items and index arrays of a single problem's check,
+// written on the device (no host buffer to keep alive).
+static __global__ void k_verify_setup_single(VerProb* vp, VerItem* items, int32_t* idx, int nitems, VerProb prob) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) {
+        *vp = prob;
+        idx[0] = 0;          // the checked problem
+        idx[1] = 0;          // its items: [0, nitems)
+        idx[2] = nitems;
+    }
+    if (i < nitems) items[i] = VerItem{0, i};
+}
+
 // The decision for a stopped problem with a target, given f_exact.  The
 // result reports f_exact.  f_exact <= the caller's target: the status becomes
 // ST_TARGET.  Otherwise a target stop is reopened (returns 0: status back to

@@ -15,13 +15,15 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "lib", "libgpl1.so")
 
 GP_F64, GP_F32, GP_BF16 = 0, 1, 2
+GP_ISTA, GP_FISTA, GP_PSD = 0, 1, 2
+FOM_METHODS = {"ista": GP_ISTA, "fista": GP_FISTA, "psd": GP_PSD}
 STATUS = {0: "ok_tol", 1: "stationary", 2: "max_iter", 3: "reached_target",
           4: "backtrack_limit", -1: "bad_argument", -2: "nonfinite",
           -3: "hip_error", -4: "out_of_memory", -5: "unsupported"}
 
 SYMBOLS = ("gp_opts_default", "gp_create", "gp_destroy", "gp_last_error",
            "gp_l1_project", "gp_l1_solve", "gp_l1_solve_noalloc", "gp_l1_solve_batched_shared",
-           "gp_l1_solve_batched_var", "gp_lista_create", "gp_lista_destroy",
+           "gp_l1_solve_batched_var", "gp_fom_solve", "gp_lista_create", "gp_lista_destroy",
            "gp_lista_init_from_K", "gp_lista_set_weights", "gp_lista_get_weights",
            "gp_lista_forward", "gp_lista_train_step", "gp_lista_gradients", "gp_lista_save",
            "gp_lista_load", "gp_lista_set_forward_planes")
@@ -96,6 +98,9 @@ def load():
                                             dbl, C.POINTER(GPOpts),
                                             C.POINTER(GPResult), vp]
     lib.gp_l1_solve_batched_var.restype = i32
+    lib.gp_fom_solve.argtypes = [vp, C.c_int32, i32, vp, i64, i64, i64, vp, dbl, dbl, vp, C.c_int32, vp,
+                                 C.POINTER(GPOpts), C.POINTER(GPResult), vp]
+    lib.gp_fom_solve.restype = i32
     fp = C.c_void_p
     lib.gp_lista_create.argtypes = [vp, C.POINTER(vp), i64, i64, C.c_int32]
     lib.gp_lista_create.restype = i32
@@ -278,6 +283,36 @@ class Handle:
         res = GPResult()
         rc = fn(self.h, kdt, _ptr(K), n, p, ldk, _ptr(y), float(rho), _ptr(x0), float(tol),
                 _ptr(out), C.byref(o), C.byref(res), _stream(stream))
+        self._raise(rc)
+        return out, res.as_dict()
+
+    # -- the comparison methods of Section 2 ------------------------------
+    def fom(self, method: str, K, y, param: float, iters: int, tau: float = 1.0, x0=None, out=None,
+            opts: GPOpts | None = None, stream=None, **kw):
+        """gp_fom_solve: `iters` iterations of ISTA / FISTA (param = lambda)
+        or PSD (param = rho).  Returns (x, result dict)."""
+        torch = _torch()
+        if method not in FOM_METHODS:
+            raise ValueError(f"method must be one of {sorted(FOM_METHODS)}")
+        _check_dev(K, y, x0)
+        kdt = k_dtype(K)
+        vdt = vec_dtype(kdt)
+        if K.dim() != 2 or K.stride(1) != 1:
+            raise ValueError("K must be a row-major 2-D tensor")
+        n, p = K.shape
+        if y.dtype != vdt or y.numel() != n or not y.is_contiguous():
+            raise ValueError(f"y must be contiguous {vdt} of length {n}")
+        if x0 is not None and (x0.dtype != vdt or x0.numel() != p or not x0.is_contiguous()):
+            raise ValueError(f"x0 must be contiguous {vdt} of length {p}")
+        if out is None:
+            out = torch.empty(p, dtype=vdt, device=K.device)
+        elif out.dtype != vdt or out.numel() != p or not out.is_contiguous() or not out.is_cuda:
+            raise ValueError(f"out must be a contiguous device {vdt} tensor of length {p}")
+        o = opts if opts is not None else default_opts(**_tuned(kdt, n, p, kw))
+        res = GPResult()
+        rc = self.lib.gp_fom_solve(self.h, FOM_METHODS[method], kdt, _ptr(K), n, p, K.stride(0), _ptr(y),
+                                   float(param), float(tau), _ptr(x0), int(iters), _ptr(out), C.byref(o),
+                                   C.byref(res), _stream(stream))
         self._raise(rc)
         return out, res.as_dict()
 
