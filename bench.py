@@ -408,6 +408,142 @@ def mall_leg(H, np, torch, gpl1, instances):
     return res
 
 
+def lasso_references(K64, y64, lams):
+    import numpy as np
+    """Exact minimisers x_bar(lambda) of the penalised functional (1),
+    ||K x - y||^2 + 2 lambda ||x||_1, at each lambda: the homotopy (LARS-lasso)
+    path of the stored problem in FP64, linear between its breakpoints (the
+    path is piecewise linear in lambda, Section 1).  scikit-learn scales the
+    functional by 1/(2n), so its alpha is lambda / n."""
+    from sklearn.linear_model import lars_path
+    n = K64.shape[0]
+    lams = np.asarray(lams, dtype=np.float64)
+    alphas, _, coefs = lars_path(K64, y64, method="lasso", alpha_min=float(lams.min()) / n * 0.999,
+                                 max_iter=50 * n, return_path=True)
+    out = []
+    for lam in lams:
+        a = lam / n
+        k = int(np.searchsorted(-alphas, -a))          # alphas decrease
+        if k == 0:
+            out.append(coefs[:, 0].copy())
+            continue
+        k = min(k, len(alphas) - 1)
+        a0, a1 = alphas[k - 1], alphas[k]
+        w = 0.0 if a0 == a1 else (a0 - a) / (a0 - a1)
+        out.append((1.0 - w) * coefs[:, k - 1] + w * coefs[:, k])
+    return np.array(out)
+
+
+def isochrone_leg(H, np, torch, gpl1, instances, nlam=50, lrange=9.0, budgets_ms=(0.5, 1.0, 2.0, 4.0, 8.0)):
+    """The experiment of Section 4 on the Gaussian operator, in shape: K
+    1848x8192 (spectral norm 1, FP32 storage), 100-sparse signal, about 2 %
+    noise; lambda_j = lambda_max 2^(-L (j+1)/nlam), rho_j = ||x_bar(lambda_j)||_1
+    with x_bar from the homotopy path.  L = 9: near lambda_max / 2^9 the
+    solution has about a thousand nonzeros and the FP64 homotopy path ends at
+    a degeneracy, so no exact reference exists below it; grid points whose
+    reference misses the KKT relation ||K^T (y - K x_bar)||_inf = lambda by
+    more than 1e-9 (relative) are dropped and counted.  Two measurements:
+      * the rho sweep: one batched GPSS call with the nlam radii as columns
+        sharing K and y, against the same nlam plain solves one after another;
+      * approximation isochrones: GPSS, ISTA, FISTA (lambda_j, step 1 as in
+        the paper, ||K|| = 1) and PSD (rho_j), one problem at a time, each run
+        for the iterations that fit a wall-time budget on this GPU (its own
+        measured time per iteration); e = ||x - x_bar|| / ||x_bar|| per
+        (method, budget, lambda_j)."""
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    inst = instances.paper_gaussian()
+    K64, y64 = inst.K64, inst.y64
+    lam_max = float(np.abs(K64.T @ y64).max())
+    l2 = lrange * (np.arange(nlam) + 1) / nlam
+    lams = lam_max * 2.0 ** (-l2)
+    tl = time.time()
+    xbar = lasso_references(K64, y64, lams)
+    t_lars = time.time() - tl
+    kkts = np.array([abs(float(np.abs(K64.T @ (y64 - K64 @ xb)).max()) - lam) / lam for xb, lam in zip(xbar, lams)])
+    keep = np.nonzero(kkts <= 1e-9)[0]
+    dropped = nlam - len(keep)
+    lams, l2, xbar = lams[keep], l2[keep], xbar[keep]
+    nlam = len(keep)
+    kkt = float(kkts[keep].max())
+    rhos = np.abs(xbar).sum(axis=1)
+    log(f"isochrones: instance and homotopy references in {time.time() - t0:.1f}s (LARS {t_lars:.1f}s); "
+        f"{nlam} grid points kept (max KKT rel err {kkt:.1e}), {dropped} dropped")
+    K = torch.from_numpy(inst.K_store).to(dev)
+    y = torch.from_numpy(inst.y_store).to(dev)
+    nx = np.linalg.norm(xbar, axis=1)
+
+    def err(xt, j):
+        return float(np.linalg.norm(xt.cpu().double().numpy() - xbar[j]) / nx[j])
+
+    # ---- the rho sweep as one batched call -------------------------------
+    Y = y.unsqueeze(0).repeat(nlam, 1).contiguous()
+    kw = dict(tol=1e-10, max_iter=5000, refresh_every=REFRESH)
+    H.solve_batched_shared(K, Y, rhos, **kw)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    X, rs = H.solve_batched_shared(K, Y, rhos, **kw)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t1
+    e_batch = [err(X[j], j) for j in range(nlam)]
+    t1 = time.perf_counter()
+    e_seq = []
+    for j in range(nlam):
+        xs, _ = H.solve(K, y, float(rhos[j]), **kw)
+        e_seq.append(xs)
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t1
+    e_seq = [err(e_seq[j], j) for j in range(nlam)]
+    sweep = {"batched_seconds": round(t_batch, 5), "sequential_plain_seconds": round(t_seq, 5),
+             "speedup": round(t_seq / t_batch, 2),
+             "iterations_min_mean_max": [min(r["iters"] for r in rs), round(float(np.mean([r["iters"] for r in rs])), 1),
+                                         max(r["iters"] for r in rs)],
+             "max_e_batched": max(e_batch), "max_e_sequential": max(e_seq)}
+    log(f"  rho sweep: batched {t_batch * 1e3:.1f} ms, sequential {t_seq * 1e3:.1f} ms; "
+        f"max e {max(e_batch):.1e} / {max(e_seq):.1e}")
+
+    # ---- isochrones: iterations per budget from each method's own rate -----
+    jm = nlam // 2
+
+    def run(method, j, k):
+        if method == "gpss":
+            return H.solve(K, y, float(rhos[j]), tol=0.0, max_iter=max(k, 1), refresh_every=REFRESH)
+        if method == "psd":
+            return H.fom("psd", K, y, float(rhos[j]), k)
+        return H.fom(method, K, y, float(lams[j]), k, tau=1.0)
+
+    per_it = {}
+    for m in ("gpss", "ista", "fista", "psd"):
+        run(m, jm, 50)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        _, r = run(m, jm, 400)
+        torch.cuda.synchronize()
+        per_it[m] = (time.perf_counter() - t1) / max(r["iters"], 1)
+    table = {}
+    for m in ("gpss", "ista", "fista", "psd"):
+        table[m] = {}
+        for b in budgets_ms:
+            k = max(1, int(b * 1e-3 / per_it[m]))
+            table[m][str(b)] = {"iterations": k,
+                                "e": [float("%.3e" % err(run(m, j, k)[0], j)) for j in range(nlam)]}
+    # the method with the smallest e at each (budget, lambda)
+    best = {str(b): [min(table, key=lambda m: table[m][str(b)]["e"][j]) for j in range(nlam)] for b in budgets_ms}
+    wins = {str(b): {m: best[str(b)].count(m) for m in table} for b in budgets_ms}
+    log(f"  per-iteration us: " + ", ".join(f"{m} {v * 1e6:.1f}" for m, v in per_it.items()))
+    for b in budgets_ms:
+        log(f"  budget {b} ms: lowest e per lambda -> {wins[str(b)]}")
+    return {"workload": "Gaussian K 1848x8192, spectral norm 1, fp32; 100-sparse N(0,1) signal, 2 % noise; "
+                        f"lambda grid log2(lambda_max/lambda) = {lrange:g} (j+1)/50, j < 50",
+            "reference": f"homotopy (LARS-lasso) path in FP64, linear between breakpoints; max KKT rel err {kkt:.1e}; "
+                         f"{dropped} grid points without an exact reference dropped",
+            "log2_lambda_max_over_lambda": [round(v, 3) for v in l2],
+            "rho": [round(float(v), 6) for v in rhos],
+            "rho_sweep": sweep,
+            "per_iteration_us": {m: round(v * 1e6, 2) for m, v in per_it.items()},
+            "budgets_ms": list(budgets_ms), "e": table, "lowest_e_count": wins}
+
+
 def ingest_counters(fetch_dir, write_dir):
     """Write the fused kernel's measured HBM bytes per live launch from two
     rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE; KiB per dispatch) of
@@ -675,6 +811,8 @@ def main():
     ap.add_argument("--no-mall", action="store_true", help="skip the 512 MiB K check")
     ap.add_argument("--no-cold", action="store_true",
                     help="skip the solves timed after an Infinity Cache flush")
+    ap.add_argument("--no-isochrone", action="store_true",
+                    help="skip the rho sweep and approximation isochrones on the 1848x8192 operator")
     ap.add_argument("--learned-train", type=int, default=100000,
                     help="training pairs of the learned leg")
     ap.add_argument("--learned-eval", type=int, default=10000,
@@ -852,6 +990,10 @@ def main():
         out["other_configs"] = configs_leg(H, np, torch, gpl1, instances, not args.no_cpu_baseline)
     if not args.no_mall:
         out["hbm_check_512MiB"] = mall_leg(H, np, torch, gpl1, instances)
+
+    # ---- rho sweep and approximation isochrones (Section 4, in shape) ------
+    if not args.no_isochrone:
+        out["isochrone"] = isochrone_leg(H, np, torch, gpl1, instances)
 
     # ---- learned warm start + batched refinement --------------------------
     if not args.no_learned:

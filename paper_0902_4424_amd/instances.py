@@ -283,6 +283,25 @@ def shared_rhs(seed=5, dtype="bf16", n=2048, p=8192, B=256) -> SharedBatch:
                         name=f"shared_{n}x{p}x{B}")
 
 
+def paper_gaussian(n=1848, p=8192, s=100, noise=0.02, seed=9, dtype="f32") -> Instance:
+    """The Gaussian test problem of Section 4 in shape: K 1848x8192 with
+    N(0,1) entries rescaled to spectral norm 1 (the norm from the largest
+    eigenvalue of K K^T, FP64), x_true s-sparse with N(0,1) amplitudes (the
+    paper gives no sparsity: 100), and noise of about 2 %:
+    sigma = noise * ||K x_true|| / sqrt(n).  rho = ||x_true||_1 (the sweep sets
+    its own radii)."""
+    rng = np.random.default_rng(seed)
+    K = rng.standard_normal((n, p))
+    K /= np.sqrt(np.linalg.eigvalsh(K @ K.T)[-1])
+    x_true = _sparse_signal(rng, p, s, "normal")
+    Kx = K @ x_true
+    sigma = noise * float(np.linalg.norm(Kx)) / np.sqrt(n)
+    y = Kx + sigma * rng.standard_normal(n)
+    Ks, ys = _store(K, y, dtype)
+    return Instance(f"paper_gauss_{n}x{p}", dtype, Ks, ys, float(np.abs(x_true).sum()), x_true, seed,
+                    dict(n=n, p=p, s=s, sigma=sigma, noise=noise))
+
+
 @dataclass
 class WarmStartSet:
     """Right-hand sides for one fixed K: Y (B x n, FP32), rho (B), and the
