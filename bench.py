@@ -642,18 +642,23 @@ def learned_leg(H, np, torch, gpl1, instances, ntrain, neval, epochs, batch=256,
     net = gpl1.Lista(H, n, p, layers)
     net.init_from_K(Kd, Lk, lam)
     net.set_forward_planes(1)            # bf16 activations suffice for a warm start
+    # each pair also enters negated: the solution of (2) is odd in y, so
+    # (-y, -x*) is an exact pair of the same problem
+    Ytr2 = torch.cat([Ytr, -Ytr]).contiguous()
+    Xs2 = torch.cat([Xstar, -Xstar]).contiguous()
+    n2 = Ytr2.shape[0]
     gen = torch.Generator(device="cpu").manual_seed(7)
     steps = 0
     losses = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for ep in range(epochs):
-        perm = torch.randperm(ntrain, generator=gen).to(dev)
+        perm = torch.randperm(n2, generator=gen).to(dev)
         el = []
         lr_ep = lr * (0.5 ** (ep // max(1, epochs // 3)))
-        for b0 in range(0, ntrain - batch + 1, batch):
+        for b0 in range(0, n2 - batch + 1, batch):
             idx = perm[b0:b0 + batch]
-            el.append(net.train_step(Ytr[idx].contiguous(), Xstar[idx].contiguous(), lr_ep))
+            el.append(net.train_step(Ytr2[idx].contiguous(), Xs2[idx].contiguous(), lr_ep))
             steps += 1
         losses.append(float(np.mean(el)))
         log(f"  epoch {ep}: mean loss {losses[-1]:.4e} (lr {lr_ep:.1e})")
@@ -661,7 +666,7 @@ def learned_leg(H, np, torch, gpl1, instances, ntrain, neval, epochs, batch=256,
     t_train = time.perf_counter() - t0
 
     # 3. evaluation on fresh right-hand sides
-    del Ytr, Xstar
+    del Ytr, Xstar, Ytr2, Xs2
     Yev = torch.from_numpy(ev.Y).to(dev)
     # reference optimum of each problem: a long batched run, f recomputed in FP64 on the host
     f_ref = np.empty(neval)
@@ -758,7 +763,8 @@ def learned_leg(H, np, torch, gpl1, instances, ntrain, neval, epochs, batch=256,
     t_plain_all = tp * neval
     res = {
         "workload": f"fixed Gaussian K {n}x{p} fp32; {layers}-layer unrolled network (bf16 weights "
-                    f"on the matrix cores); {ntrain} training pairs from the batched solver, "
+                    f"on the matrix cores); {ntrain} training pairs from the batched solver (each also "
+                    "negated), "
                     f"{epochs} epochs of batch {batch}; {neval} fresh y (50-sparse +-1, sigma 1e-2, "
                     "rho = ||x_true||_1), each run to f <= 1.000001 f_ref",
         "f_ref_source": "3000-iteration batched GPU run per problem, f recomputed in FP64 on the host "

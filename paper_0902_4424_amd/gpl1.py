@@ -323,14 +323,22 @@ class Handle:
         _check_dev(K, Y, X0)
         kdt = k_dtype(K)
         vdt = vec_dtype(kdt)
+        if K.dim() != 2 or K.stride(1) != 1:
+            raise ValueError("K must be a row-major 2-D tensor")
         n, p = K.shape
-        B = Y.shape[0]
         if Y.dim() != 2 or Y.shape[1] != n or Y.dtype != vdt or Y.stride(1) != 1:
             raise ValueError(f"Y must be a row-major B x {n} {vdt} tensor")
-        rho_arr = (C.c_double * B)(*[float(r) for r in rho])
-        if X0 is not None and (X0.shape != (B, p) or X0.dtype != vdt or X0.stride(1) != 1):
+        B = Y.shape[0]
+        rho = [float(r) for r in rho]
+        if len(rho) != B:
+            raise ValueError(f"rho holds {len(rho)} radii for {B} right-hand sides")
+        rho_arr = (C.c_double * B)(*rho)
+        if X0 is not None and (tuple(X0.shape) != (B, p) or X0.dtype != vdt or X0.stride(1) != 1):
             raise ValueError("X0 must be a row-major B x p tensor of the vector dtype")
-        out = torch.empty(B, p, dtype=vdt, device=K.device) if out is None else out
+        if out is None:
+            out = torch.empty(B, p, dtype=vdt, device=K.device)
+        elif tuple(out.shape) != (B, p) or out.dtype != vdt or out.stride(1) != 1 or not out.is_cuda:
+            raise ValueError(f"out must be a row-major device B x p tensor of dtype {vdt}")
         ldx = out.stride(0)
         if X0 is not None and X0.stride(0) != ldx:
             raise ValueError("X0 and out must share a leading dimension")
@@ -360,9 +368,13 @@ class Handle:
             K, y, rho = prob[0], prob[1], prob[2]
             x0 = prob[3] if len(prob) > 3 else None
             _check_dev(K, y, x0)
-            if k_dtype(K) != kdt or K.stride(1) != 1:
+            if k_dtype(K) != kdt or K.dim() != 2 or K.stride(1) != 1:
                 raise ValueError("all K must share one dtype and be row-major")
             n, p = K.shape
+            if y.dtype != vdt or y.numel() != n or not y.is_contiguous():
+                raise ValueError(f"problem {b}: y must be contiguous {vdt} of length {n}")
+            if x0 is not None and (x0.dtype != vdt or x0.numel() != p or not x0.is_contiguous()):
+                raise ValueError(f"problem {b}: x0 must be contiguous {vdt} of length {p}")
             out = torch.empty(p, dtype=vdt, device=K.device)
             outs.append(out)
             inst[b] = GPInstance(K.data_ptr(), y.data_ptr(),

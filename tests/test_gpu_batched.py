@@ -426,3 +426,24 @@ def test_var_special_and_padded(H):
     probs3 = [(probs[3][0], probs[3][1], probs[3][2], X[3].clone())]
     X2, res2 = H.solve_batched_var(probs3, tol=1e-13, max_iter=5000, refresh_every=50)
     assert res2[0]["iters"] <= max(5, res[3]["iters"] // 2)
+
+
+def test_binding_rejects_bad_shapes_before_launch(H):
+    """The binding's argument checks: a short or wrongly typed y or x0, a
+    column-major K, a radius list of the wrong length and a mis-shaped out are
+    refused (ValueError) before the library reads any device memory."""
+    K = torch.zeros(8, 32, dtype=torch.float32, device=DEV)
+    y = torch.zeros(8, dtype=torch.float32, device=DEV)
+    with pytest.raises(ValueError):
+        H.solve_batched_var([(K, y[:7], 1.0)])
+    with pytest.raises(ValueError):
+        H.solve_batched_var([(K, y.double(), 1.0)])
+    with pytest.raises(ValueError):
+        H.solve_batched_var([(K, y, 1.0, torch.zeros(31, device=DEV))])
+    Y = torch.zeros(3, 8, dtype=torch.float32, device=DEV)
+    with pytest.raises(ValueError):
+        H.solve_batched_shared(K, Y, [1.0, 1.0])
+    with pytest.raises(ValueError):
+        H.solve_batched_shared(K.t().contiguous().t(), Y, [1.0] * 3)
+    with pytest.raises(ValueError):
+        H.solve_batched_shared(K, Y, [1.0] * 3, out=torch.zeros(3, 31, device=DEV))
