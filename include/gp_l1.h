@@ -95,11 +95,22 @@ typedef struct {
                                  instead (result.x0_rejected = 1).  Shared-K batches test it on the
                                  device in their first residual pass, gp_l1_solve with two extra
                                  residual passes; uneven batches return GP_E_UNSUPPORTED. */
-    int32_t graph;            /* gp_l1_solve: 1 = replay a captured HIP graph of one chunk of
-                                 iterations (refresh_every iterations, or chunk when refresh_every is
-                                 0; iterations outside whole chunks run as plain launches).  The
-                                 graph is kept in the handle while the problem's arguments are
-                                 unchanged.  Results are identical to graph = 0.  Not with profile. */
+    int32_t graph;            /* 1 = replay a captured HIP graph of one chunk of iterations
+                                 (refresh_every iterations, or chunk when refresh_every is 0;
+                                 iterations outside whole chunks run as plain launches), with the
+                                 status poll after each chunk.  gp_l1_solve keeps its graph in the
+                                 handle while the problem's arguments are unchanged; the batched
+                                 solvers capture per call (shared K: again whenever finished
+                                 problems leave the launches).  Results are identical to graph = 0.
+                                 Not with profile. */
+    /* tuning of the batched solvers (0 = automatic; the autotuner fills them) */
+    int32_t batch_splitk;     /* shared K: reduction chunk of the two GEMMs, a multiple of 32
+                                 (about 1024 when 0); rounded down to divide the padded size */
+    int32_t batch_rows_t;     /* shared K: threads of the per-problem row kernel: 256, 512, 1024 */
+    int32_t batch_cols_t;     /* shared K: threads of the per-problem column kernel: 256, 512, 1024
+                                 (a width with no compiled register shape for p: GP_E_ARG) */
+    int32_t var_item_rows;    /* uneven batches: rows of K per work item of the fused pass, 16..1024
+                                 (64 when 0) */
 } gp_opts;
 
 typedef struct {

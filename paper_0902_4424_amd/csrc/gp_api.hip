@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <mutex>
 #include <new>
 #include <string>
@@ -92,6 +93,36 @@ int ensure_workspace(gp_handle h, size_t bytes) {
     return GP_OK_TOL;
 }
 
+int graph_stream(gp_handle h, hipStream_t user, hipStream_t* out) {
+    *out = user;
+    if (user) return GP_OK_TOL;
+    // a graph cannot be captured on the null stream: run on the handle's own
+    // stream, ordered after the caller's work
+    hipError_t e;
+    if (!h->gstream && (e = hipStreamCreateWithFlags(&h->gstream, hipStreamNonBlocking)) != hipSuccess)
+        return hip_fail(h, e, "graph stream");
+    if (!h->gevent && (e = hipEventCreateWithFlags(&h->gevent, hipEventDisableTiming)) != hipSuccess)
+        return hip_fail(h, e, "graph event");
+    e = hipEventRecord(h->gevent, user);
+    if (e == hipSuccess) e = hipStreamWaitEvent(h->gstream, h->gevent, 0);
+    if (e != hipSuccess) return hip_fail(h, e, "graph stream order");
+    *out = h->gstream;
+    return GP_OK_TOL;
+}
+
+int capture_graph(gp_handle h, hipStream_t s, hipGraphExec_t* exec, const std::function<void()>& enqueue) {
+    if (*exec) { (void)hipGraphExecDestroy(*exec); *exec = nullptr; }
+    hipGraph_t gr = nullptr;
+    hipError_t ce = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+    if (ce != hipSuccess) return hip_fail(h, ce, "graph capture");
+    enqueue();
+    ce = hipStreamEndCapture(s, &gr);
+    if (ce == hipSuccess) ce = hipGraphInstantiate(exec, gr, nullptr, nullptr, 0);
+    if (gr) (void)hipGraphDestroy(gr);
+    if (ce != hipSuccess) { *exec = nullptr; return hip_fail(h, ce, "graph instantiate"); }
+    return GP_OK_TOL;
+}
+
 hipEvent_t prof_event(gp_handle h) {
     if (h->ev_used == (int)h->events.size()) {
         hipEvent_t e;
@@ -148,6 +179,13 @@ int check_opts(gp_handle h, const gp_opts& o) {
     if (std::isnan(o.f_target)) return fail(h, GP_E_ARG, "opts.f_target is NaN");
     if (o.profile < 0) return fail(h, GP_E_ARG, "opts.profile must be >= 0");
     if (o.graph && o.profile) return fail(h, GP_E_ARG, "opts.graph and opts.profile exclude each other");
+    if (o.batch_splitk < 0 || o.batch_splitk % 32 != 0)
+        return fail(h, GP_E_ARG, "opts.batch_splitk must be 0 or a positive multiple of 32");
+    for (int t : {o.batch_rows_t, o.batch_cols_t})
+        if (t != 0 && t != 256 && t != 512 && t != 1024)
+            return fail(h, GP_E_ARG, "opts.batch_rows_t and batch_cols_t must be 0, 256, 512 or 1024");
+    if (o.var_item_rows != 0 && (o.var_item_rows < 16 || o.var_item_rows > 1024))
+        return fail(h, GP_E_ARG, "opts.var_item_rows must be 0 or in 16..1024");
     return GP_OK_TOL;
 }
 
@@ -378,6 +416,10 @@ void gp_opts_default(gp_opts* o) {
     o->f_targets = nullptr;
     o->x0_fallback = 0;
     o->graph = 0;
+    o->batch_splitk = 0;
+    o->batch_rows_t = 0;
+    o->batch_cols_t = 0;
+    o->var_item_rows = 0;
 }
 
 int gp_create(gp_handle* out, int device) {
@@ -413,6 +455,7 @@ int gp_destroy(gp_handle h) {
     if (h->host_state) (void)hipHostFree(h->host_state);
     for (hipEvent_t ev : h->events) (void)hipEventDestroy(ev);
     if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
+    if (h->gexec_b) (void)hipGraphExecDestroy(h->gexec_b);
     if (h->gevent) (void)hipEventDestroy(h->gevent);
     if (h->gstream) (void)hipStreamDestroy(h->gstream);
     delete h;
@@ -512,19 +555,7 @@ static int solve_single(gp_handle h, gp_dtype kdtype, const void* K, int64_t n, 
         if (rc) return rc;
     }
     hipStream_t s = (hipStream_t)stream;
-    const hipStream_t user_stream = s;
-    if (o.graph && !s) {
-        // a graph cannot be captured on the null stream: run on the handle's
-        // own stream, ordered after the caller's work
-        if (!h->gstream && (e = hipStreamCreateWithFlags(&h->gstream, hipStreamNonBlocking)) != hipSuccess)
-            return hip_fail(h, e, "graph stream");
-        if (!h->gevent && (e = hipEventCreateWithFlags(&h->gevent, hipEventDisableTiming)) != hipSuccess)
-            return hip_fail(h, e, "graph event");
-        e = hipEventRecord(h->gevent, user_stream);
-        if (e == hipSuccess) e = hipStreamWaitEvent(h->gstream, h->gevent, 0);
-        if (e != hipSuccess) return hip_fail(h, e, "graph stream order");
-        s = h->gstream;
-    }
+    if (o.graph && (rc = graph_stream(h, (hipStream_t)stream, &s))) return rc;
     char* ws = fixed_ws ? (char*)fixed_ws : (char*)h->ws;
     GPState* st = (GPState*)(ws + P.o_state);
     double* x = (double*)(ws + P.o_x);
@@ -619,19 +650,15 @@ static int solve_single(gp_handle h, gp_dtype kdtype, const void* K, int64_t n, 
                                           o.refresh_every, (int64_t)(uintptr_t)s};
         if (!h->gexec || h->gkey != key) {
             if (h->gexec) { (void)hipGraphExecDestroy(h->gexec); h->gexec = nullptr; }
-            hipGraph_t gr = nullptr;
-            hipError_t ce = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
-            if (ce != hipSuccess) return hip_fail(h, ce, "graph capture");
-            for (int k = 0; k < gch; ++k) {
-                launch_proj(s, st, PM_ITER, p, x, g, nullptr, upart, P.GU, vb, d32);
-                launch_fused(kdtype, P.cfg, aligned, s, P.G, fa_iter);
-                launch_update(kdtype, s, st, UM_ITER, spart, (int)P.G, wpart, P.ldw, p, n, x, g, r, q, upart);
-            }
-            if (o.refresh_every > 0) refresh();
-            ce = hipStreamEndCapture(s, &gr);
-            if (ce == hipSuccess) ce = hipGraphInstantiate(&h->gexec, gr, nullptr, nullptr, 0);
-            if (gr) (void)hipGraphDestroy(gr);
-            if (ce != hipSuccess) { h->gexec = nullptr; return hip_fail(h, ce, "graph instantiate"); }
+            const int crc = capture_graph(h, s, &h->gexec, [&]() {
+                for (int k = 0; k < gch; ++k) {
+                    launch_proj(s, st, PM_ITER, p, x, g, nullptr, upart, P.GU, vb, d32);
+                    launch_fused(kdtype, P.cfg, aligned, s, P.G, fa_iter);
+                    launch_update(kdtype, s, st, UM_ITER, spart, (int)P.G, wpart, P.ldw, p, n, x, g, r, q, upart);
+                }
+                if (o.refresh_every > 0) refresh();
+            });
+            if (crc) return crc;
             h->gkey = key;
         }
         const hipError_t le = hipGraphLaunch(h->gexec, s);

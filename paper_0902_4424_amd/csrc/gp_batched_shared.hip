@@ -639,7 +639,31 @@ int bs_nv(int64_t p) {
     }
 
 // the (threads, slots) shapes of k_bs_cols that are compiled
-#define GPL1_BS_COLS_SHAPES(X) X(256, 2) X(256, 4) X(256, 8) X(512, 8) X(512, 16) X(1024, 16)
+#define GPL1_BS_COLS_SHAPES(X) \
+    X(256, 2) X(256, 4) X(256, 8) X(512, 4) X(512, 8) X(512, 16) X(1024, 2) X(1024, 4) X(1024, 8) X(1024, 16)
+// the (threads, rows per thread in registers; 0 = q parked in memory) shapes
+// of k_bs_rows that are compiled
+#define GPL1_BS_ROWS_SHAPES(X) \
+    X(256, 4) X(256, 8) X(256, 0) X(512, 2) X(512, 4) X(512, 0) X(1024, 1) X(1024, 2) X(1024, 4) X(1024, 0)
+
+// rows per thread of the row kernel with T threads: the smallest compiled
+// register count that holds n, else 0
+int rows_rpt(int64_t n, int T) {
+    const int64_t per = (n + T - 1) / T;
+    static const int opts256[] = {4, 8}, opts512[] = {2, 4}, opts1024[] = {1, 2, 4};
+    const int* o = T == 256 ? opts256 : T == 512 ? opts512 : opts1024;
+    const int no = T == 1024 ? 3 : 2;
+    for (int i = 0; i < no; ++i)
+        if (per <= o[i]) return o[i];
+    return 0;
+}
+
+void launch_rows(int T, int rpt, int64_t B, hipStream_t s, const BsPtrs& P, int mode) {
+#define GPL1_BS_ROWS(TT, RR) \
+    if (T == TT && rpt == RR) { hipLaunchKernelGGL((k_bs_rows<TT, RR>), dim3((unsigned)B), dim3(TT), 0, s, P, mode); return; }
+    GPL1_BS_ROWS_SHAPES(GPL1_BS_ROWS)
+#undef GPL1_BS_ROWS
+}
 
 bool cols_shape_ok(int T, int nv) {
 #define GPL1_BS_OK(TT, NN) \
@@ -676,12 +700,20 @@ int solve_batched_shared_mfma(gp_handle h, gp_dtype kdtype, const void* K, int64
     if (kdtype != GP_BF16 && kdtype != GP_F32) return GP_E_UNSUPPORTED;
     const int nK = kdtype == GP_F32 ? 3 : 1;   // bf16 planes of K
     const int nv = bs_nv(p);
-    const int ct = bs_cols_t(p), cnv = bs_nv_t(p, ct);
-    if (nv == 0 || !cols_shape_ok(ct, cnv) || B > (1 << 20)) return GP_E_UNSUPPORTED;
+    const int ct = o.batch_cols_t ? o.batch_cols_t : bs_cols_t(p), cnv = bs_nv_t(p, ct);
+    if (nv == 0 || B > (1 << 20)) return GP_E_UNSUPPORTED;
+    if (!cols_shape_ok(ct, cnv)) {
+        if (o.batch_cols_t)
+            return fail(h, GP_E_ARG, "opts.batch_cols_t = " + std::to_string(ct) + " has no column-kernel shape for p = " +
+                                         std::to_string(p));
+        return GP_E_UNSUPPORTED;
+    }
+    const int rt = o.batch_rows_t ? o.batch_rows_t : 256, rrpt = rows_rpt(n, rt);
     const int64_t npad = rup(n, BS_PAD), ppad = rup(p, BS_PAD), bpad = rup(B, BS_PAD);
-    // split-K chunks of about 1024 (multiples of 32) per GEMM
-    auto chunk_of = [](int64_t kd) {
-        int64_t c = std::min<int64_t>(kd, 1024);
+    // split-K chunks (multiples of 32 dividing the padded size) per GEMM:
+    // about 1024, or the tuned size
+    auto chunk_of = [&](int64_t kd) {
+        int64_t c = std::min<int64_t>(kd, o.batch_splitk > 0 ? o.batch_splitk : 1024);
         while (kd % c) c -= 32;
         return c;
     };
@@ -704,6 +736,7 @@ int solve_batched_shared_mfma(gp_handle h, gp_dtype kdtype, const void* K, int64
     const size_t o_cand = take(4 * B), o_kout = take(4 * B);
     int rc = ensure_workspace(h, off);
     if (rc) return rc;
+    if (o.graph && (rc = graph_stream(h, s, &s))) return rc;
     char* ws = (char*)h->ws;
     BsPtrs P;
     P.st = (GPState*)(ws + o_st);
@@ -768,12 +801,7 @@ int solve_batched_shared_mfma(gp_handle h, gp_dtype kdtype, const void* K, int64
         gemm_planes(Kt, npad, ppad, P.Qsp, npad, P.plQ, S2, kc2, Wpart, ppad, P.sW);
     };
     auto rows = [&](int mode) {
-        if (n <= 4 * 256)
-            hipLaunchKernelGGL((k_bs_rows<256, 4>), dim3((unsigned)live), dim3(256), 0, s, P, mode);
-        else if (n <= 8 * 256)
-            hipLaunchKernelGGL((k_bs_rows<256, 8>), dim3((unsigned)live), dim3(256), 0, s, P, mode);
-        else
-            hipLaunchKernelGGL((k_bs_rows<256, 0>), dim3((unsigned)live), dim3(256), 0, s, P, mode);
+        launch_rows(rt, rrpt, live, s, P, mode);
     };
     auto cols = [&](int mode) {
         launch_cols(ct, cnv, live, s, P, mode);
@@ -804,22 +832,42 @@ int solve_batched_shared_mfma(gp_handle h, gp_dtype kdtype, const void* K, int64
     // a problem that is never stopped has done exactly `it` iterations; one
     // reopened by a target check at iteration k needs max_iter - k more
     int it = 0, it_cap = o.max_iter;
-    while (it < it_cap) {
-        const int end = std::min(it_cap, it + o.chunk);
-        for (; it < end; ++it) {
-            const bool refresh = o.refresh_every > 0 && (it + 1) % o.refresh_every == 0 && it + 1 < it_cap;
+    auto iteration = [&](int i) {
+        const bool refresh = o.refresh_every > 0 && (i + 1) % o.refresh_every == 0 && i + 1 < it_cap;
+        gemm1();
+        rows(BR_ITER);
+        gemm2();
+        if (refresh) {
+            cols(BC_ITER_NOPROJ);
             gemm1();
-            rows(BR_ITER);
+            rows(BR_REFRESH);
             gemm2();
-            if (refresh) {
-                cols(BC_ITER_NOPROJ);
-                gemm1();
-                rows(BR_REFRESH);
-                gemm2();
-                cols(BC_REFRESH_PROJ);
-            } else {
-                cols(BC_ITER);
+            cols(BC_REFRESH_PROJ);
+        } else {
+            cols(BC_ITER);
+        }
+    };
+    // graph replay: chunks of gch iterations starting at multiples of gch
+    // (the refresh that the plain schedule puts at their end included),
+    // captured again whenever the running problems change the launch sizes
+    const int gch = o.refresh_every > 0 ? o.refresh_every : o.chunk;
+    int64_t glive = -1;
+    while (it < it_cap) {
+        if (o.graph && it % gch == 0 && it + gch < it_cap) {
+            if (glive != live) {
+                const int base = it;
+                if ((rc = capture_graph(h, s, &h->gexec_b, [&]() {
+                         for (int k = 0; k < gch; ++k) iteration(base + k);
+                     })))
+                    return rc;
+                glive = live;
             }
+            e = hipGraphLaunch(h->gexec_b, s);
+            if (e != hipSuccess) return hip_fail(h, e, "batched graph launch");
+            it += gch;
+        } else {
+            const int end = o.graph ? std::min(it_cap, (it / gch + 1) * gch) : std::min(it_cap, it + o.chunk);
+            for (; it < end; ++it) iteration(it);
         }
         e = hipGetLastError();
         if (e != hipSuccess) return hip_fail(h, e, "batched iteration launch");

@@ -32,7 +32,7 @@ namespace gpl1 {
 
 constexpr int BV_T = 1024;   // per-problem workgroups
 constexpr int BV_FT = 256;   // fused-pass workgroups
-constexpr int BV_ROWS = 64;  // rows per work item (32: the same, 256: 30 % slower)
+constexpr int BV_ROWS = 64;  // rows per work item unless tuned (32: the same, 256: 30 % slower)
 constexpr int BV_RB = 1;     // rows per block in the fused pass (2 measured the same, 4 slower)
 constexpr int BV_NB = 2;     // register buffers (3 measured the same)
 
@@ -51,7 +51,7 @@ struct VarInst {
     double ftarget;                  // this problem's f_target
     int32_t aligned;                 // rows 16-byte aligned
     int32_t aligned8;                // rows 8-byte aligned (bf16: read as 4-element chunks)
-    int32_t pad_;
+    int32_t item_rows;               // rows of K per work item
 };
 
 struct VarItem { int32_t inst, slab; };
@@ -112,7 +112,7 @@ __global__ __launch_bounds__(BV_FT) void k_bv_fused(const VarInst* __restrict__ 
     const double* ys = refresh ? D.y : nullptr;
     const double* rs = refresh ? nullptr : D.r;
     if (D.aligned) {
-        fused_body<TK, ACC, BV_FT, CPT, BV_RB, BV_NB, true>((const TK*)D.K, D.n, D.p, D.ldk, BV_ROWS, v, nullptr,
+        fused_body<TK, ACC, BV_FT, CPT, BV_RB, BV_NB, true>((const TK*)D.K, D.n, D.p, D.ldk, D.item_rows, v, nullptr,
                                                              nullptr, ys, rs, D.q, wrow, D.ldw, sp, 0, it.slab,
                                                              D.nitems);
         return;
@@ -123,12 +123,12 @@ __global__ __launch_bounds__(BV_FT) void k_bv_fused(const VarInst* __restrict__ 
         // the same columns
         if (D.aligned8) {
             fused_body<bf16x4_t, ACC, BV_FT, 2 * CPT, BV_RB, BV_NB, true>(
-                (const bf16x4_t*)D.K, D.n, D.p, D.ldk, BV_ROWS, v, nullptr, nullptr, ys, rs, D.q, wrow, D.ldw, sp,
+                (const bf16x4_t*)D.K, D.n, D.p, D.ldk, D.item_rows, v, nullptr, nullptr, ys, rs, D.q, wrow, D.ldw, sp,
                 0, it.slab, D.nitems);
             return;
         }
     }
-    fused_body<TK, ACC, BV_FT, CPT, BV_RB, BV_NB, false>((const TK*)D.K, D.n, D.p, D.ldk, BV_ROWS, v, nullptr,
+    fused_body<TK, ACC, BV_FT, CPT, BV_RB, BV_NB, false>((const TK*)D.K, D.n, D.p, D.ldk, D.item_rows, v, nullptr,
                                                           nullptr, ys, rs, D.q, wrow, D.ldw, sp, 0, it.slab,
                                                           D.nitems);
 }
@@ -389,7 +389,8 @@ int solve_batched_var_lockstep(gp_handle h, gp_dtype kdtype, const gp_instance* 
         D.K = S.K; D.yin = S.y; D.x0in = S.x0; D.xout = S.x_out;
         D.n = S.n; D.p = S.p; D.ldk = S.ldk; D.rho = S.rho;
         D.ftarget = o.f_targets ? o.f_targets[b] : o.f_target;
-        D.nitems = (S.n + BV_ROWS - 1) / BV_ROWS;
+        D.item_rows = o.var_item_rows > 0 ? o.var_item_rows : BV_ROWS;
+        D.nitems = (S.n + D.item_rows - 1) / D.item_rows;
         D.item0 = total_items;
         D.ldw = (S.p + 63) / 64 * 64;
         D.aligned = (S.ldk % vec == 0) && (((uintptr_t)S.K) % 16 == 0);
@@ -412,6 +413,7 @@ int solve_batched_var_lockstep(gp_handle h, gp_dtype kdtype, const gp_instance* 
     const size_t o_vs = take(check_target ? sizeof(double) * vrows : 0);
     int rc = ensure_workspace(h, off);
     if (rc) return rc;
+    if (o.graph && (rc = graph_stream(h, s, &s))) return rc;
     char* ws = (char*)h->ws;
     for (int64_t b = 0; b < B; ++b) {
         VarInst& D = hI[(size_t)b];
@@ -486,16 +488,35 @@ int solve_batched_var_lockstep(gp_handle h, gp_dtype kdtype, const gp_instance* 
         if (pe == hipSuccess) pe = hipStreamSynchronize(s);
         return pe == hipSuccess ? 0 : hip_fail(h, pe, "batched-var status poll");
     };
+    auto sweep = [&](int i) {
+        fused(0);
+        update(0);
+        if (o.refresh_every > 0 && (i + 1) % o.refresh_every == 0 && i + 1 < it_cap) {
+            fused(1);
+            update(1);
+        }
+        proj(0, 0);
+    };
+    // graph replay: chunks of gch sweeps starting at multiples of gch (the
+    // launch sizes never change here, so one capture serves the call)
+    const int gch = o.refresh_every > 0 ? o.refresh_every : o.chunk;
+    bool captured = false;
     while (it < it_cap) {
-        const int end = std::min(it_cap, it + o.chunk);
-        for (; it < end; ++it) {
-            fused(0);
-            update(0);
-            if (o.refresh_every > 0 && (it + 1) % o.refresh_every == 0 && it + 1 < it_cap) {
-                fused(1);
-                update(1);
+        if (o.graph && it % gch == 0 && it + gch < it_cap) {
+            if (!captured) {
+                const int base = it;
+                if ((rc = capture_graph(h, s, &h->gexec_b, [&]() {
+                         for (int k = 0; k < gch; ++k) sweep(base + k);
+                     })))
+                    return rc;
+                captured = true;
             }
-            proj(0, 0);
+            e = hipGraphLaunch(h->gexec_b, s);
+            if (e != hipSuccess) return hip_fail(h, e, "batched-var graph launch");
+            it += gch;
+        } else {
+            const int end = o.graph ? std::min(it_cap, (it / gch + 1) * gch) : std::min(it_cap, it + o.chunk);
+            for (; it < end; ++it) sweep(it);
         }
         e = hipGetLastError();
         if (e != hipSuccess) return hip_fail(h, e, "batched-var iteration launch");

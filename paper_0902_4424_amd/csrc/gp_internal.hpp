@@ -2,6 +2,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -23,6 +24,7 @@ struct gp_handle_s {
     hipEvent_t gevent = nullptr;         // orders it with the caller's stream
     hipGraphExec_t gexec = nullptr;
     std::vector<int64_t> gkey;           // the arguments of the captured chunk
+    hipGraphExec_t gexec_b = nullptr;    // the batched solvers' captured chunk (per call)
 };
 
 namespace gpl1 {
@@ -56,6 +58,12 @@ struct VerProb;
 struct VerItem;
 void launch_verify_rows(gp_dtype dt, hipStream_t s, int nitems, const VerProb* vp, const VerItem* items,
                         double* part);
+
+// Graph replay: the stream to capture on (the handle's own one, ordered
+// after the caller's work, when the caller passes the null stream), and the
+// capture of what `enqueue` launches into `exec` (replacing its old graph).
+int graph_stream(gp_handle h, hipStream_t user, hipStream_t* out);
+int capture_graph(gp_handle h, hipStream_t s, hipGraphExec_t* exec, const std::function<void()>& enqueue);
 
 int fail(gp_handle h, int code, const std::string& msg);
 int hip_fail(gp_handle h, hipError_t e, const char* where);

@@ -38,7 +38,9 @@ class GPOpts(C.Structure):
                 ("chunk", C.c_int32), ("fused_cfg", C.c_int32),
                 ("fused_grid", C.c_int32), ("profile", C.c_int32),
                 ("fused_interleave", C.c_int32), ("f_targets", C.POINTER(C.c_double)),
-                ("x0_fallback", C.c_int32), ("graph", C.c_int32)]
+                ("x0_fallback", C.c_int32), ("graph", C.c_int32),
+                ("batch_splitk", C.c_int32), ("batch_rows_t", C.c_int32),
+                ("batch_cols_t", C.c_int32), ("var_item_rows", C.c_int32)]
 
 
 class GPResult(C.Structure):

@@ -447,3 +447,69 @@ def test_binding_rejects_bad_shapes_before_launch(H):
         H.solve_batched_shared(K.t().contiguous().t(), Y, [1.0] * 3)
     with pytest.raises(ValueError):
         H.solve_batched_shared(K, Y, [1.0] * 3, out=torch.zeros(3, 31, device=DEV))
+
+
+def test_batched_graph_replay_is_bit_identical(H):
+    """opts.graph = 1 in both batched solvers: captured chunks (re-captured in
+    the shared-K solver whenever finished problems leave the launches) give the
+    same bits and counters as plain launches, on the null stream and on a
+    stream of the caller's, with refreshes, per-problem targets (whose checks
+    may reopen problems between chunks) and a ragged last chunk."""
+    batch = instances.shared_batch(192, 700, 40, 8, dtype="f32", seed=83, rhs_seed_base=830)
+    Kt = torch.from_numpy(batch.K_store).to(DEV)
+    Y = torch.from_numpy(batch.Y_store).to(DEV)
+    K64 = batch.K64
+    fref = [gpss(K64, batch.Y_store[b].astype(np.float64), float(batch.rho[b]), tol=0.0,
+                 max_iter=20000)["f"] for b in range(0, 40, 8)]
+    # targets for every 8th problem (the others run to their floor)
+    targets = [fref[b // 8] * (1 + 1e-6) if b % 8 == 0 else -1.0 for b in range(40)]
+    side = torch.cuda.Stream()
+    cases = [dict(tol=1e-9, max_iter=3000, refresh_every=20),
+             dict(tol=0.0, max_iter=3000, refresh_every=20, f_targets=targets),
+             dict(tol=1e-9, max_iter=203, refresh_every=0, chunk=16)]
+    for i, kw in enumerate(cases):
+        for s in (None, side):
+            say(f"[graph] shared-K case {i}, {'caller stream' if s else 'null stream'}")
+            with torch.cuda.stream(s or torch.cuda.current_stream()):
+                Xa, ra = H.solve_batched_shared(Kt, Y, batch.rho, stream=s, **kw)
+                Xb, rb = H.solve_batched_shared(Kt, Y, batch.rho, stream=s, graph=1, **kw)
+            torch.cuda.synchronize()
+            assert torch.equal(Xa, Xb) and ra == rb, i
+    insts = [instances.gaussian_instance(int(n), 4 * int(n), max(1, int(n) // 20), dtype="f32", seed=940 + i)
+             for i, n in enumerate((40, 97, 160, 33))]
+    probs = [(torch.from_numpy(i.K_store).to(DEV), torch.from_numpy(i.y_store).to(DEV), i.rho) for i in insts]
+    for kw in (dict(tol=1e-10, max_iter=3000, refresh_every=20), dict(tol=1e-10, max_iter=77, chunk=8)):
+        say(f"[graph] uneven batch {kw}")
+        Xa, ra = H.solve_batched_var(probs, **kw)
+        Xb, rb = H.solve_batched_var(probs, graph=1, **kw)
+        assert all(torch.equal(a, b) for a, b in zip(Xa, Xb)) and ra == rb
+
+
+def test_batched_tuning_options(H):
+    """Every shape the batched tuner may pick meets the FP32 bar against the
+    oracle: shared-K split-K chunks, row- and column-kernel widths (a width
+    without a compiled shape for p is refused), uneven-batch rows per item."""
+    batch = instances.shared_batch(300, 2100, 5, 15, dtype="bf16", seed=84, rhs_seed_base=840)
+    Kt = _kt(batch)
+    Y = torch.from_numpy(batch.Y_store).to(DEV)
+    base = dict(tol=1e-12, max_iter=4000, refresh_every=50)
+    for kw in (dict(batch_splitk=256), dict(batch_splitk=2048), dict(batch_rows_t=512),
+               dict(batch_rows_t=1024), dict(batch_cols_t=512), dict(batch_cols_t=1024)):
+        say(f"[tuning] shared {kw}")
+        X, res = H.solve_batched_shared(Kt, Y, batch.rho, **base, **kw)
+        _check_columns(batch, X, res, range(5))
+    # p = 2100 needs 16 slots at 256 threads: not a compiled shape
+    with pytest.raises(gpl1.GPError) as e:
+        H.solve_batched_shared(Kt, Y, batch.rho, batch_cols_t=256, **base)
+    assert e.value.code == -1
+    for bad in (dict(batch_splitk=100), dict(batch_rows_t=300), dict(var_item_rows=8)):
+        with pytest.raises(gpl1.GPError):
+            H.solve_batched_shared(Kt, Y, batch.rho, **base, **bad)
+    rng = np.random.default_rng(85)
+    insts = [instances.gaussian_instance(int(n), 4 * int(n), max(1, int(n) // 20), dtype="bf16", seed=950 + i)
+             for i, n in enumerate(rng.integers(40, 400, size=5))]
+    for rows in (16, 32, 128, 256):
+        say(f"[tuning] uneven rows per item {rows}")
+        X, res = H.solve_batched_var(_var_problems(insts, "bf16"), tol=1e-13, max_iter=5000,
+                                     refresh_every=50, var_item_rows=rows)
+        _check_var(insts, X, res, range(5), 1e-6, 1e-4)
