@@ -344,7 +344,7 @@ class Handle:
         ldx = out.stride(0)
         if X0 is not None and X0.stride(0) != ldx:
             raise ValueError("X0 and out must share a leading dimension")
-        o = opts if opts is not None else default_opts(**kw)
+        o = opts if opts is not None else default_opts(**_tuned_shared(kdt, n, p, B, kw))
         _check_targets(o, B)
         res = (GPResult * B)()
         rc = self.lib.gp_l1_solve_batched_shared(
@@ -382,7 +382,7 @@ class Handle:
             inst[b] = GPInstance(K.data_ptr(), y.data_ptr(),
                                  x0.data_ptr() if x0 is not None else None,
                                  out.data_ptr(), n, p, K.stride(0), float(rho))
-        o = opts if opts is not None else default_opts(**kw)
+        o = opts if opts is not None else default_opts(**_tuned_var(kdt, kw))
         _check_targets(o, B)
         res = (GPResult * B)()
         rc = self.lib.gp_l1_solve_batched_var(self.h, kdt, inst, B, float(tol), C.byref(o),
@@ -511,6 +511,40 @@ def _tuned(kdt, n, p, kw):
     kw["fused_cfg"] = int(t["fused_cfg"])
     kw["fused_grid"] = int(t["fused_grid"])
     kw["fused_interleave"] = int(t.get("fused_interleave", 0))
+    return kw
+
+
+_SHARED_KEYS = ("batch_splitk", "batch_rows_t", "batch_cols_t", "graph")
+
+
+def _tuned_shared(kdt, n, p, B, kw):
+    """Add the tuned shared-K batch options (tuned.json, nearest batch size)
+    unless the caller chose any of them."""
+    if any(k in kw for k in _SHARED_KEYS):
+        return kw
+    from . import tune
+    t = tune.lookup_shared(_DT_NAME[kdt], n, p, B)
+    if not t:
+        return kw
+    kw = dict(kw)
+    for k in _SHARED_KEYS:
+        if t.get(k):
+            kw[k] = int(t[k])
+    return kw
+
+
+def _tuned_var(kdt, kw):
+    """Add the tuned uneven-batch options unless the caller chose any."""
+    if "var_item_rows" in kw or "graph" in kw:
+        return kw
+    from . import tune
+    t = tune.lookup_var(_DT_NAME[kdt])
+    if not t:
+        return kw
+    kw = dict(kw)
+    for k in ("var_item_rows", "graph"):
+        if t.get(k):
+            kw[k] = int(t[k])
     return kw
 
 

@@ -1,13 +1,18 @@
-"""Tile autotuner for the fused K / K^T kernel.
+"""Autotuner of the solvers' kernel shapes, results in tuned.json.
 
-For each problem shape (K dtype, n, p) it times the solver's fused kernel
-(HIP events around every 4th launch, `profile` option) and the whole iteration
+Single problems (K dtype, n, p): it times the fused K / K^T kernel (HIP
+events around every 4th launch, `profile` option) and the whole iteration
 over the candidate kernel shapes (threads, column chunks per thread, rows
-per block) and grid sizes (row slabs), and records the fastest pair in
-tuned.json next to this file.  The binding reads that table and passes the
-pair through gp_opts.fused_cfg / fused_grid unless the caller sets them.
+per block) and grid sizes (row slabs), and records the fastest; the binding
+passes it through gp_opts.fused_cfg / fused_grid / fused_interleave.
 
-    python -m paper_0902_4424_amd.tune f32:4096x16384 f64:256x1024 ...
+Shared-K batches (dtype, n, p, B): the whole batched solve to a relative
+change of 1e-10 over the GEMM split-K chunk, the per-problem row and column
+kernel widths and graph replay, one option at a time (coordinate search from
+the automatic choice).  Uneven batches (dtype, the 512-problem workload of n
+in [128, 1024], p = 4n): rows per work item and graph replay.
+
+    python -m paper_0902_4424_amd.tune f32:4096x16384 shared:bf16:2048x8192:256 var:bf16:512 ...
 """
 import json
 import os
@@ -89,25 +94,131 @@ def tune_shape(H, dtype, n, p, iters=40, reps=3, log=print):
     return best
 
 
+def shared_key(dtype, n, p, B):
+    return f"shared:{dtype}:{n}x{p}:{B}"
+
+
+def var_key(dtype):
+    return f"var:{dtype}"
+
+
+def lookup_shared(dtype, n, p, B):
+    """The tuned options of the shared-K batch with this (dtype, n, p) and the
+    nearest batch size (log scale), or None."""
+    import math
+    best, dist = None, None
+    pre = f"shared:{dtype}:{n}x{p}:"
+    for k, v in load_table().items():
+        if k.startswith(pre):
+            d = abs(math.log2(int(k[len(pre):])) - math.log2(max(B, 1)))
+            if dist is None or d < dist:
+                best, dist = v, d
+    return best
+
+
+def lookup_var(dtype):
+    return load_table().get(var_key(dtype))
+
+
+def _coordinate_search(space, run, log):
+    """Minimise run(opts) one option at a time, from the automatic choice."""
+    cur = {k: 0 for k in space}
+    best_t = run(dict(cur))
+    for k, values in space.items():
+        for v in values:
+            if v == cur[k]:
+                continue
+            trial = dict(cur, **{k: v})
+            t = run(trial)
+            if t is not None and (best_t is None or t < best_t):
+                best_t, cur = t, trial
+        log(f"  {k} -> {cur[k]} ({best_t * 1e3:.3f} ms)")
+    return cur, best_t
+
+
+def tune_shared(H, dtype, n, p, B, reps=3, log=print):
+    import numpy as np
+    import torch
+    from . import gpl1, instances
+    batch = instances.shared_batch(n, p, B, max(1, n // 20), dtype=dtype, seed=12346, rhs_seed_base=70000)
+    K = torch.from_numpy(batch.K_store.view(np.int16) if dtype == "bf16" else batch.K_store).cuda()
+    Y = torch.from_numpy(batch.Y_store).cuda()
+
+    def run(o):
+        kw = {k: v for k, v in o.items() if v}
+        try:
+            H.solve_batched_shared(K, Y, batch.rho, tol=1e-10, max_iter=5000, refresh_every=50, chunk=8, **kw)
+        except gpl1.GPError:
+            return None
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            H.solve_batched_shared(K, Y, batch.rho, tol=1e-10, max_iter=5000, refresh_every=50, chunk=8, **kw)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        log(f"  {shared_key(dtype, n, p, B)} {kw or 'automatic'}: {min(ts) * 1e3:.3f} ms")
+        return min(ts)
+
+    space = {"batch_splitk": (256, 512, 2048), "batch_rows_t": (512, 1024), "batch_cols_t": (256, 512, 1024),
+             "graph": (1,)}
+    best, t = _coordinate_search(space, run, log)
+    return dict(best, solve_ms=round(t * 1e3, 3))
+
+
+def tune_var(H, dtype, B, reps=3, log=print):
+    import numpy as np
+    import torch
+    from . import gpl1, instances
+    insts = instances.uneven_batch(B, dtype=dtype, seed=4)
+    probs = [(torch.from_numpy(i.K_store.view(np.int16) if dtype == "bf16" else i.K_store).cuda(),
+              torch.from_numpy(i.y_store).cuda(), i.rho) for i in insts]
+
+    def run(o):
+        kw = {k: v for k, v in o.items() if v}
+        H.solve_batched_var(probs, tol=1e-10, max_iter=5000, refresh_every=50, **kw)
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            H.solve_batched_var(probs, tol=1e-10, max_iter=5000, refresh_every=50, **kw)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        log(f"  {var_key(dtype)} ({B} problems) {kw or 'automatic'}: {min(ts) * 1e3:.3f} ms")
+        return min(ts)
+
+    best, t = _coordinate_search({"var_item_rows": (16, 32, 128, 256), "graph": (1,)}, run, log)
+    return dict(best, solve_ms=round(t * 1e3, 3), problems=B)
+
+
 def main(argv):
     import torch
     from . import gpl1
     if not torch.cuda.is_available():
         print("tune: needs a GPU", file=sys.stderr)
         return 2
-    shapes = []
-    for a in argv:
-        dt, nm = a.split(":")
-        n, p = (int(v) for v in nm.split("x"))
-        shapes.append((dt, n, p))
     table = load_table()
     H = gpl1.Handle(0)
-    for dt, n, p in shapes:
-        print(f"tuning {key(dt, n, p)}", flush=True)
-        best = tune_shape(H, dt, n, p, log=lambda m: print(m, flush=True))
-        if best:
-            table[key(dt, n, p)] = best
-            print(f"  -> {best}", flush=True)
+    say = lambda m: print(m, flush=True)   # noqa: E731
+    for a in argv:
+        parts = a.split(":")
+        if parts[0] == "shared":
+            dt, nm, B = parts[1], parts[2], int(parts[3])
+            n, p = (int(v) for v in nm.split("x"))
+            say(f"tuning {shared_key(dt, n, p, B)}")
+            table[shared_key(dt, n, p, B)] = best = tune_shared(H, dt, n, p, B, log=say)
+        elif parts[0] == "var":
+            dt, B = parts[1], int(parts[2])
+            say(f"tuning {var_key(dt)}")
+            table[var_key(dt)] = best = tune_var(H, dt, B, log=say)
+        else:
+            dt, nm = parts
+            n, p = (int(v) for v in nm.split("x"))
+            say(f"tuning {key(dt, n, p)}")
+            best = tune_shape(H, dt, n, p, log=say)
+            if best:
+                table[key(dt, n, p)] = best
+        say(f"  -> {best}")
     with open(TABLE, "w") as fh:
         json.dump(table, fh, indent=1, sort_keys=True)
     return 0
