@@ -548,7 +548,7 @@ def ingest_counters(fetch_dir, write_dir):
     """Write the fused kernel's measured HBM bytes per live launch from two
     rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE; KiB per dispatch) of
     `bench.py --steps 1 --warmup 0 --no-gap --no-cpu-baseline --no-forms
-    --no-learned --no-configs --no-mall --no-cold --calibrate-copy`.  Each counter is scaled by what it reads for
+    --no-learned --no-configs --no-mall --no-cold --no-isochrone --calibrate-copy`.  Each counter is scaled by what it reads for
     the 256 MiB reference copy; launches below half the largest fetch (those
     that exited at once after the solve stopped) are left out."""
     import csv
@@ -577,7 +577,7 @@ def ingest_counters(fetch_dir, write_dir):
     kname = next(fname[k] for k in fv if "k_fused" in fname[k])
     if len({fname[k] for k in fv if "k_fused" in fname[k]}) != 1:
         raise SystemExit("counter runs hold more than one fused-kernel shape: profile the main leg only "
-                         "(--no-forms --no-learned --no-configs --no-mall --no-cold)")
+                         "(--no-forms --no-learned --no-configs --no-mall --no-cold --no-isochrone)")
     lf = [v for v in fused_f if v > 0.5 * max(fused_f)]
     lw = sorted(fused_w)[-len(lf):]
     fb = sum(lf) / len(lf) * 1024 * fs
@@ -590,7 +590,7 @@ def ingest_counters(fetch_dir, write_dir):
          "command": "cd /tmp && export TMPDIR=/tmp && timeout -s KILL 120 rocprofv3 --pmc "
                     "<FETCH_SIZE|WRITE_SIZE> -f csv -d <out> -o run -- python3 <repo>/bench.py --steps 1 "
                     "--warmup 0 --no-gap --no-cpu-baseline --no-forms --no-learned --no-configs --no-mall --no-cold "
-                    "--calibrate-copy"}
+                    "--no-isochrone --calibrate-copy"}
     with open(TRAFFIC_FILE, "w") as fh:
         json.dump(t, fh, indent=1)
         fh.write("\n")
