@@ -489,92 +489,110 @@ __global__ __launch_bounds__(T) void k_bs_cols(BsPtrs P, int mode) {
     }
 }
 
-// Target check of the problems listed in `cand` (one workgroup each): f in
-// double from the padded transposed planes of K (Kt, ppad x npad; one bf16
-// plane for bf16 K, three for FP32 K, which add up exactly to the stored
-// value), y and x narrowed to float as returned.  Only the nonzero entries of
-// x are visited, each adding x_j times the contiguous column j of K to r.
-// The decision marks P.done (1 kept, 3 reopened) and kout[c] = the problem's
-// iteration count.  RPT > 0: n <= RPT * T, r in registers; RPT = 0: r in Qv.
-template <int T, int RPT>
-__global__ __launch_bounds__(T) void k_bs_verify(BsPtrs P, const uint16_t* __restrict__ Kt, int64_t ldkt,
-                                                 int64_t kts, int nK, const int32_t* __restrict__ cand,
-                                                 int32_t* __restrict__ kout) {
-    constexpr int NWV = T / WAVE;
-    __shared__ int32_t sj[T];
-    __shared__ double sv[T];
-    __shared__ int32_t wcnt[NWV];
-    __shared__ double lds[NWV];
-    const int b = cand[blockIdx.x], tid = threadIdx.x;
-    const int lane = tid & (WAVE - 1), wid = tid / WAVE;
-    const int64_t n = P.n, p = P.p;
-    const double* x = P.X + b * p;
-    const double* y = P.Y + b * n;
-    double* rq = P.Qv + b * n;
-    double r[RPT > 0 ? RPT : 1];
+// Target check of the problems listed in `cand`: f = ||K x - y||^2 in double
+// from the caller's K (widened exactly), y and x narrowed to float as
+// returned.  The checked problems' iterates are not sparse enough to skip
+// columns (GP keeps old entries whenever lambda < 1), so this is a batched
+// product in double: a workgroup owns 64 rows of K, 64 checked problems and
+// one of `ns` column chunks, stages K and x tiles of 32 columns in LDS (each K
+// element read once for the 64 problems), and every thread accumulates 4 rows
+// x 4 problems.  dot[(s * nc + c) * n + i] = sum over chunk s of K_ij x_cj.
+constexpr int CV_T = 256, CV_R = 64, CV_C = 64, CV_J = 32;
+
+template <typename TK> __device__ __forceinline__ double cv_widen(TK v);
+template <> __device__ __forceinline__ double cv_widen<float>(float v) { return (double)v; }
+template <> __device__ __forceinline__ double cv_widen<uint16_t>(uint16_t v) { return (double)bf16_bits_to_f32(v); }
+
+template <typename TK>
+__global__ __launch_bounds__(CV_T) void k_bs_check_tiles(const TK* __restrict__ K, int64_t ldk, int64_t n,
+                                                         int64_t p, const double* __restrict__ X,
+                                                         const int32_t* __restrict__ cand, int nc, int64_t jchunk,
+                                                         double* __restrict__ dot) {
+    __shared__ double ks[CV_J][CV_R + 1];
+    __shared__ double xs[CV_J][CV_C + 1];
+    const int tid = threadIdx.x, tr = tid % 16, tc = tid / 16;
+    const int64_t i0 = (int64_t)blockIdx.x * CV_R;
+    const int c0 = (int)blockIdx.y * CV_C;
+    const int64_t jb = (int64_t)blockIdx.z * jchunk;
+    const int64_t je = jb + jchunk < p ? jb + jchunk : p;
+    double acc[4][4];
 #pragma unroll
-    for (int k = 0; k < (RPT > 0 ? RPT : 1); ++k) r[k] = 0.0;
-    if (RPT == 0)
-        for (int64_t i = tid; i < n; i += T) rq[i] = 0.0;
-    auto kval = [&](const uint16_t* col, int64_t i) {
-        double v = (double)bf16_bits_to_f32(col[i]);
-        if (nK == 3) v = (v + (double)bf16_bits_to_f32(col[kts + i])) + (double)bf16_bits_to_f32(col[2 * kts + i]);
-        return v;
-    };
-    for (int64_t j0 = 0; j0 < p; j0 += T) {
-        const int64_t j = j0 + tid;
-        const double xv = j < p ? (double)(float)x[j] : 0.0;
-        const bool nz = xv != 0.0;
-        // list the block's nonzeros in column order
-        const uint64_t mask = __builtin_amdgcn_ballot_w64(nz);
-        const int below = __builtin_popcountll(mask & ((1ull << lane) - 1ull));
-        __syncthreads();   // the previous block's list is consumed
-        if (lane == 0) wcnt[wid] = __builtin_popcountll(mask);
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+    for (int64_t j0 = jb; j0 < je; j0 += CV_J) {
         __syncthreads();
-        int base = 0, total = 0;
-#pragma unroll
-        for (int w = 0; w < NWV; ++w) {
-            base += w < wid ? wcnt[w] : 0;
-            total += wcnt[w];
+        for (int e = tid; e < CV_R * CV_J; e += CV_T) {
+            const int r = e / CV_J, jj = e % CV_J;
+            const int64_t i = i0 + r, j = j0 + jj;
+            ks[jj][r] = (i < n && j < je) ? cv_widen<TK>(K[i * ldk + j]) : 0.0;
         }
-        if (nz) { sj[base + below] = (int32_t)j; sv[base + below] = xv; }
+        for (int e = tid; e < CV_C * CV_J; e += CV_T) {
+            const int cc = e / CV_J, jj = e % CV_J;
+            const int c = c0 + cc;
+            const int64_t j = j0 + jj;
+            xs[jj][cc] = (c < nc && j < je) ? (double)(float)X[(int64_t)cand[c] * p + j] : 0.0;
+        }
         __syncthreads();
-        for (int c = 0; c < total; ++c) {
-            const uint16_t* col = Kt + (int64_t)sj[c] * ldkt;
-            const double xj = sv[c];
-            if constexpr (RPT > 0) {
+#pragma unroll 4
+        for (int jj = 0; jj < CV_J; ++jj) {
+            double kr[4], xc[4];
 #pragma unroll
-                for (int k = 0; k < RPT; ++k) {
-                    const int64_t i = tid + (int64_t)k * T;
-                    if (i < n) r[k] = fma(kval(col, i), xj, r[k]);
-                }
-            } else {
-                for (int64_t i = tid; i < n; i += T) rq[i] = fma(kval(col, i), xj, rq[i]);
-            }
+            for (int a = 0; a < 4; ++a) kr[a] = ks[jj][tr + 16 * a];
+#pragma unroll
+            for (int b = 0; b < 4; ++b) xc[b] = xs[jj][tc + 16 * b];
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b) acc[a][b] = fma(kr[a], xc[b], acc[a][b]);
         }
     }
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        const int c = c0 + tc + 16 * b;
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+            const int64_t i = i0 + tr + 16 * a;
+            if (i < n && c < nc) dot[((int64_t)blockIdx.z * nc + c) * n + i] = acc[a][b];
+        }
+    }
+}
+
+// One workgroup per checked problem: r_i = (sum of the chunks' dots) - y_i,
+// f = sum r_i^2 (fixed order), then the decision: P.done 1 (kept) or 3
+// (reopened), kout[c] = iterations.
+__global__ __launch_bounds__(256) void k_bs_check_decide(BsPtrs P, const double* __restrict__ dot, int ns, int nc,
+                                                         const int32_t* __restrict__ cand,
+                                                         int32_t* __restrict__ kout) {
+    __shared__ double lds[256 / WAVE];
+    const int c = blockIdx.x, b = cand[c];
+    const int64_t n = P.n;
+    const double* y = P.Y + (int64_t)b * n;
     double acc = 0.0;
-    if constexpr (RPT > 0) {
-#pragma unroll
-        for (int k = 0; k < RPT; ++k) {
-            const int64_t i = tid + (int64_t)k * T;
-            if (i < n) {
-                const double d = r[k] - y[i];
-                acc += d * d;
-            }
-        }
-    } else {
-        for (int64_t i = tid; i < n; i += T) {
-            const double d = rq[i] - y[i];
-            acc += d * d;
-        }
+    for (int64_t i = threadIdx.x; i < n; i += 256) {
+        double t = 0.0;
+        for (int sidx = 0; sidx < ns; ++sidx) t += dot[((int64_t)sidx * nc + c) * n + i];
+        const double d = t - y[i];
+        acc += d * d;
     }
-    const double f = block_sum<T>(acc, lds);
-    if (tid == 0) {
+    const double f = block_sum<256>(acc, lds);
+    if (threadIdx.x == 0) {
         GPState* st = P.st + b;
         P.done[b] = target_decide(st, f) ? 1 : 3;
-        kout[blockIdx.x] = st->k;
+        kout[c] = st->k;
     }
+}
+
+// Column chunks of the check for nc problems: about 512 workgroups in all,
+// at most 16 chunks, whole tiles of 32 columns per chunk.
+void check_split(int64_t n, int64_t p, int nc, int* ns, int64_t* jchunk) {
+    const int64_t wg = ((n + CV_R - 1) / CV_R) * ((nc + CV_C - 1) / CV_C);
+    int64_t want = (512 + wg - 1) / wg;
+    const int64_t tiles = (p + CV_J - 1) / CV_J;
+    want = std::max<int64_t>(1, std::min<int64_t>({want, 16, tiles}));
+    const int64_t tpc = (tiles + want - 1) / want;
+    *jchunk = tpc * CV_J;
+    *ns = (int)((p + *jchunk - 1) / *jchunk);
 }
 
 // results: ||x||_1, ||g||_inf and x out in the vector dtype
@@ -734,6 +752,19 @@ int solve_batched_shared_mfma(gp_handle h, gp_dtype kdtype, const void* K, int64
     const size_t o_Qp = take(4 * (size_t)S1 * brows * npad), o_Wp = take(4 * (size_t)S2 * brows * ppad);
     const size_t o_rho = take(8 * B), o_ft = take(8 * B), o_list = take(4 * bpad);
     const size_t o_cand = take(4 * B), o_kout = take(4 * B);
+    // target check: the dots of every (column chunk, checked problem, row),
+    // for the largest chunk count x problem count a check can need
+    size_t check_elems = 0;
+    if (o.f_target >= 0.0 || o.f_targets) {
+        for (int64_t g = 1; g <= (B + CV_C - 1) / CV_C; ++g) {
+            int ns;
+            int64_t jchunk;
+            const int nc = (int)std::min<int64_t>(B, g * CV_C);
+            check_split(n, p, nc, &ns, &jchunk);
+            check_elems = std::max(check_elems, (size_t)ns * nc * n);
+        }
+    }
+    const size_t o_check = take(8 * check_elems);
     int rc = ensure_workspace(h, off);
     if (rc) return rc;
     if (o.graph && (rc = graph_stream(h, s, &s))) return rc;
@@ -757,6 +788,7 @@ int solve_batched_shared_mfma(gp_handle h, gp_dtype kdtype, const void* K, int64
     int32_t* dlist = (int32_t*)(ws + o_list);
     int32_t* dcand = (int32_t*)(ws + o_cand);
     int32_t* dkout = (int32_t*)(ws + o_kout);
+    double* dcheck = (double*)(ws + o_check);
     const bool check_target = o.f_target >= 0.0 || o.f_targets != nullptr;
     double* drho = (double*)(ws + o_rho);
     double* dft = o.f_targets ? (double*)(ws + o_ft) : nullptr;
@@ -816,17 +848,17 @@ int solve_batched_shared_mfma(gp_handle h, gp_dtype kdtype, const void* K, int64
 
     // target check of the problems that stopped at their target (P.done 2)
     auto launch_verify = [&](int nc) {
-        const dim3 g((unsigned)nc);
-#define GPL1_BS_VER(TT, RR) \
-    hipLaunchKernelGGL((k_bs_verify<TT, RR>), g, dim3(TT), 0, s, P, Kt, npad, kpl, nK, dcand, dkout)
-        if (n <= 256) GPL1_BS_VER(256, 1);
-        else if (n <= 512) GPL1_BS_VER(256, 2);
-        else if (n <= 1024) GPL1_BS_VER(256, 4);
-        else if (n <= 2048) GPL1_BS_VER(256, 8);
-        else if (n <= 4096) GPL1_BS_VER(256, 16);
-        else if (n <= 16384) GPL1_BS_VER(1024, 16);
-        else GPL1_BS_VER(256, 0);
-#undef GPL1_BS_VER
+        int ns;
+        int64_t jchunk;
+        check_split(n, p, nc, &ns, &jchunk);
+        const dim3 g((unsigned)((n + CV_R - 1) / CV_R), (unsigned)((nc + CV_C - 1) / CV_C), (unsigned)ns);
+        if (nK == 1)
+            hipLaunchKernelGGL(k_bs_check_tiles<uint16_t>, g, dim3(CV_T), 0, s, (const uint16_t*)K, ldk, n, p,
+                               (const double*)P.X, dcand, nc, jchunk, dcheck);
+        else
+            hipLaunchKernelGGL(k_bs_check_tiles<float>, g, dim3(CV_T), 0, s, (const float*)K, ldk, n, p,
+                               (const double*)P.X, dcand, nc, jchunk, dcheck);
+        hipLaunchKernelGGL(k_bs_check_decide, dim3((unsigned)nc), dim3(256), 0, s, P, dcheck, ns, nc, dcand, dkout);
     };
     std::vector<int32_t> hdone((size_t)B), hlist((size_t)bpad), hcand, hk;
     // a problem that is never stopped has done exactly `it` iterations; one
