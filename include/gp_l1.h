@@ -111,6 +111,7 @@ typedef struct {
                                  (a width with no compiled register shape for p: GP_E_ARG) */
     int32_t var_item_rows;    /* uneven batches: rows of K per work item of the fused pass, 16..1024
                                  (64 when 0) */
+    int32_t batch_gemm_depth; /* shared bf16 K: k-steps of GEMM loads in flight, 1 or 2 (1 when 0) */
 } gp_opts;
 
 typedef struct {

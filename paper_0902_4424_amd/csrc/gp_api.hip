@@ -186,6 +186,8 @@ int check_opts(gp_handle h, const gp_opts& o) {
             return fail(h, GP_E_ARG, "opts.batch_rows_t and batch_cols_t must be 0, 256, 512 or 1024");
     if (o.var_item_rows != 0 && (o.var_item_rows < 16 || o.var_item_rows > 1024))
         return fail(h, GP_E_ARG, "opts.var_item_rows must be 0 or in 16..1024");
+    if (o.batch_gemm_depth < 0 || o.batch_gemm_depth > 2)
+        return fail(h, GP_E_ARG, "opts.batch_gemm_depth must be 0, 1 or 2");
     return GP_OK_TOL;
 }
 
@@ -420,6 +422,7 @@ void gp_opts_default(gp_opts* o) {
     o->batch_rows_t = 0;
     o->batch_cols_t = 0;
     o->var_item_rows = 0;
+    o->batch_gemm_depth = 0;
 }
 
 int gp_create(gp_handle* out, int device) {

@@ -819,7 +819,10 @@ int solve_batched_shared_mfma(gp_handle h, gp_dtype kdtype, const void* K, int64
     auto gemm_planes = [&](const uint16_t* A0, int64_t lda, int64_t M, const uint16_t* Bpl, int64_t ldb,
                            int64_t plB, int S, int64_t kc, float* Cp, int64_t ldc, int64_t cs) {
         const dim3 grid((unsigned)(M / GM_BM), (unsigned)(rup(live, GM_BN) / GM_BN), (unsigned)S);
-        if (nK == 1)
+        if (nK == 1 && o.batch_gemm_depth == 2)
+            hipLaunchKernelGGL(k_gemm_bf16_d2<NSPL>, grid, dim3(GM_T), 0, s, A0, lda, Bpl, ldb, plB, (int)kc, Cp, ldc,
+                               cs, P.list);
+        else if (nK == 1)
             hipLaunchKernelGGL(k_gemm_bf16<NSPL>, grid, dim3(GM_T), 0, s, A0, lda, Bpl, ldb, plB, (int)kc, Cp, ldc, cs,
                                P.list);
         else

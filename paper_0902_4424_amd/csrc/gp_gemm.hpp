@@ -151,6 +151,137 @@ __global__ __launch_bounds__(GM_T) void k_gemm_bf16(const uint16_t* __restrict__
 #undef GPL1_ST
 }
 
+// k_gemm_bf16 with the global loads issued two k-steps ahead: two sets of
+// staging registers (S and T) alternate, so a step's tiles have about two
+// steps of matrix-core work to arrive instead of one.  That is what a grid of
+// one workgroup per CU needs when the operands come from the Infinity Cache
+// rather than L2.  Same arguments, tiling and output as k_gemm_bf16.
+template <int NSPLIT>
+__global__ __launch_bounds__(GM_T) void k_gemm_bf16_d2(const uint16_t* __restrict__ A, int64_t lda,
+                                                       const uint16_t* __restrict__ Bp, int64_t ldb,
+                                                       int64_t pstride, int kchunk,
+                                                       float* __restrict__ Cpart, int64_t ldc,
+                                                       int64_t cstride, const int32_t* __restrict__ nmap) {
+    static_assert(NSPLIT >= 1 && NSPLIT <= 3, "one to three bf16 planes");
+    constexpr int TILE = GM_BM * GM_LDS_ROW;
+    __shared__ __attribute__((aligned(16))) uint16_t lds[2][(1 + NSPLIT) * TILE];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave & 1, wn = wave >> 1;
+    const int64_t m0 = (int64_t)blockIdx.x * GM_BM;
+    const int64_t n0 = (int64_t)blockIdx.y * GM_BN;
+    const int64_t k_begin = (int64_t)blockIdx.z * kchunk;
+    const int nsteps = kchunk / GM_BK;
+    const int c0_ = tid, c1_ = tid + GM_T;
+    const int row0_ = c0_ >> 2, kc0_ = (c0_ & 3) * 8, row1_ = c1_ >> 2, kc1_ = (c1_ & 3) * 8;
+    const uint16_t* a0p = A + (m0 + row0_) * lda + k_begin + kc0_;
+    const uint16_t* a1p = A + (m0 + row1_) * lda + k_begin + kc1_;
+    const int64_t bn0_ = nmap ? nmap[n0 + row0_] : n0 + row0_;
+    const int64_t bn1_ = nmap ? nmap[n0 + row1_] : n0 + row1_;
+    const uint16_t* b0p = Bp + bn0_ * ldb + k_begin + kc0_;
+    const uint16_t* b1p = Bp + bn1_ * ldb + k_begin + kc1_;
+    // two staging sets, named one by one so that they stay in VGPRs
+    uint4 Sa0, Sa1, Sb00, Sb01, Sb10, Sb11, Sb20, Sb21;
+    uint4 Ta0, Ta1, Tb00, Tb01, Tb10, Tb11, Tb20, Tb21;
+#define GPL1_D2_LD(p_, off_) (*reinterpret_cast<const uint4*>((p_) + (off_)))
+#define GPL1_D2_GLOAD(X_, step_)                                                \
+    {                                                                           \
+        const int64_t ko_ = (int64_t)(step_) * GM_BK;                           \
+        X_##a0 = GPL1_D2_LD(a0p, ko_);                                          \
+        X_##a1 = GPL1_D2_LD(a1p, ko_);                                          \
+        X_##b00 = GPL1_D2_LD(b0p, ko_);                                         \
+        X_##b01 = GPL1_D2_LD(b1p, ko_);                                         \
+        if constexpr (NSPLIT > 1) {                                             \
+            X_##b10 = GPL1_D2_LD(b0p, pstride + ko_);                           \
+            X_##b11 = GPL1_D2_LD(b1p, pstride + ko_);                           \
+        }                                                                       \
+        if constexpr (NSPLIT > 2) {                                             \
+            X_##b20 = GPL1_D2_LD(b0p, 2 * pstride + ko_);                       \
+            X_##b21 = GPL1_D2_LD(b1p, 2 * pstride + ko_);                       \
+        }                                                                       \
+    }
+#define GPL1_D2_ST(buf_, t_, row_, kc_, v_) \
+    (*reinterpret_cast<uint4*>(&lds[buf_][(t_) * TILE + (row_) * GM_LDS_ROW + (kc_)]) = (v_))
+#define GPL1_D2_LSTORE(buf_, X_)                                                \
+    {                                                                           \
+        GPL1_D2_ST(buf_, 0, row0_, kc0_, X_##a0);                               \
+        GPL1_D2_ST(buf_, 0, row1_, kc1_, X_##a1);                               \
+        GPL1_D2_ST(buf_, 1, row0_, kc0_, X_##b00);                              \
+        GPL1_D2_ST(buf_, 1, row1_, kc1_, X_##b01);                              \
+        if constexpr (NSPLIT > 1) {                                             \
+            GPL1_D2_ST(buf_, 2, row0_, kc0_, X_##b10);                          \
+            GPL1_D2_ST(buf_, 2, row1_, kc1_, X_##b11);                          \
+        }                                                                       \
+        if constexpr (NSPLIT > 2) {                                             \
+            GPL1_D2_ST(buf_, 3, row0_, kc0_, X_##b20);                          \
+            GPL1_D2_ST(buf_, 3, row1_, kc1_, X_##b21);                          \
+        }                                                                       \
+    }
+// one k-step: every fragment of the step is read from LDS first, then the
+// 16 * NSPLIT MFMAs issue back to back (the scheduling barriers keep the
+// compiler from interleaving reads and waits between them)
+#define GPL1_D2_COMPUTE(buf_)                                                   \
+    {                                                                           \
+        bf16x8_t af[4], bfr[NSPLIT][4];                                         \
+        _Pragma("unroll") for (int i = 0; i < 4; ++i)                           \
+            af[i] = *reinterpret_cast<const bf16x8_t*>(&lds[buf_][(wm * 64 + i * 16 + fr) * GM_LDS_ROW + fk]); \
+        _Pragma("unroll") for (int t = 0; t < NSPLIT; ++t)                      \
+        _Pragma("unroll") for (int j = 0; j < 4; ++j)                           \
+            bfr[t][j] = *reinterpret_cast<const bf16x8_t*>(                     \
+                &lds[buf_][(1 + t) * TILE + (wn * 64 + j * 16 + fr) * GM_LDS_ROW + fk]); \
+        __builtin_amdgcn_sched_group_barrier(0x100, 4 + 4 * NSPLIT, 0);         \
+        _Pragma("unroll") for (int t = 0; t < NSPLIT; ++t)                      \
+        _Pragma("unroll") for (int j = 0; j < 4; ++j)                           \
+        _Pragma("unroll") for (int i = 0; i < 4; ++i)                           \
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[t][j], acc[i][j], 0, 0, 0); \
+        __builtin_amdgcn_sched_group_barrier(0x008, 16 * NSPLIT, 0);            \
+    }
+
+    f32x4_t acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+    const int fr = lane & 15, fk = (lane >> 4) * 8;
+    // Every load is issued unconditionally (steps past the end re-read the
+    // last one), so the count of loads in flight is the same on every path
+    // and the wait before storing one set leaves the other set in flight.
+    const int last = nsteps - 1;
+    GPL1_D2_GLOAD(S, 0)
+    GPL1_D2_LSTORE(0, S)
+    GPL1_D2_GLOAD(S, 1 < last ? 1 : last)
+    GPL1_D2_GLOAD(T, 2 < last ? 2 : last)
+    __syncthreads();
+    // buffer 0 holds even steps, buffer 1 odd ones; S carries odd steps, T even ones
+    for (int step = 0; step < nsteps; step += 2) {
+        GPL1_D2_COMPUTE(0)
+        if (step + 1 >= nsteps) break;
+        GPL1_D2_LSTORE(1, S)
+        __syncthreads();
+        GPL1_D2_GLOAD(S, step + 3 < last ? step + 3 : last)
+        GPL1_D2_COMPUTE(1)
+        if (step + 2 >= nsteps) break;
+        GPL1_D2_LSTORE(0, T)
+        __syncthreads();
+        GPL1_D2_GLOAD(T, step + 4 < last ? step + 4 : last)
+    }
+    float* out = Cpart + (int64_t)blockIdx.z * cstride;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int64_t m = m0 + wm * 64 + i * 16 + (lane >> 4) * 4;
+            const int64_t nl = n0 + wn * 64 + j * 16 + (lane & 15);
+            const int64_t nn = nmap ? nmap[nl] : nl;
+            *reinterpret_cast<float4*>(out + nn * ldc + m) =
+                make_float4(acc[i][j][0], acc[i][j][1], acc[i][j][2], acc[i][j][3]);
+        }
+#undef GPL1_D2_GLOAD
+#undef GPL1_D2_LSTORE
+#undef GPL1_D2_LD
+#undef GPL1_D2_ST
+#undef GPL1_D2_COMPUTE
+}
+
 // Both operands as bf16 planes: A = sum_a A_a (NA planes, stride apstride),
 // B = sum_t B_t (NB planes), and only the plane products with a + t < NB are
 // formed: for NA = NB = 3 that is A_h (B_h + B_m + B_l) + A_m (B_h + B_m) +

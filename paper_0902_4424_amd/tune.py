@@ -161,7 +161,7 @@ def tune_shared(H, dtype, n, p, B, reps=3, log=print):
         return min(ts)
 
     space = {"batch_splitk": (256, 512, 2048), "batch_rows_t": (512, 1024), "batch_cols_t": (256, 512, 1024),
-             "graph": (1,)}
+             "batch_gemm_depth": (2,) if dtype == "bf16" else (), "graph": (1,)}
     best, t = _coordinate_search(space, run, log)
     return dict(best, solve_ms=round(t * 1e3, 3))
 

@@ -498,11 +498,20 @@ def test_batched_tuning_options(H):
         say(f"[tuning] shared {kw}")
         X, res = H.solve_batched_shared(Kt, Y, batch.rho, **base, **kw)
         _check_columns(batch, X, res, range(5))
+    # loads two k-steps ahead: the same products in the same order, so the
+    # same bits; chunks of 1, 2 and 3 k-steps (split-K 32 and 96) cover the
+    # loop's odd and early exits
+    for sk in (0, 96, 32):
+        say(f"[tuning] shared GEMM depth 2, split-K {sk}")
+        X1, r1 = H.solve_batched_shared(Kt, Y, batch.rho, batch_splitk=sk, batch_gemm_depth=1, **base)
+        X2, r2 = H.solve_batched_shared(Kt, Y, batch.rho, batch_splitk=sk, batch_gemm_depth=2, **base)
+        assert torch.equal(X1, X2) and r1 == r2
+    _check_columns(batch, X2, r2, range(5))
     # p = 2100 needs 16 slots at 256 threads: not a compiled shape
     with pytest.raises(gpl1.GPError) as e:
         H.solve_batched_shared(Kt, Y, batch.rho, batch_cols_t=256, **base)
     assert e.value.code == -1
-    for bad in (dict(batch_splitk=100), dict(batch_rows_t=300), dict(var_item_rows=8)):
+    for bad in (dict(batch_splitk=100), dict(batch_rows_t=300), dict(var_item_rows=8), dict(batch_gemm_depth=3)):
         with pytest.raises(gpl1.GPError):
             H.solve_batched_shared(Kt, Y, batch.rho, **base, **bad)
     rng = np.random.default_rng(85)
