@@ -209,13 +209,51 @@ __global__ __launch_bounds__(T) void k_bv_update(const VarInst* __restrict__ I, 
     const double lam = sh[0];
     for (int64_t i = tid; i < D.n; i += T) D.r[i] += lam * D.q[i];
     double dots[2] = {0.0, 0.0};
-    for (int64_t j = tid; j < D.p; j += T) {
-        const double w = wsum(j);
-        const double dj = D.d[j];
-        D.x[j] += lam * dj;
-        D.g[j] += 2.0 * lam * w;
-        dots[0] += dj * w;
-        dots[1] += w * w;
+    // JU columns per thread at a time; the items' partial values of those
+    // columns are requested eight items at a time (clamped indices, values
+    // masked) and added in item order, as wsum does
+    constexpr int JU = 4, CU = 8;
+    for (int64_t j0 = tid; j0 < D.p; j0 += (int64_t)T * JU) {
+        double w[JU];
+#pragma unroll
+        for (int u = 0; u < JU; ++u) w[u] = 0.0;
+        for (int64_t c0 = 0; c0 < D.nitems; c0 += CU) {
+            ACC v[JU][CU];
+#pragma unroll
+            for (int u = 0; u < JU; ++u) {
+                const int64_t j = j0 + (int64_t)u * T;
+                const int64_t jc = j < D.p ? j : 0;
+#pragma unroll
+                for (int cc = 0; cc < CU; ++cc) {
+                    const int64_t c = c0 + cc < D.nitems ? c0 + cc : 0;
+                    v[u][cc] = wp[c * D.ldw + jc];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < JU; ++u)
+#pragma unroll
+                for (int cc = 0; cc < CU; ++cc)
+                    if (c0 + cc < D.nitems) w[u] += (double)v[u][cc];
+        }
+        double dj[JU], xj[JU], gj[JU];
+#pragma unroll
+        for (int u = 0; u < JU; ++u) {
+            const int64_t j = j0 + (int64_t)u * T;
+            const int64_t jc = j < D.p ? j : 0;
+            dj[u] = D.d[jc];
+            xj[u] = D.x[jc];
+            gj[u] = D.g[jc];
+        }
+#pragma unroll
+        for (int u = 0; u < JU; ++u) {
+            const int64_t j = j0 + (int64_t)u * T;
+            if (j < D.p) {
+                D.x[j] = xj[u] + lam * dj[u];
+                D.g[j] = gj[u] + 2.0 * lam * w[u];
+                dots[0] += dj[u] * w[u];
+                dots[1] += w[u] * w[u];
+            }
+        }
     }
     block_reduce<T, 2, 1>(dots, none, lds);
     if (tid == 0) {
@@ -251,6 +289,22 @@ __global__ __launch_bounds__(T) void k_bv_proj(const VarInst* __restrict__ I, GP
     double m, t;
     bool inside;
     int passes;
+    // x and g of this thread's slots, requested together (clamped indices,
+    // values masked) and kept for the output loop while they fit the
+    // registers (else read again where used)
+    constexpr bool KEEP = T <= 256 || NV <= 8;
+    double xr[KEEP ? NV : 1], gr[KEEP ? NV : 1];
+    auto xval = [&](int e, int j) { return KEEP ? xr[KEEP ? e : 0] : D.x[j]; };
+    auto gval = [&](int e, int j) { return KEEP ? gr[KEEP ? e : 0] : D.g[j]; };
+    if constexpr (KEEP) {
+#pragma unroll
+        for (int e = 0; e < NV; ++e) {
+            const int j = 2 * ((e / 2) * T + tid) + (e & 1);
+            const int jc = j < p ? j : 0;
+            xr[e] = D.x[jc];
+            gr[e] = D.g[jc];
+        }
+    }
     if (tid == 0) { sh[0] = st->alpha; sh[1] = st->mu; }
     __syncthreads();
     double alpha = sh[0];
@@ -258,7 +312,7 @@ __global__ __launch_bounds__(T) void k_bv_proj(const VarInst* __restrict__ I, GP
 #pragma unroll
         for (int e = 0; e < NV; ++e) {
             const int j = 2 * ((e / 2) * T + tid) + (e & 1);
-            vr[e] = j < p ? D.x[j] - D.g[j] : 0.0;
+            vr[e] = j < p ? xval(e, j) - gval(e, j) : 0.0;
         }
         l1_threshold_regs<T, NV>(vr, p, rho, -1.0, lds, m, t, inside, passes);
         double hm = 0.0;
@@ -273,7 +327,7 @@ __global__ __launch_bounds__(T) void k_bv_proj(const VarInst* __restrict__ I, GP
 #pragma unroll
     for (int e = 0; e < NV; ++e) {
         const int j = 2 * ((e / 2) * T + tid) + (e & 1);
-        vr[e] = j < p ? D.x[j] - alpha * D.g[j] : 0.0;
+        vr[e] = j < p ? xval(e, j) - alpha * gval(e, j) : 0.0;
     }
     double mloc = 0.0;
 #pragma unroll
@@ -286,9 +340,9 @@ __global__ __launch_bounds__(T) void k_bv_proj(const VarInst* __restrict__ I, GP
     for (int e = 0; e < NV; ++e) {
         const int j = 2 * ((e / 2) * T + tid) + (e & 1);
         if (j < p) {
-            const double dj = l1_hval(vr[e], m, t, inside, rho) - D.x[j];
+            const double dj = l1_hval(vr[e], m, t, inside, rho) - xval(e, j);
             D.d[j] = dj;
-            sums[0] += D.g[j] * dj;
+            sums[0] += gval(e, j) * dj;
             sums[1] += dj * dj;
             mx[0] = fmax(mx[0], fabs(dj));
         }
