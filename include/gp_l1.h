@@ -112,6 +112,8 @@ typedef struct {
     int32_t var_item_rows;    /* uneven batches: rows of K per work item of the fused pass, 16..1024
                                  (64 when 0) */
     int32_t batch_gemm_depth; /* shared bf16 K: k-steps of GEMM loads in flight, 1 or 2 (1 when 0) */
+    int32_t batch_gemm_tile;  /* shared bf16 K: rows of the GEMM output tile, 128 or 256 (128 when 0;
+                                 256 takes one k-step in flight and about half the reduction chunk) */
 } gp_opts;
 
 typedef struct {

@@ -188,6 +188,10 @@ int check_opts(gp_handle h, const gp_opts& o) {
         return fail(h, GP_E_ARG, "opts.var_item_rows must be 0 or in 16..1024");
     if (o.batch_gemm_depth < 0 || o.batch_gemm_depth > 2)
         return fail(h, GP_E_ARG, "opts.batch_gemm_depth must be 0, 1 or 2");
+    if (o.batch_gemm_tile != 0 && o.batch_gemm_tile != 128 && o.batch_gemm_tile != 256)
+        return fail(h, GP_E_ARG, "opts.batch_gemm_tile must be 0, 128 or 256");
+    if (o.batch_gemm_tile == 256 && o.batch_gemm_depth == 2)
+        return fail(h, GP_E_ARG, "opts.batch_gemm_depth = 2 is for 128-row GEMM tiles");
     return GP_OK_TOL;
 }
 
@@ -423,6 +427,7 @@ void gp_opts_default(gp_opts* o) {
     o->batch_cols_t = 0;
     o->var_item_rows = 0;
     o->batch_gemm_depth = 0;
+    o->batch_gemm_tile = 0;
 }
 
 int gp_create(gp_handle* out, int device) {

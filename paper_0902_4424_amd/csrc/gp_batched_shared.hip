@@ -729,9 +729,10 @@ int solve_batched_shared_mfma(gp_handle h, gp_dtype kdtype, const void* K, int64
     const int rt = o.batch_rows_t ? o.batch_rows_t : 256, rrpt = rows_rpt(n, rt);
     const int64_t npad = rup(n, BS_PAD), ppad = rup(p, BS_PAD), bpad = rup(B, BS_PAD);
     // split-K chunks (multiples of 32 dividing the padded size) per GEMM:
-    // about 1024, or the tuned size
+    // about 1024 (512 with 256-row tiles), or the tuned size
+    const bool tile256 = nK == 1 && o.batch_gemm_tile == 256;
     auto chunk_of = [&](int64_t kd) {
-        int64_t c = std::min<int64_t>(kd, o.batch_splitk > 0 ? o.batch_splitk : 1024);
+        int64_t c = std::min<int64_t>(kd, o.batch_splitk > 0 ? o.batch_splitk : (tile256 ? 512 : 1024));
         while (kd % c) c -= 32;
         return c;
     };
@@ -819,7 +820,10 @@ int solve_batched_shared_mfma(gp_handle h, gp_dtype kdtype, const void* K, int64
     auto gemm_planes = [&](const uint16_t* A0, int64_t lda, int64_t M, const uint16_t* Bpl, int64_t ldb,
                            int64_t plB, int S, int64_t kc, float* Cp, int64_t ldc, int64_t cs) {
         const dim3 grid((unsigned)(M / GM_BM), (unsigned)(rup(live, GM_BN) / GM_BN), (unsigned)S);
-        if (nK == 1 && o.batch_gemm_depth == 2)
+        if (tile256)
+            hipLaunchKernelGGL(k_gemm_bf16_m256<NSPL>, dim3((unsigned)((M + GM2_BM - 1) / GM2_BM), grid.y, grid.z),
+                               dim3(GM2_T), 0, s, A0, lda, Bpl, ldb, plB, (int)kc, Cp, ldc, cs, P.list, M);
+        else if (nK == 1 && o.batch_gemm_depth == 2)
             hipLaunchKernelGGL(k_gemm_bf16_d2<NSPL>, grid, dim3(GM_T), 0, s, A0, lda, Bpl, ldb, plB, (int)kc, Cp, ldc,
                                cs, P.list);
         else if (nK == 1)

@@ -41,7 +41,7 @@ class GPOpts(C.Structure):
                 ("x0_fallback", C.c_int32), ("graph", C.c_int32),
                 ("batch_splitk", C.c_int32), ("batch_rows_t", C.c_int32),
                 ("batch_cols_t", C.c_int32), ("var_item_rows", C.c_int32),
-                ("batch_gemm_depth", C.c_int32)]
+                ("batch_gemm_depth", C.c_int32), ("batch_gemm_tile", C.c_int32)]
 
 
 class GPResult(C.Structure):
@@ -515,7 +515,7 @@ def _tuned(kdt, n, p, kw):
     return kw
 
 
-_SHARED_KEYS = ("batch_splitk", "batch_rows_t", "batch_cols_t", "batch_gemm_depth", "graph")
+_SHARED_KEYS = ("batch_splitk", "batch_rows_t", "batch_cols_t", "batch_gemm_depth", "batch_gemm_tile", "graph")
 
 
 def _tuned_shared(kdt, n, p, B, kw):

@@ -7,7 +7,7 @@ per block) and grid sizes (row slabs), and records the fastest; the binding
 passes it through gp_opts.fused_cfg / fused_grid / fused_interleave.
 
 Shared-K batches (dtype, n, p, B): the whole batched solve to a relative
-change of 1e-10 over the GEMM split-K chunk, the per-problem row and column
+change of 1e-10 over the GEMM output tile and split-K chunk, the per-problem row and column
 kernel widths and graph replay, one option at a time (coordinate search from
 the automatic choice).  Uneven batches (dtype, the 512-problem workload of n
 in [128, 1024], p = 4n): rows per work item and graph replay.
@@ -160,7 +160,8 @@ def tune_shared(H, dtype, n, p, B, reps=3, log=print):
         log(f"  {shared_key(dtype, n, p, B)} {kw or 'automatic'}: {min(ts) * 1e3:.3f} ms")
         return min(ts)
 
-    space = {"batch_splitk": (256, 512, 2048), "batch_rows_t": (512, 1024), "batch_cols_t": (256, 512, 1024),
+    space = {"batch_gemm_tile": (256,) if dtype == "bf16" else (), "batch_splitk": (256, 512, 1024, 2048),
+             "batch_rows_t": (512, 1024), "batch_cols_t": (256, 512, 1024),
              "batch_gemm_depth": (2,) if dtype == "bf16" else (), "graph": (1,)}
     best, t = _coordinate_search(space, run, log)
     return dict(best, solve_ms=round(t * 1e3, 3))

@@ -507,11 +507,21 @@ def test_batched_tuning_options(H):
         X2, r2 = H.solve_batched_shared(Kt, Y, batch.rho, batch_splitk=sk, batch_gemm_depth=2, **base)
         assert torch.equal(X1, X2) and r1 == r2
     _check_columns(batch, X2, r2, range(5))
+    # 256-row GEMM tiles: each wave's sub-tile products in the same order, so
+    # the same bits for the same split-K chunk; both padded sizes (384 and
+    # 2176 rows) end in half a tile
+    for sk in (512, 96, 32):
+        say(f"[tuning] shared GEMM tile 256, split-K {sk}")
+        X1, r1 = H.solve_batched_shared(Kt, Y, batch.rho, batch_splitk=sk, batch_gemm_tile=128, **base)
+        X3, r3 = H.solve_batched_shared(Kt, Y, batch.rho, batch_splitk=sk, batch_gemm_tile=256, **base)
+        assert torch.equal(X1, X3) and r1 == r3
+    _check_columns(batch, X3, r3, range(5))
     # p = 2100 needs 16 slots at 256 threads: not a compiled shape
     with pytest.raises(gpl1.GPError) as e:
         H.solve_batched_shared(Kt, Y, batch.rho, batch_cols_t=256, **base)
     assert e.value.code == -1
-    for bad in (dict(batch_splitk=100), dict(batch_rows_t=300), dict(var_item_rows=8), dict(batch_gemm_depth=3)):
+    for bad in (dict(batch_splitk=100), dict(batch_rows_t=300), dict(var_item_rows=8), dict(batch_gemm_depth=3),
+                dict(batch_gemm_tile=100), dict(batch_gemm_tile=256, batch_gemm_depth=2)):
         with pytest.raises(gpl1.GPError):
             H.solve_batched_shared(Kt, Y, batch.rho, **base, **bad)
     rng = np.random.default_rng(85)
