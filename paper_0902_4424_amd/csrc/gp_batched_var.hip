@@ -98,11 +98,7 @@ __global__ __launch_bounds__(BV_T) void k_bv_init(const VarInst* __restrict__ I,
 
 // fused pass on one work item; v = x (refresh, with y subtracted) or d
 template <typename TK, typename ACC, int CPT>
-__global__ __launch_bounds__(BV_FT) void k_bv_fused(const VarInst* __restrict__ I, const VarItem* __restrict__ items,
-                                                    const GPState* __restrict__ st, int refresh) {
-    const VarItem it = items[blockIdx.x];
-    if (st[it.inst].done) return;
-    const VarInst D = I[it.inst];
+__device__ __forceinline__ void bv_item(const VarItem& it, const VarInst& D, int refresh) {
     ACC* wp;
     if constexpr (sizeof(ACC) == 8) wp = (ACC*)D.wpart64;
     else wp = (ACC*)D.wpart;
@@ -131,6 +127,25 @@ __global__ __launch_bounds__(BV_FT) void k_bv_fused(const VarInst* __restrict__ 
     fused_body<TK, ACC, BV_FT, CPT, BV_RB, BV_NB, false>((const TK*)D.K, D.n, D.p, D.ldk, D.item_rows, v, nullptr,
                                                           nullptr, ys, rs, D.q, wrow, D.ldw, sp, 0, it.slab,
                                                           D.nitems);
+}
+
+// CPT column chunks per thread cover the widest problem of the batch; an
+// item of a narrower problem runs with the fewest chunks that cover its own p
+// (the chunks past p hold zeros either way, so the sums are the same)
+template <typename TK, typename ACC, int CPT>
+__global__ __launch_bounds__(BV_FT) void k_bv_fused(const VarInst* __restrict__ I, const VarItem* __restrict__ items,
+                                                    const GPState* __restrict__ st, int refresh) {
+    const VarItem it = items[blockIdx.x];
+    if (st[it.inst].done) return;
+    const VarInst D = I[it.inst];
+    constexpr int64_t COLS1 = (int64_t)BV_FT * KTraits<TK>::VEC;   // columns of one chunk per thread
+    if constexpr (CPT >= 4) {
+        if (D.p <= COLS1) { bv_item<TK, ACC, 1>(it, D, refresh); return; }
+        if (D.p <= 2 * COLS1) { bv_item<TK, ACC, 2>(it, D, refresh); return; }
+    } else if constexpr (CPT == 2) {
+        if (D.p <= COLS1) { bv_item<TK, ACC, 1>(it, D, refresh); return; }
+    }
+    bv_item<TK, ACC, CPT>(it, D, refresh);
 }
 
 // line search, updates, steplength rule (iteration) or r, g, f (refresh)
