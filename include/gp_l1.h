@@ -114,6 +114,12 @@ typedef struct {
     int32_t batch_gemm_depth; /* shared bf16 K: k-steps of GEMM loads in flight, 1 or 2 (1 when 0) */
     int32_t batch_gemm_tile;  /* shared bf16 K: rows of the GEMM output tile, 128 or 256 (128 when 0;
                                  256 takes one k-step in flight and about half the reduction chunk) */
+    int32_t lookahead;        /* gp_l1_solve without graph: k > 0 = keep at most k iterations enqueued
+                                 ahead of the device, which posts every completed update to a
+                                 host-mapped word of the handle, and poll the state only once a stop
+                                 is posted (a stop leaves at most about k iterations of launches
+                                 that return at once, and no status polls before it); 0 = `chunk`
+                                 iterations between status polls.  Results are identical. */
 } gp_opts;
 
 typedef struct {
@@ -137,7 +143,7 @@ typedef struct gp_handle_s* gp_handle;
 
 /* Fill `o` with the paper's GPSS parameters, max_iter = 100000,
  * f_target = -1 (off), f_targets = NULL, x0_fallback = 0, graph = 0, refresh_every = 0,
- * backtrack_cap = 60, chunk = 64, automatic kernel shapes. */
+ * backtrack_cap = 60, chunk = 64, lookahead = 2, automatic kernel shapes. */
 void gp_opts_default(gp_opts* o);
 
 /* Create a handle bound to HIP device `device`; it owns the solver's scratch

@@ -5,6 +5,7 @@
 #include <hip/hip_ext.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -161,6 +162,7 @@ GPParams make_params(const gp_opts& o, double rho, double tol) {
     P.max_iter = o.max_iter;
     P.bt_cap = o.backtrack_cap;
     P.x0_fallback = o.x0_fallback ? 1 : 0;
+    P.progress = nullptr;
     return P;
 }
 
@@ -190,6 +192,7 @@ int check_opts(gp_handle h, const gp_opts& o) {
         return fail(h, GP_E_ARG, "opts.batch_gemm_depth must be 0, 1 or 2");
     if (o.batch_gemm_tile != 0 && o.batch_gemm_tile != 128 && o.batch_gemm_tile != 256)
         return fail(h, GP_E_ARG, "opts.batch_gemm_tile must be 0, 128 or 256");
+    if (o.lookahead < 0) return fail(h, GP_E_ARG, "opts.lookahead must be >= 0");
     if (o.batch_gemm_tile == 256 && o.batch_gemm_depth == 2)
         return fail(h, GP_E_ARG, "opts.batch_gemm_depth = 2 is for 128-row GEMM tiles");
     return GP_OK_TOL;
@@ -428,6 +431,7 @@ void gp_opts_default(gp_opts* o) {
     o->var_item_rows = 0;
     o->batch_gemm_depth = 0;
     o->batch_gemm_tile = 0;
+    o->lookahead = 2;
 }
 
 int gp_create(gp_handle* out, int device) {
@@ -441,13 +445,21 @@ int gp_create(gp_handle* out, int device) {
     h->device = device;
     e = hipSetDevice(device);
     if (e == hipSuccess) e = hipHostMalloc((void**)&h->host_state, sizeof(GPState), hipHostMallocDefault);
+    // the progress word: coherent, so the device's system-scope stores reach
+    // the host's loads without a synchronisation
+    if (e == hipSuccess)
+        e = hipHostMalloc((void**)&h->progress, 64, hipHostMallocMapped | hipHostMallocCoherent);
+    if (e == hipSuccess) e = hipHostGetDevicePointer((void**)&h->progress_dev, h->progress, 0);
     if (e != hipSuccess) {
+        if (h->progress) (void)hipHostFree(h->progress);
+        if (h->host_state) (void)hipHostFree(h->host_state);
         delete h;
         return GP_E_HIP;
     }
     // the allocation-free solve's scratch: its address on this device (the
     // device is current here)
     if (setup_scratch(device) != GP_OK_TOL) {
+        (void)hipHostFree(h->progress);
         (void)hipHostFree(h->host_state);
         delete h;
         return GP_E_HIP;
@@ -461,6 +473,7 @@ int gp_destroy(gp_handle h) {
     (void)hipSetDevice(h->device);
     if (h->ws) (void)hipFree(h->ws);
     if (h->host_state) (void)hipHostFree(h->host_state);
+    if (h->progress) (void)hipHostFree(h->progress);
     for (hipEvent_t ev : h->events) (void)hipEventDestroy(ev);
     if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
     if (h->gexec_b) (void)hipGraphExecDestroy(h->gexec_b);
@@ -582,13 +595,20 @@ static int solve_single(gp_handle h, gp_dtype kdtype, const void* K, int64_t n, 
     const bool aligned = (ldk % vec == 0) && (((uintptr_t)K) % 16 == 0);
     const bool f64v = kdtype == GP_F64;
 
+    // lookahead: the update kernel posts its progress to the handle's
+    // host-mapped word, cleared here (the handle's last solve has ended with
+    // a synchronising poll, so no launch of it can still write the word)
+    const bool ahead = o.lookahead > 0 && !o.graph;
+    if (ahead) __atomic_store_n(h->progress, 0u, __ATOMIC_RELEASE);
     {
+        GPParams prm = make_params(o, rho, tol);
+        if (ahead) prm.progress = h->progress_dev;
         const unsigned sg = (unsigned)((std::max(n, p) + 255) / 256);
         if (f64v)
-            hipLaunchKernelGGL(k_setup<double>, dim3(sg), dim3(256), 0, s, st, make_params(o, rho, tol),
+            hipLaunchKernelGGL(k_setup<double>, dim3(sg), dim3(256), 0, s, st, prm,
                                (const double*)y, y64, n, (const double*)x0, x, p);
         else
-            hipLaunchKernelGGL(k_setup<float>, dim3(sg), dim3(256), 0, s, st, make_params(o, rho, tol),
+            hipLaunchKernelGGL(k_setup<float>, dim3(sg), dim3(256), 0, s, st, prm,
                                (const float*)y, y64, n, (const float*)x0, x, p);
     }
     if (x0) launch_proj(s, st, PM_INIT_X0, p, x, nullptr, nullptr, nullptr, 0, vb, nullptr);
@@ -699,9 +719,79 @@ static int solve_single(gp_handle h, gp_dtype kdtype, const void* K, int64_t n, 
         if (ce != hipSuccess) return hip_fail(h, ce, "target check");
         return h->host_state->done ? 0 : 1;
     };
+    // one iteration's launches: projection (with the steplength rule), fused
+    // K / K^T pass, update, and the residual refresh where one falls due
+    auto enqueue_iteration = [&](int i) {
+        launch_proj(s, st, PM_ITER, p, x, g, nullptr, upart, P.GU, vb, d32);
+        // every profile-th iteration's fused launch is bracketed by events
+        if (o.profile > 0 && i % o.profile == 0) {
+            FusedArgs fa = fa_iter;
+            fa.ev0 = prof_event(h);
+            fa.ev1 = fa.ev0 ? prof_event(h) : nullptr;
+            if (fa.ev0 && !fa.ev1) { --h->ev_used; fa.ev0 = nullptr; }   // keep the pairs aligned
+            launch_fused(kdtype, P.cfg, aligned, s, P.G, fa);
+        } else {
+            launch_fused(kdtype, P.cfg, aligned, s, P.G, fa_iter);
+        }
+        launch_update(kdtype, s, st, UM_ITER, spart, (int)P.G, wpart, P.ldw, p, n, x, g, r, q, upart);
+        if (o.refresh_every > 0 && (i + 1) % o.refresh_every == 0 && i + 1 < o.max_iter) refresh();
+    };
+    // lookahead: wait until the device has completed `need` updates (0), has
+    // posted a stop (1), or has run out of launches without either (2: a
+    // stop that the update kernel does not post, or a device faster than the
+    // host); < 0 is an error
+    auto wait_progress = [&](int need) -> int {
+        auto last = std::chrono::steady_clock::now();
+        for (;;) {
+            const uint32_t w = __atomic_load_n(h->progress, __ATOMIC_ACQUIRE);
+            if (w & 0x80000000u) return 1;
+            if ((int)(w & 0x7fffffffu) >= need) return 0;
+            const auto now = std::chrono::steady_clock::now();
+            // the stream is queried only after a millisecond without news: a
+            // query can enqueue a marker between the kernels
+            if (now - last > std::chrono::milliseconds(1)) {
+                last = now;
+                const hipError_t q = hipStreamQuery(s);
+                if (q == hipSuccess) return 2;
+                if (q != hipErrorNotReady) return hip_fail(h, q, "progress wait");
+            }
+            __builtin_ia32_pause();
+        }
+    };
     bool finished = false;
     int it = 0;
     while (it < o.max_iter) {
+        if (ahead) {
+            for (; it < o.max_iter; ++it) {
+                const int wr = wait_progress(it - o.lookahead);
+                if (wr < 0) return wr;
+                if (wr == 1) break;
+                if (wr == 2) {
+                    // the device is idle and posted no stop: read its state
+                    if ((rc = poll(false))) return rc;
+                    if (h->host_state->done) break;
+                }
+                enqueue_iteration(it);
+            }
+            e = hipGetLastError();
+            if (e != hipSuccess) return hip_fail(h, e, "iteration launch");
+            if ((rc = poll(it >= o.max_iter))) return rc;
+            if (h->host_state->done) {
+                const int re = check();
+                if (re < 0) return re;
+                if (re) {
+                    // reopened: the stream is idle, so the word can be reset
+                    it = h->host_state->k;
+                    __atomic_store_n(h->progress, (uint32_t)it, __ATOMIC_RELEASE);
+                    continue;
+                }
+                finished = true;
+                break;
+            }
+            // a posted stop that the state does not show: pace by the updates again
+            __atomic_store_n(h->progress, (uint32_t)h->host_state->k, __ATOMIC_RELEASE);
+            continue;
+        }
         if (o.graph && it % gch == 0 && it + gch < o.max_iter) {
             rc = graph_chunk();
             if (rc) return rc;
@@ -717,21 +807,7 @@ static int solve_single(gp_handle h, gp_dtype kdtype, const void* K, int64_t n, 
             continue;
         }
         const int end = o.graph ? std::min(o.max_iter, (it / gch + 1) * gch) : std::min(o.max_iter, it + o.chunk);
-        for (; it < end; ++it) {
-            launch_proj(s, st, PM_ITER, p, x, g, nullptr, upart, P.GU, vb, d32);
-            // every profile-th iteration's fused launch is bracketed by events
-            if (o.profile > 0 && it % o.profile == 0) {
-                FusedArgs fa = fa_iter;
-                fa.ev0 = prof_event(h);
-                fa.ev1 = fa.ev0 ? prof_event(h) : nullptr;
-                if (fa.ev0 && !fa.ev1) { --h->ev_used; fa.ev0 = nullptr; }   // keep the pairs aligned
-                launch_fused(kdtype, P.cfg, aligned, s, P.G, fa);
-            } else {
-                launch_fused(kdtype, P.cfg, aligned, s, P.G, fa_iter);
-            }
-            launch_update(kdtype, s, st, UM_ITER, spart, (int)P.G, wpart, P.ldw, p, n, x, g, r, q, upart);
-            if (o.refresh_every > 0 && (it + 1) % o.refresh_every == 0 && it + 1 < o.max_iter) refresh();
-        }
+        for (; it < end; ++it) enqueue_iteration(it);
         e = hipGetLastError();
         if (e != hipSuccess) return hip_fail(h, e, "iteration launch");
         if ((rc = poll(it >= o.max_iter))) return rc;

@@ -15,6 +15,8 @@ struct gp_handle_s {
     void* ws = nullptr;                  // device workspace, grows on demand
     size_t ws_bytes = 0;
     gpl1::GPState* host_state = nullptr; // pinned copy of a state for status reads
+    uint32_t* progress = nullptr;        // host-mapped word the update kernel posts its progress to
+    uint32_t* progress_dev = nullptr;    // its device address
     void* extra = nullptr;               // batched-solver resources
     std::vector<hipEvent_t> events;      // profiling: start/stop pairs of fused launches
     int ev_used = 0;

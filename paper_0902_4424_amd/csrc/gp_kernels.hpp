@@ -859,6 +859,16 @@ __global__ __launch_bounds__(T) void k_fused(const GPState* __restrict__ st, con
 }
 
 // ---------------------------------------------------------------------------
+// The update kernel's progress report to the host (when the solve has a
+// host-mapped word): updates completed, bit 31 once a stop is requested.  A
+// system-scope store, so the host sees it without a synchronisation; the word
+// only paces how far ahead the host enqueues, the state stays authoritative.
+__device__ __forceinline__ void post_progress(const GPParams& P, int32_t k, bool stop) {
+    if (P.progress)
+        __hip_atomic_store(P.progress, (uint32_t)k | (stop ? 0x80000000u : 0u), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
 // k_update: line search and vector updates (see file comment).
 // Grid: nbp workgroups over columns (UPD_COLS each), then workgroups over rows.
 // ---------------------------------------------------------------------------
@@ -934,6 +944,7 @@ __global__ __launch_bounds__(UPD_T) void k_update(GPState* __restrict__ st, int 
             st->dmax = dmax;
             st->status = ST_STATIONARY;
             st->stop_req = 1;
+            post_progress(S.prm, S.k, true);
         }
         return;
     }
@@ -957,7 +968,11 @@ __global__ __launch_bounds__(UPD_T) void k_update(GPState* __restrict__ st, int 
             lam *= P.theta;
         }
         if (fail) {
-            if (blockIdx.x == 0 && tid == 0) { st->status = ST_BACKTRACK; st->stop_req = 1; }
+            if (blockIdx.x == 0 && tid == 0) {
+                st->status = ST_BACKTRACK;
+                st->stop_req = 1;
+                post_progress(S.prm, S.k, true);
+            }
             return;
         }
     }
@@ -1055,10 +1070,14 @@ __global__ __launch_bounds__(UPD_T) void k_update(GPState* __restrict__ st, int 
             st->ss_pending = 1;
             const double rel = (f - fn) / f;
             st->rel = rel;
-            if (!isfinite(fn)) { st->status = ST_NONFINITE; st->stop_req = 1; }
-            else if (P.f_target >= 0.0 && fn <= P.f_target) { st->status = ST_TARGET; st->stop_req = 1; }
-            else if (P.tol > 0.0 && rel < P.tol) { st->status = ST_OK_TOL; st->stop_req = 1; }
-            else if (S.k + 1 >= P.max_iter) { st->status = ST_MAX_ITER; st->stop_req = 1; }
+            bool stop = true;
+            if (!isfinite(fn)) st->status = ST_NONFINITE;
+            else if (P.f_target >= 0.0 && fn <= P.f_target) st->status = ST_TARGET;
+            else if (P.tol > 0.0 && rel < P.tol) st->status = ST_OK_TOL;
+            else if (S.k + 1 >= P.max_iter) st->status = ST_MAX_ITER;
+            else stop = false;
+            if (stop) st->stop_req = 1;
+            post_progress(P, S.k + 1, stop);
         } else {
             st->f_new = qq;              // sum of t_i^2 = ||K x - y||^2
             if (!S.pending) st->k_new = S.k;

@@ -32,6 +32,9 @@ struct GPParams {
     double theta, beta, amin, amax, tau1, f_target, tol, rho;
     int32_t M, Malpha, max_iter, bt_cap;
     int32_t x0_fallback;       // start from 0 when f(P(x0)) >= f(0) = ||y||^2
+    // host-mapped word the update kernel posts its progress to (updates
+    // completed, bit 31 once a stop is requested), or NULL
+    uint32_t* progress;
 };
 
 struct GPState {

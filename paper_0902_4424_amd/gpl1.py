@@ -41,7 +41,8 @@ class GPOpts(C.Structure):
                 ("x0_fallback", C.c_int32), ("graph", C.c_int32),
                 ("batch_splitk", C.c_int32), ("batch_rows_t", C.c_int32),
                 ("batch_cols_t", C.c_int32), ("var_item_rows", C.c_int32),
-                ("batch_gemm_depth", C.c_int32), ("batch_gemm_tile", C.c_int32)]
+                ("batch_gemm_depth", C.c_int32), ("batch_gemm_tile", C.c_int32),
+                ("lookahead", C.c_int32)]
 
 
 class GPResult(C.Structure):

@@ -45,7 +45,7 @@ int main(void) {
   printf("%zu %zu %zu %zu %zu %zu %zu %zu\n", offsetof(gp_opts, theta), offsetof(gp_opts, M_alpha),
          offsetof(gp_opts, f_target), offsetof(gp_opts, chunk), offsetof(gp_opts, fused_grid),
          offsetof(gp_opts, f_targets), offsetof(gp_opts, x0_fallback), offsetof(gp_result, x0_rejected));
-  printf("%zu %zu\n", offsetof(gp_opts, graph), offsetof(gp_result, reopened));
+  printf("%zu %zu %zu\n", offsetof(gp_opts, graph), offsetof(gp_result, reopened), offsetof(gp_opts, lookahead));
   printf("%zu %zu %zu\n", offsetof(gp_result, f), offsetof(gp_result, lambda_est),
          offsetof(gp_result, l1norm));
   printf("%zu %zu\n", offsetof(gp_instance, n), offsetof(gp_instance, rho));
@@ -60,7 +60,7 @@ int main(void) {
     want = [C.sizeof(O), C.sizeof(R), C.sizeof(I),
             O.theta.offset, O.M_alpha.offset, O.f_target.offset, O.chunk.offset,
             O.fused_grid.offset, O.f_targets.offset, O.x0_fallback.offset, R.x0_rejected.offset, O.graph.offset,
-            R.reopened.offset, R.f.offset, R.lambda_est.offset, R.l1norm.offset,
+            R.reopened.offset, O.lookahead.offset, R.f.offset, R.lambda_est.offset, R.l1norm.offset,
             I.n.offset, I.rho.offset]
     assert vals == want
 
@@ -73,6 +73,7 @@ def test_defaults_are_the_papers_gpss_parameters():
         (1, 0.5, 1e-4, 1e-10, 1e10, 0.5, 2)
     assert o.backtrack_cap == 60 and o.f_target < 0 and o.refresh_every == 0
     assert not o.f_targets and o.fused_interleave == 0 and o.x0_fallback == 0 and o.graph == 0
+    assert o.chunk == 64 and o.lookahead == 2
     with pytest.raises(TypeError):
         gpl1.default_opts(no_such_option=1)
 

@@ -467,3 +467,44 @@ def test_graph_mode_matches_plain(H):
     with pytest.raises(gpl1.GPError) as e:
         H.solve(Ka, ya, a.rho, graph=1, profile=4)
     assert e.value.code == -1
+
+
+def test_lookahead_matches_chunked_polls(H):
+    """Pacing the launches by the progress word the update kernel posts
+    (lookahead k) changes only when the host enqueues: every stop kind (the
+    tolerance, the budget, stationarity, an objective target checked in
+    double) gives the bits of the chunked polls, for several k, through both
+    entry points, with profiling and refreshes, and an invalid k is refused."""
+    say("[solve] lookahead pacing vs chunked polls")
+    a = instances.gaussian_instance(512, 2048, 20, dtype="f32", seed=5)
+    b = instances.gaussian_instance(300, 1100, 9, dtype="f64", seed=6)
+    Ka, ya = _K_tensor(a), _dev(a.y_store)
+    Kb, yb = _K_tensor(b), _dev(b.y_store)
+    xs, rs = H.solve(Ka, ya, a.rho, tol=0.0, max_iter=3000, lookahead=0)
+    target = rs["f"] * (1 + 1e-7)
+    cases = [
+        (Ka, ya, a.rho, dict(tol=0.0, max_iter=300)),
+        (Ka, ya, a.rho, dict(tol=0.0, max_iter=203, refresh_every=25, profile=4)),
+        (Kb, yb, b.rho, dict(tol=1e-12, max_iter=5000)),
+        (Ka, ya, a.rho, dict(tol=1e-9, max_iter=100000)),
+        (Ka, ya, a.rho, dict(tol=0.0, max_iter=5000, refresh_every=50, f_target=target)),
+        (Ka, ya, a.rho, dict(tol=0.0, max_iter=1)),
+        (Ka, ya, a.rho, dict(tol=0.0, max_iter=0)),
+    ]
+    timing = ("t_fused_ms",)
+    for i, (K, y, rho, kw) in enumerate(cases):
+        x0, r0 = H.solve(K, y, rho, lookahead=0, **kw)
+        x1, r1 = H.solve(K, y, rho, lookahead=0, chunk=1, **kw)
+        assert torch.equal(x1, x0)
+        for la in (1, 2, 5):
+            # (the allocation-free entry point takes no profiling)
+            for fn in (H.solve,) if "profile" in kw else (H.solve, H.solve_noalloc):
+                x, r = fn(K, y, rho, lookahead=la, **kw)
+                torch.cuda.synchronize()
+                assert torch.equal(x, x0), (i, la)
+                assert {k: v for k, v in r.items() if k not in timing} == \
+                    {k: v for k, v in r0.items() if k not in timing}, (i, la, r, r0)
+        say(f"   case {i}: {r0['iters']} iterations, {r0['status_name']}, reopened {r0['reopened']}")
+    with pytest.raises(gpl1.GPError) as e:
+        H.solve(Ka, ya, a.rho, lookahead=-1)
+    assert e.value.code == -1
