@@ -94,6 +94,25 @@ int ensure_workspace(gp_handle h, size_t bytes) {
     return GP_OK_TOL;
 }
 
+int ensure_pinned(gp_handle h, size_t bytes) {
+    if (bytes <= h->pin_bytes) return GP_OK_TOL;
+    if (h->pin) {
+        hipError_t e = hipHostFree(h->pin);
+        h->pin = nullptr;
+        h->pin_bytes = 0;
+        if (e != hipSuccess) return hip_fail(h, e, "hipHostFree(pinned buffer)");
+    }
+    const size_t want = std::max(bytes, (size_t)1 << 16);
+    hipError_t e = hipHostMalloc(&h->pin, want, hipHostMallocDefault);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        h->pin = nullptr;
+        return fail(h, GP_E_NOMEM, "pinned host allocation of " + std::to_string(want) + " bytes failed");
+    }
+    h->pin_bytes = want;
+    return GP_OK_TOL;
+}
+
 int graph_stream(gp_handle h, hipStream_t user, hipStream_t* out) {
     *out = user;
     if (user) return GP_OK_TOL;
@@ -474,6 +493,7 @@ int gp_destroy(gp_handle h) {
     if (h->ws) (void)hipFree(h->ws);
     if (h->host_state) (void)hipHostFree(h->host_state);
     if (h->progress) (void)hipHostFree(h->progress);
+    if (h->pin) (void)hipHostFree(h->pin);
     for (hipEvent_t ev : h->events) (void)hipEventDestroy(ev);
     if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
     if (h->gexec_b) (void)hipGraphExecDestroy(h->gexec_b);

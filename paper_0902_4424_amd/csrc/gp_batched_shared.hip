@@ -867,7 +867,12 @@ int solve_batched_shared_mfma(gp_handle h, gp_dtype kdtype, const void* K, int64
                                (const double*)P.X, dcand, nc, jchunk, dcheck);
         hipLaunchKernelGGL(k_bs_check_decide, dim3((unsigned)nc), dim3(256), 0, s, P, dcheck, ns, nc, dcand, dkout);
     };
-    std::vector<int32_t> hdone((size_t)B), hlist((size_t)bpad), hcand, hk;
+    // status flags and the active list go through the handle's pinned buffer,
+    // so the copies are plain DMA and the list upload needs no wait of its own
+    if ((rc = ensure_pinned(h, 4 * (size_t)(B + bpad)))) return rc;
+    int32_t* hdone = (int32_t*)h->pin;
+    int32_t* hlist = hdone + B;
+    std::vector<int32_t> hcand, hk;
     // a problem that is never stopped has done exactly `it` iterations; one
     // reopened by a target check at iteration k needs max_iter - k more
     int it = 0, it_cap = o.max_iter;
@@ -910,7 +915,7 @@ int solve_batched_shared_mfma(gp_handle h, gp_dtype kdtype, const void* K, int64
         }
         e = hipGetLastError();
         if (e != hipSuccess) return hip_fail(h, e, "batched iteration launch");
-        e = hipMemcpyAsync(hdone.data(), P.done, 4 * B, hipMemcpyDeviceToHost, s);
+        e = hipMemcpyAsync(hdone, P.done, 4 * B, hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         if (e != hipSuccess) return hip_fail(h, e, "batched status poll");
         if (check_target) {
@@ -924,7 +929,7 @@ int solve_batched_shared_mfma(gp_handle h, gp_dtype kdtype, const void* K, int64
                 launch_verify(nc);
                 hk.resize((size_t)nc);
                 e = hipGetLastError();
-                if (e == hipSuccess) e = hipMemcpyAsync(hdone.data(), P.done, 4 * B, hipMemcpyDeviceToHost, s);
+                if (e == hipSuccess) e = hipMemcpyAsync(hdone, P.done, 4 * B, hipMemcpyDeviceToHost, s);
                 if (e == hipSuccess) e = hipMemcpyAsync(hk.data(), dkout, 4 * nc, hipMemcpyDeviceToHost, s);
                 if (e == hipSuccess) e = hipStreamSynchronize(s);
                 if (e != hipSuccess) return hip_fail(h, e, "batched target check");
@@ -956,8 +961,8 @@ int solve_batched_shared_mfma(gp_handle h, gp_dtype kdtype, const void* K, int64
         if (nlive != live) {
             // compact: later launches cover the listed problems only
             for (int64_t k = nlive; k < rup(nlive, GM_BN); ++k) hlist[(size_t)k] = (int32_t)bpad;
-            e = hipMemcpyAsync(dlist, hlist.data(), 4 * rup(nlive, GM_BN), hipMemcpyHostToDevice, s);
-            if (e == hipSuccess) e = hipStreamSynchronize(s);   // hlist is reused at the next poll
+            // (hlist is next written after the next poll's synchronisation)
+            e = hipMemcpyAsync(dlist, hlist, 4 * rup(nlive, GM_BN), hipMemcpyHostToDevice, s);
             if (e != hipSuccess) return hip_fail(h, e, "batched active set");
             live = nlive;
             P.list = dlist;

@@ -546,14 +546,16 @@ int solve_batched_var_lockstep(gp_handle h, gp_dtype kdtype, const gp_instance* 
     proj(1, 0);
     e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(h, e, "batched-var init launch");
-    std::vector<GPState> hst((size_t)B);
+    // the states are polled into the handle's pinned buffer (plain DMA)
+    if ((rc = ensure_pinned(h, sizeof(GPState) * (size_t)B))) return rc;
+    GPState* hst = (GPState*)h->pin;
     std::vector<int32_t> hvc;
     std::vector<VerItem> hvi;
     // a problem that is never stopped has done exactly `it` iterations; one
     // reopened by a target check at iteration k needs max_iter - k more
     int it = 0, it_cap = o.max_iter;
     auto read_states = [&]() -> int {
-        hipError_t pe = hipMemcpyAsync(hst.data(), st, sizeof(GPState) * B, hipMemcpyDeviceToHost, s);
+        hipError_t pe = hipMemcpyAsync(hst, st, sizeof(GPState) * B, hipMemcpyDeviceToHost, s);
         if (pe == hipSuccess) pe = hipStreamSynchronize(s);
         return pe == hipSuccess ? 0 : hip_fail(h, pe, "batched-var status poll");
     };
@@ -635,7 +637,7 @@ int solve_batched_var_lockstep(gp_handle h, gp_dtype kdtype, const gp_instance* 
         if (all) break;
     }
     hipLaunchKernelGGL(k_bv_finish, dim3((unsigned)B), dim3(BV_T), 0, s, dI, st, f64v ? 1 : 0);
-    e = hipMemcpyAsync(hst.data(), st, sizeof(GPState) * B, hipMemcpyDeviceToHost, s);
+    e = hipMemcpyAsync(hst, st, sizeof(GPState) * B, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(h, e, "batched-var final sync");
     int worst = GP_OK_TOL;

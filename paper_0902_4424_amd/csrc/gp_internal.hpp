@@ -17,6 +17,8 @@ struct gp_handle_s {
     gpl1::GPState* host_state = nullptr; // pinned copy of a state for status reads
     uint32_t* progress = nullptr;        // host-mapped word the update kernel posts its progress to
     uint32_t* progress_dev = nullptr;    // its device address
+    void* pin = nullptr;                 // pinned host buffer of the batched status polls, grows on demand
+    size_t pin_bytes = 0;
     void* extra = nullptr;               // batched-solver resources
     std::vector<hipEvent_t> events;      // profiling: start/stop pairs of fused launches
     int ev_used = 0;
@@ -70,6 +72,7 @@ int capture_graph(gp_handle h, hipStream_t s, hipGraphExec_t* exec, const std::f
 int fail(gp_handle h, int code, const std::string& msg);
 int hip_fail(gp_handle h, hipError_t e, const char* where);
 int ensure_workspace(gp_handle h, size_t bytes);
+int ensure_pinned(gp_handle h, size_t bytes);
 void fill_result(const GPState& s, gp_result* res);
 void destroy_extra(gp_handle h);
 const char* status_name(int s);
