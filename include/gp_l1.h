@@ -112,8 +112,11 @@ typedef struct {
     int32_t var_item_rows;    /* uneven batches: rows of K per work item of the fused pass, 16..1024
                                  (64 when 0) */
     int32_t batch_gemm_depth; /* shared bf16 K: k-steps of GEMM loads in flight, 1 or 2 (1 when 0) */
-    int32_t batch_gemm_tile;  /* shared bf16 K: rows of the GEMM output tile, 128 or 256 (128 when 0;
-                                 256 takes one k-step in flight and about half the reduction chunk) */
+    int32_t batch_gemm_tile;  /* shared bf16 K: the GEMM output tile, 128 x 128 (0 or 128), 256 x 128
+                                 (256: one k-step in flight, about half the reduction chunk) or
+                                 128 x 64 (64); whatever is set, 128 x 64 once at most 128 problems
+                                 run.  Every tile gives the same bits at the same reduction chunk;
+                                 batch_gemm_depth = 2 goes with 128 x 128 only (GP_E_ARG). */
     int32_t lookahead;        /* gp_l1_solve without graph: k > 0 = keep at most k iterations enqueued
                                  ahead of the device, which posts every completed update to a
                                  host-mapped word of the handle, and poll the state only once a stop

@@ -209,11 +209,11 @@ int check_opts(gp_handle h, const gp_opts& o) {
         return fail(h, GP_E_ARG, "opts.var_item_rows must be 0 or in 16..1024");
     if (o.batch_gemm_depth < 0 || o.batch_gemm_depth > 2)
         return fail(h, GP_E_ARG, "opts.batch_gemm_depth must be 0, 1 or 2");
-    if (o.batch_gemm_tile != 0 && o.batch_gemm_tile != 128 && o.batch_gemm_tile != 256)
-        return fail(h, GP_E_ARG, "opts.batch_gemm_tile must be 0, 128 or 256");
+    if (o.batch_gemm_tile != 0 && o.batch_gemm_tile != 64 && o.batch_gemm_tile != 128 && o.batch_gemm_tile != 256)
+        return fail(h, GP_E_ARG, "opts.batch_gemm_tile must be 0, 64, 128 or 256");
     if (o.lookahead < 0) return fail(h, GP_E_ARG, "opts.lookahead must be >= 0");
-    if (o.batch_gemm_tile == 256 && o.batch_gemm_depth == 2)
-        return fail(h, GP_E_ARG, "opts.batch_gemm_depth = 2 is for 128-row GEMM tiles");
+    if ((o.batch_gemm_tile == 256 || o.batch_gemm_tile == 64) && o.batch_gemm_depth == 2)
+        return fail(h, GP_E_ARG, "opts.batch_gemm_depth = 2 is for 128 x 128 GEMM tiles");
     return GP_OK_TOL;
 }
 

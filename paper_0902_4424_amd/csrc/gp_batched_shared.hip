@@ -820,7 +820,12 @@ int solve_batched_shared_mfma(gp_handle h, gp_dtype kdtype, const void* K, int64
     auto gemm_planes = [&](const uint16_t* A0, int64_t lda, int64_t M, const uint16_t* Bpl, int64_t ldb,
                            int64_t plB, int S, int64_t kc, float* Cp, int64_t ldc, int64_t cs) {
         const dim3 grid((unsigned)(M / GM_BM), (unsigned)(rup(live, GM_BN) / GM_BN), (unsigned)S);
-        if (tile256)
+        if (nK == 1 && (grid.y == 1 || o.batch_gemm_tile == 64))
+            // 64-column tiles (same bits): always when asked, else once one
+            // 128-column tile is left, where they keep the chip busy
+            hipLaunchKernelGGL(k_gemm_bf16_n64<NSPL>, dim3(grid.x, grid.y * (unsigned)(GM_BN / GM3_BN), grid.z),
+                               dim3(GM_T), 0, s, A0, lda, Bpl, ldb, plB, (int)kc, Cp, ldc, cs, P.list);
+        else if (tile256)
             hipLaunchKernelGGL(k_gemm_bf16_m256<NSPL>, dim3((unsigned)((M + GM2_BM - 1) / GM2_BM), grid.y, grid.z),
                                dim3(GM2_T), 0, s, A0, lda, Bpl, ldb, plB, (int)kc, Cp, ldc, cs, P.list, M);
         else if (nK == 1 && o.batch_gemm_depth == 2)

@@ -534,4 +534,105 @@ __global__ __launch_bounds__(GM2_T) void k_gemm_bf16_m256(const uint16_t* __rest
 #undef GPL1_M2_ST
 }
 
+// k_gemm_bf16 with 64-column tiles, for a right operand of at most one
+// 128-column tile (the last problems of a batch): twice the workgroups, each
+// with half the work, where the 128-column grid would leave half the chip
+// idle.  Four waves of 64 x 32 sub-tiles (4 x 2 MFMA blocks); every output
+// element sees the same MFMAs in the same order as in k_gemm_bf16 (k-steps in
+// turn, planes in turn within a step), so the results are bitwise those of
+// k_gemm_bf16 for the same kchunk.  Same arguments; N (the column list) is
+// padded to 64.
+constexpr int GM3_BN = 64;
+template <int NSPLIT>
+__global__ __launch_bounds__(GM_T) void k_gemm_bf16_n64(const uint16_t* __restrict__ A, int64_t lda,
+                                                        const uint16_t* __restrict__ Bp, int64_t ldb,
+                                                        int64_t pstride, int kchunk,
+                                                        float* __restrict__ Cpart, int64_t ldc,
+                                                        int64_t cstride, const int32_t* __restrict__ nmap) {
+    static_assert(NSPLIT >= 1 && NSPLIT <= 3, "one to three bf16 planes");
+    constexpr int TA = GM_BM * GM_LDS_ROW, TB = GM3_BN * GM_LDS_ROW;
+    __shared__ __attribute__((aligned(16))) uint16_t lds[2][TA + NSPLIT * TB];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave & 1, wn = wave >> 1;
+    const int64_t m0 = (int64_t)blockIdx.x * GM_BM;
+    const int64_t n0 = (int64_t)blockIdx.y * GM3_BN;
+    const int64_t k_begin = (int64_t)blockIdx.z * kchunk;
+    const int nsteps = kchunk / GM_BK;
+    // staging: the A tile is 128 rows x 4 chunks of 8 (two per thread), each
+    // B plane 64 rows x 4 chunks (one per thread)
+    const int rowA0 = tid >> 2, rowA1 = (tid + GM_T) >> 2, kc_ = (tid & 3) * 8;
+    const int rowB = tid >> 2;
+    const uint16_t* a0p = A + (m0 + rowA0) * lda + k_begin + kc_;
+    const uint16_t* a1p = A + (m0 + rowA1) * lda + k_begin + kc_;
+    const int64_t bn = nmap ? nmap[n0 + rowB] : n0 + rowB;
+    const uint16_t* bp = Bp + bn * ldb + k_begin + kc_;
+    uint4 ra0, ra1, rb0, rb1, rb2;
+#define GPL1_N3_LD(p_, off_) (*reinterpret_cast<const uint4*>((p_) + (off_)))
+#define GPL1_N3_GLOAD(step_)                                                    \
+    {                                                                           \
+        const int64_t ko_ = (int64_t)(step_) * GM_BK;                           \
+        ra0 = GPL1_N3_LD(a0p, ko_);                                             \
+        ra1 = GPL1_N3_LD(a1p, ko_);                                             \
+        rb0 = GPL1_N3_LD(bp, ko_);                                              \
+        if constexpr (NSPLIT > 1) rb1 = GPL1_N3_LD(bp, pstride + ko_);          \
+        if constexpr (NSPLIT > 2) rb2 = GPL1_N3_LD(bp, 2 * pstride + ko_);      \
+    }
+#define GPL1_N3_ST(buf_, off_, v_) (*reinterpret_cast<uint4*>(&lds[buf_][(off_)]) = (v_))
+#define GPL1_N3_LSTORE(buf_)                                                    \
+    {                                                                           \
+        GPL1_N3_ST(buf_, rowA0 * GM_LDS_ROW + kc_, ra0);                        \
+        GPL1_N3_ST(buf_, rowA1 * GM_LDS_ROW + kc_, ra1);                        \
+        GPL1_N3_ST(buf_, TA + rowB * GM_LDS_ROW + kc_, rb0);                    \
+        if constexpr (NSPLIT > 1) GPL1_N3_ST(buf_, TA + TB + rowB * GM_LDS_ROW + kc_, rb1);       \
+        if constexpr (NSPLIT > 2) GPL1_N3_ST(buf_, TA + 2 * TB + rowB * GM_LDS_ROW + kc_, rb2);   \
+    }
+    f32x4_t acc[4][2];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+    GPL1_N3_GLOAD(0)
+    GPL1_N3_LSTORE(0)
+    __syncthreads();
+    const int fr = lane & 15, fk = (lane >> 4) * 8;
+    for (int step = 0; step < nsteps; ++step) {
+        const int cur = step & 1;
+        if (step + 1 < nsteps) GPL1_N3_GLOAD(step + 1)
+        bf16x8_t af[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            af[i] = *reinterpret_cast<const bf16x8_t*>(&lds[cur][(wm * 64 + i * 16 + fr) * GM_LDS_ROW + fk]);
+#pragma unroll
+        for (int t = 0; t < NSPLIT; ++t) {
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const bf16x8_t bfr = *reinterpret_cast<const bf16x8_t*>(
+                    &lds[cur][TA + t * TB + (wn * 32 + j * 16 + fr) * GM_LDS_ROW + fk]);
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr, acc[i][j], 0, 0, 0);
+            }
+        }
+        if (step + 1 < nsteps) {
+            GPL1_N3_LSTORE(cur ^ 1)
+            __syncthreads();
+        }
+    }
+    float* out = Cpart + (int64_t)blockIdx.z * cstride;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int64_t m = m0 + wm * 64 + i * 16 + (lane >> 4) * 4;
+            const int64_t nl = n0 + wn * 32 + j * 16 + (lane & 15);
+            const int64_t nn = nmap ? nmap[nl] : nl;
+            *reinterpret_cast<float4*>(out + nn * ldc + m) =
+                make_float4(acc[i][j][0], acc[i][j][1], acc[i][j][2], acc[i][j][3]);
+        }
+#undef GPL1_N3_GLOAD
+#undef GPL1_N3_LSTORE
+#undef GPL1_N3_LD
+#undef GPL1_N3_ST
+}
+
 }  // namespace gpl1

@@ -160,7 +160,7 @@ def tune_shared(H, dtype, n, p, B, reps=3, log=print):
         log(f"  {shared_key(dtype, n, p, B)} {kw or 'automatic'}: {min(ts) * 1e3:.3f} ms")
         return min(ts)
 
-    space = {"batch_gemm_tile": (256,) if dtype == "bf16" else (), "batch_splitk": (256, 512, 1024, 2048),
+    space = {"batch_gemm_tile": (256, 64) if dtype == "bf16" else (), "batch_splitk": (256, 512, 1024, 2048),
              "batch_rows_t": (512, 1024), "batch_cols_t": (256, 512, 1024),
              "batch_gemm_depth": (2,) if dtype == "bf16" else (), "graph": (1,)}
     best, t = _coordinate_search(space, run, log)

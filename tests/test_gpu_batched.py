@@ -498,30 +498,30 @@ def test_batched_tuning_options(H):
         say(f"[tuning] shared {kw}")
         X, res = H.solve_batched_shared(Kt, Y, batch.rho, **base, **kw)
         _check_columns(batch, X, res, range(5))
-    # loads two k-steps ahead: the same products in the same order, so the
-    # same bits; chunks of 1, 2 and 3 k-steps (split-K 32 and 96) cover the
-    # loop's odd and early exits
-    for sk in (0, 96, 32):
-        say(f"[tuning] shared GEMM depth 2, split-K {sk}")
-        X1, r1 = H.solve_batched_shared(Kt, Y, batch.rho, batch_splitk=sk, batch_gemm_depth=1, **base)
-        X2, r2 = H.solve_batched_shared(Kt, Y, batch.rho, batch_splitk=sk, batch_gemm_depth=2, **base)
-        assert torch.equal(X1, X2) and r1 == r2
-    _check_columns(batch, X2, r2, range(5))
-    # 256-row GEMM tiles: each wave's sub-tile products in the same order, so
-    # the same bits for the same split-K chunk; both padded sizes (384 and
-    # 2176 rows) end in half a tile
-    for sk in (512, 96, 32):
-        say(f"[tuning] shared GEMM tile 256, split-K {sk}")
-        X1, r1 = H.solve_batched_shared(Kt, Y, batch.rho, batch_splitk=sk, batch_gemm_tile=128, **base)
-        X3, r3 = H.solve_batched_shared(Kt, Y, batch.rho, batch_splitk=sk, batch_gemm_tile=256, **base)
-        assert torch.equal(X1, X3) and r1 == r3
-    _check_columns(batch, X3, r3, range(5))
+    # GEMM variants on a batch of 150 right-hand sides, so that the launches
+    # span two 128-column tiles until problems finish: loads two k-steps
+    # ahead, 256 x 128 and 128 x 64 tiles take the same products in the same
+    # order as the 128 x 128 tile, so the same bits (and 128 x 64 tiles, used
+    # by all of them once at most 128 problems run, too); chunks of 1, 2 and 3
+    # k-steps (split-K 32 and 96) cover the loop's odd and early exits; both
+    # padded sizes (384 and 2176 rows) end in half a 256-row tile
+    wide = instances.shared_batch(300, 2100, 150, 15, dtype="bf16", seed=86, rhs_seed_base=860)
+    Kw = _kt(wide)
+    Yw = torch.from_numpy(wide.Y_store).to(DEV)
+    for sk in (512, 96, 32):   # explicit chunks: the automatic one differs with the tile
+        say(f"[tuning] shared GEMM variants, split-K {sk}")
+        X1, r1 = H.solve_batched_shared(Kw, Yw, wide.rho, batch_splitk=sk, **base)
+        for kw in (dict(batch_gemm_depth=2), dict(batch_gemm_tile=256), dict(batch_gemm_tile=64)):
+            X2, r2 = H.solve_batched_shared(Kw, Yw, wide.rho, batch_splitk=sk, **base, **kw)
+            assert torch.equal(X1, X2) and r1 == r2, (sk, kw)
+    _check_columns(wide, X2, r2, (0, 77, 149))
     # p = 2100 needs 16 slots at 256 threads: not a compiled shape
     with pytest.raises(gpl1.GPError) as e:
         H.solve_batched_shared(Kt, Y, batch.rho, batch_cols_t=256, **base)
     assert e.value.code == -1
     for bad in (dict(batch_splitk=100), dict(batch_rows_t=300), dict(var_item_rows=8), dict(batch_gemm_depth=3),
-                dict(batch_gemm_tile=100), dict(batch_gemm_tile=256, batch_gemm_depth=2)):
+                dict(batch_gemm_tile=100), dict(batch_gemm_tile=256, batch_gemm_depth=2),
+                dict(batch_gemm_tile=64, batch_gemm_depth=2)):
         with pytest.raises(gpl1.GPError):
             H.solve_batched_shared(Kt, Y, batch.rho, **base, **bad)
     rng = np.random.default_rng(85)
