@@ -319,10 +319,8 @@ __global__ __launch_bounds__(T) void k_proj(GPState* __restrict__ st, int mode, 
     // are read after the steplength rule).  g is not read in the modes that
     // have none.
     constexpr bool PREF = VPT > 0 && VPT <= 32 && VPT * T <= 16384;
-    // x parked per thread in LDS (slot e of thread tid at e*T + tid) while
-    // the steplength rule runs, so that its registers are free for the rule,
-    // and kept there for the float copy of d at the end instead of a second
-    // read from memory
+    // x kept per thread in LDS (slot e of thread tid at e*T + tid) for the
+    // float copy of d at the end, instead of a second read from memory
     __shared__ double xkeep[PREF ? NV * T : 1];
     const bool use_g = mode == PM_ITER || mode == PM_ALPHA0;
     const bool keep_x = PREF && d32 != nullptr;
@@ -349,8 +347,10 @@ __global__ __launch_bounds__(T) void k_proj(GPState* __restrict__ st, int mode, 
                 if (NV > 1) { vr[e + 1] = 0.0; gr[PREF ? e + 1 : 0] = 0.0; }
             }
         }
+        if (keep_x) {
 #pragma unroll
-        for (int e = 0; e < NV; ++e) xkeep[PREF ? e * T + tid : 0] = vr[e];
+            for (int e = 0; e < NV; ++e) xkeep[PREF ? e * T + tid : 0] = vr[e];
+        }
     }
     state_load(S, st);
     __syncthreads();
@@ -385,10 +385,9 @@ __global__ __launch_bounds__(T) void k_proj(GPState* __restrict__ st, int mode, 
     double Sm_s[1] = {0.0}, Sm_m[1] = {0.0};
     if (VPT > 0) {
         if (PREF) {
+            if (use_g) {
 #pragma unroll
-            for (int e = 0; e < NV; ++e) {
-                const double xe = xkeep[PREF ? e * T + tid : 0];
-                vr[e] = use_g ? fma(-alpha, gr[PREF ? e : 0], xe) : xe;
+                for (int e = 0; e < NV; ++e) vr[e] = fma(-alpha, gr[PREF ? e : 0], vr[e]);
             }
         } else {
 #pragma unroll
