@@ -123,6 +123,10 @@ typedef struct {
                                  is posted (a stop leaves at most about k iterations of launches
                                  that return at once, and no status polls before it); 0 = `chunk`
                                  iterations between status polls.  Results are identical. */
+    int32_t var_wave_rows;    /* uneven batches with float or bf16 K: 0 or 1 = items of problems with
+                                 p <= 1024 run the fused pass one row per wave (dots reduced within
+                                 the wave, no barrier per row); -1 = the workgroup-wide pass for
+                                 every item.  The two round differently (both FP32-level). */
 } gp_opts;
 
 typedef struct {

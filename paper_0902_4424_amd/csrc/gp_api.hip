@@ -205,6 +205,7 @@ int check_opts(gp_handle h, const gp_opts& o) {
     for (int t : {o.batch_rows_t, o.batch_cols_t})
         if (t != 0 && t != 256 && t != 512 && t != 1024)
             return fail(h, GP_E_ARG, "opts.batch_rows_t and batch_cols_t must be 0, 256, 512 or 1024");
+    if (o.var_wave_rows < -1 || o.var_wave_rows > 1) return fail(h, GP_E_ARG, "opts.var_wave_rows must be -1, 0 or 1");
     if (o.var_item_rows != 0 && (o.var_item_rows < 16 || o.var_item_rows > 1024))
         return fail(h, GP_E_ARG, "opts.var_item_rows must be 0 or in 16..1024");
     if (o.batch_gemm_depth < 0 || o.batch_gemm_depth > 2)
@@ -451,6 +452,7 @@ void gp_opts_default(gp_opts* o) {
     o->batch_gemm_depth = 0;
     o->batch_gemm_tile = 0;
     o->lookahead = 2;
+    o->var_wave_rows = 0;
 }
 
 int gp_create(gp_handle* out, int device) {

@@ -52,6 +52,8 @@ struct VarInst {
     int32_t aligned;                 // rows 16-byte aligned
     int32_t aligned8;                // rows 8-byte aligned (bf16: read as 4-element chunks)
     int32_t item_rows;               // rows of K per work item
+    int32_t waves;                   // 1: the wave-per-row fused pass (narrow float or bf16 problems)
+    int64_t nparts;                  // partial vectors and dots: nitems, or BV_NW per item with `waves`
 };
 
 struct VarItem { int32_t inst, slab; };
@@ -129,15 +131,131 @@ __device__ __forceinline__ void bv_item(const VarItem& it, const VarInst& D, int
                                                           D.nitems);
 }
 
+// Work item of a narrow problem, whose rows fit CW chunks of one wave (at most
+// BV_NARROW columns): each wave takes every fourth row of the item and
+// reduces its row dots within the wave, so no row waits for a barrier (in the
+// workgroup-wide pass a row of a few KB spends most of its time in the
+// cross-wave reduction), and each wave leaves a partial vector and partial
+// dots of its own (partial row 4 * slab + wave), which the update kernel adds
+// with the others in index order.  Same outputs otherwise as bv_item: t_i =
+// K_i v (minus y_i on a refresh) for the item's rows.
+constexpr int BV_NW = BV_FT / WAVE;
+constexpr int BV_NARROW = 1024;   // widest p of the wave-per-row pass
+template <typename TK, int CW, bool ALIGNED>
+__device__ __forceinline__ void bv_item_waves(const VarItem& it, const VarInst& D, int refresh) {
+    constexpr int VEC = KTraits<TK>::VEC;
+    static_assert(CW * WAVE * VEC <= BV_NARROW, "narrow items only");
+    const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
+    const int64_t p = D.p, ldk = D.ldk;
+    const TK* K = (const TK*)D.K;
+    const double* v = refresh ? D.x : D.d;
+    const int64_t r0 = (int64_t)it.slab * D.item_rows;
+    const int64_t r1 = r0 + D.item_rows < D.n ? r0 + D.item_rows : D.n;
+    float dv[CW][VEC], w[CW][VEC];
+#pragma unroll
+    for (int c = 0; c < CW; ++c)
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) {
+            const int64_t j = ((int64_t)c * WAVE + lane) * VEC + e;
+            dv[c][e] = j < p ? (float)v[j] : 0.0f;
+            w[c][e] = 0.0f;
+        }
+    // rows past the item reload its last row (issued unconditionally so the
+    // waits count exactly, never used); y_i (subtracted on a refresh) or r_i
+    // (for t'r in an iteration) comes with each row
+    auto rowc = [&](int64_t r) { return r < r1 ? r : r1 - 1; };
+    const double* yv = refresh ? D.y : D.r;
+    auto load = [&](KVec<TK> (&buf)[CW], double& yr, int64_t row) {
+#pragma unroll
+        for (int c = 0; c < CW; ++c) {
+            const int64_t col = ((int64_t)c * WAVE + lane) * VEC;
+            if (col < p) load_kvec<TK, ALIGNED>(K + row * ldk, col, p, buf[c]);
+            else buf[c].clear();
+        }
+        yr = yv[row];
+    };
+    double tt = 0.0, tr = 0.0;
+    auto proc = [&](const KVec<TK> (&buf)[CW], double yr, int64_t row) {
+        float sdot = 0.0f;
+#pragma unroll
+        for (int c = 0; c < CW; ++c)
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) sdot += buf[c].get(e) * dv[c][e];
+        const double t = wave_sum((double)sdot) - (refresh ? yr : 0.0);
+        if (lane == 0) {
+            D.q[row] = t;
+            tt += t * t;
+            if (!refresh) tr += t * yr;
+        }
+        const float ta = (float)t;
+#pragma unroll
+        for (int c = 0; c < CW; ++c)
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) w[c][e] += buf[c].get(e) * ta;
+    };
+    KVec<TK> A[CW], B[CW];
+    double ya = 0.0, yb = 0.0;
+    int64_t row = r0 + wv;
+    if (row < r1) {
+        load(A, ya, row);
+        for (; row < r1; row += 2 * BV_NW) {
+            load(B, yb, rowc(row + BV_NW));
+            proc(A, ya, row);
+            if (row + BV_NW >= r1) break;
+            load(A, ya, rowc(row + 2 * BV_NW));
+            proc(B, yb, row + BV_NW);
+        }
+    }
+    const int64_t part = (int64_t)it.slab * BV_NW + wv;
+    float* wrow = D.wpart + part * D.ldw;
+#pragma unroll
+    for (int c = 0; c < CW; ++c)
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) {
+            const int64_t j = ((int64_t)c * WAVE + lane) * VEC + e;
+            if (j < D.ldw) wrow[j] = w[c][e];
+        }
+    if (lane == 0) {
+        double* sp = D.spart + SPART * part;
+        sp[0] = tt;
+        sp[1] = tr;
+        sp[2] = 0.0;
+        sp[3] = 0.0;
+        sp[4] = 0.0;
+    }
+}
+
+// the wave-per-row item with the fewest chunks that cover p
+template <typename TK>
+__device__ __forceinline__ void bv_item_narrow(const VarItem& it, const VarInst& D, int refresh) {
+    constexpr int VEC = KTraits<TK>::VEC;
+    const int64_t p = D.p;
+    if (p <= WAVE * VEC) bv_item_waves<TK, 1, true>(it, D, refresh);
+    else if (p <= 2 * WAVE * VEC) bv_item_waves<TK, 2, true>(it, D, refresh);
+    else if constexpr (VEC == 4) bv_item_waves<TK, 4, true>(it, D, refresh);
+}
+
 // CPT column chunks per thread cover the widest problem of the batch; an
 // item of a narrower problem runs with the fewest chunks that cover its own p
-// (the chunks past p hold zeros either way, so the sums are the same)
-template <typename TK, typename ACC, int CPT>
+// (the chunks past p hold zeros either way, so the sums are the same).  WAVES:
+// compiled with the wave-per-row pass for the problems marked `waves` (it
+// needs more registers than the one-chunk workgroup pass, so a batch whose
+// widest problem needs one chunk uses it only if every problem is narrow)
+template <typename TK, typename ACC, int CPT, bool WAVES>
 __global__ __launch_bounds__(BV_FT) void k_bv_fused(const VarInst* __restrict__ I, const VarItem* __restrict__ items,
                                                     const GPState* __restrict__ st, int refresh) {
     const VarItem it = items[blockIdx.x];
     if (st[it.inst].done) return;
     const VarInst D = I[it.inst];
+    if constexpr (WAVES && sizeof(ACC) == 4) {
+        if (D.waves) {
+            if constexpr (std::is_same<TK, bf16_t>::value) {
+                if (!D.aligned) { bv_item_narrow<bf16x4_t>(it, D, refresh); return; }
+            }
+            bv_item_narrow<TK>(it, D, refresh);
+            return;
+        }
+    }
     constexpr int64_t COLS1 = (int64_t)BV_FT * KTraits<TK>::VEC;   // columns of one chunk per thread
     if constexpr (CPT >= 4) {
         if (D.p <= COLS1) { bv_item<TK, ACC, 1>(it, D, refresh); return; }
@@ -163,7 +281,7 @@ __global__ __launch_bounds__(T) void k_bv_update(const VarInst* __restrict__ I, 
     else wp = (const ACC*)D.wpart;
     // partial dots of the items, fixed order
     double a[2] = {0.0, 0.0}, none[1] = {0.0};
-    for (int64_t i = tid; i < D.nitems; i += T) {
+    for (int64_t i = tid; i < D.nparts; i += T) {
         a[0] += D.spart[SPART * i];
         a[1] += D.spart[SPART * i + 1];
     }
@@ -171,7 +289,7 @@ __global__ __launch_bounds__(T) void k_bv_update(const VarInst* __restrict__ I, 
     const double tt = a[0], tr = a[1];
     auto wsum = [&](int64_t j) {
         double s = 0.0;
-        for (int64_t c = 0; c < D.nitems; ++c) s += (double)wp[c * D.ldw + j];
+        for (int64_t c = 0; c < D.nparts; ++c) s += (double)wp[c * D.ldw + j];
         return s;
     };
     if (refresh) {
@@ -232,7 +350,7 @@ __global__ __launch_bounds__(T) void k_bv_update(const VarInst* __restrict__ I, 
         double w[JU];
 #pragma unroll
         for (int u = 0; u < JU; ++u) w[u] = 0.0;
-        for (int64_t c0 = 0; c0 < D.nitems; c0 += CU) {
+        for (int64_t c0 = 0; c0 < D.nparts; c0 += CU) {
             ACC v[JU][CU];
 #pragma unroll
             for (int u = 0; u < JU; ++u) {
@@ -240,7 +358,7 @@ __global__ __launch_bounds__(T) void k_bv_update(const VarInst* __restrict__ I, 
                 const int64_t jc = j < D.p ? j : 0;
 #pragma unroll
                 for (int cc = 0; cc < CU; ++cc) {
-                    const int64_t c = c0 + cc < D.nitems ? c0 + cc : 0;
+                    const int64_t c = c0 + cc < D.nparts ? c0 + cc : 0;
                     v[u][cc] = wp[c * D.ldw + jc];
                 }
             }
@@ -248,7 +366,7 @@ __global__ __launch_bounds__(T) void k_bv_update(const VarInst* __restrict__ I, 
             for (int u = 0; u < JU; ++u)
 #pragma unroll
                 for (int cc = 0; cc < CU; ++cc)
-                    if (c0 + cc < D.nitems) w[u] += (double)v[u][cc];
+                    if (c0 + cc < D.nparts) w[u] += (double)v[u][cc];
         }
         double dj[JU], xj[JU], gj[JU];
 #pragma unroll
@@ -417,14 +535,26 @@ int severity(int s) {
         case 16: { constexpr int NVc = 16; STMT; } break; \
     }
 
-template <typename TK, typename ACC>
-void launch_bv_fused(int cpt, hipStream_t s, unsigned nitems, const VarInst* I, const VarItem* items,
-                     const GPState* st, int refresh) {
+template <typename TK, typename ACC, bool WAVES>
+void launch_bv_fused_w(int cpt, hipStream_t s, unsigned nitems, const VarInst* I, const VarItem* items,
+                       const GPState* st, int refresh) {
     switch (cpt) {
-        case 1: hipLaunchKernelGGL((k_bv_fused<TK, ACC, 1>), dim3(nitems), dim3(BV_FT), 0, s, I, items, st, refresh); break;
-        case 2: hipLaunchKernelGGL((k_bv_fused<TK, ACC, 2>), dim3(nitems), dim3(BV_FT), 0, s, I, items, st, refresh); break;
-        case 4: hipLaunchKernelGGL((k_bv_fused<TK, ACC, 4>), dim3(nitems), dim3(BV_FT), 0, s, I, items, st, refresh); break;
+        case 1:
+            hipLaunchKernelGGL((k_bv_fused<TK, ACC, 1, WAVES>), dim3(nitems), dim3(BV_FT), 0, s, I, items, st, refresh);
+            break;
+        case 2:
+            hipLaunchKernelGGL((k_bv_fused<TK, ACC, 2, WAVES>), dim3(nitems), dim3(BV_FT), 0, s, I, items, st, refresh);
+            break;
+        case 4:
+            hipLaunchKernelGGL((k_bv_fused<TK, ACC, 4, WAVES>), dim3(nitems), dim3(BV_FT), 0, s, I, items, st, refresh);
+            break;
     }
+}
+template <typename TK, typename ACC>
+void launch_bv_fused(int cpt, bool waves, hipStream_t s, unsigned nitems, const VarInst* I, const VarItem* items,
+                     const GPState* st, int refresh) {
+    if (waves) launch_bv_fused_w<TK, ACC, true>(cpt, s, nitems, I, items, st, refresh);
+    else launch_bv_fused_w<TK, ACC, false>(cpt, s, nitems, I, items, st, refresh);
 }
 }  // namespace
 
@@ -464,11 +594,16 @@ int solve_batched_var_lockstep(gp_handle h, gp_dtype kdtype, const gp_instance* 
         D.ldw = (S.p + 63) / 64 * 64;
         D.aligned = (S.ldk % vec == 0) && (((uintptr_t)S.K) % 16 == 0);
         D.aligned8 = (S.ldk * esz % 8 == 0) && (((uintptr_t)S.K) % 8 == 0);
+        // narrow problems of float or bf16 K with 16-byte aligned rows (or
+        // 8-byte aligned bf16 rows) run the wave-per-row pass
+        D.waves = (o.var_wave_rows >= 0 && !f64v && S.p <= BV_NARROW &&
+                   (D.aligned || (kdtype == GP_BF16 && D.aligned8))) ? 1 : 0;
         for (int64_t i = 0; i < D.nitems; ++i) hitems.push_back(VarItem{(int32_t)b, (int32_t)i});
         total_items += D.nitems;
         ox[(size_t)b] = take(8 * (3 * S.p + 3 * S.n));
-        ow[(size_t)b] = take((size_t)(f64v ? 8 : 4) * D.nitems * D.ldw);
-        osp[(size_t)b] = take(8 * SPART * D.nitems);
+        D.nparts = D.waves ? BV_NW * D.nitems : D.nitems;
+        ow[(size_t)b] = take((size_t)(f64v ? 8 : 4) * D.nparts * D.ldw);
+        osp[(size_t)b] = take(8 * SPART * D.nparts);
     }
     const size_t o_items = take(sizeof(VarItem) * hitems.size());
     // target check: a descriptor per problem; candidates, item ranges, row
@@ -493,6 +628,19 @@ int solve_batched_var_lockstep(gp_handle h, gp_dtype kdtype, const gp_instance* 
         D.wpart64 = f64v ? (double*)(ws + ow[(size_t)b]) : nullptr;
         D.spart = (double*)(ws + osp[(size_t)b]);
     }
+    // the kernel with the wave-per-row pass: when some problem uses it, and,
+    // while the workgroup pass of the batch's widest problem needs fewer
+    // registers than the wave pass (bf16 K with one column chunk per thread,
+    // float K with up to two), only if every problem does (the problems keep
+    // the workgroup pass otherwise)
+    int64_t nwaves = 0;
+    for (int64_t b = 0; b < B; ++b) nwaves += hI[(size_t)b].waves;
+    const bool kwaves = nwaves > 0 && (cpt >= (kdtype == GP_BF16 ? 2 : 4) || nwaves == B);
+    if (!kwaves)
+        for (int64_t b = 0; b < B; ++b) {
+            hI[(size_t)b].waves = 0;
+            hI[(size_t)b].nparts = hI[(size_t)b].nitems;   // (their partials were sized for the waves)
+        }
     // longest rows first so that big items start early
     std::stable_sort(hitems.begin(), hitems.end(), [&](const VarItem& a, const VarItem& c) {
         return hI[(size_t)a.inst].p > hI[(size_t)c.inst].p;
@@ -521,9 +669,9 @@ int solve_batched_var_lockstep(gp_handle h, gp_dtype kdtype, const gp_instance* 
     const GPParams prm = make_params(o, 0.0, tol);
     const unsigned nit = (unsigned)hitems.size();
     auto fused = [&](int refresh) {
-        if (kdtype == GP_F64) launch_bv_fused<double, double>(cpt, s, nit, dI, ditems, st, refresh);
-        else if (kdtype == GP_F32) launch_bv_fused<float, float>(cpt, s, nit, dI, ditems, st, refresh);
-        else launch_bv_fused<bf16_t, float>(cpt, s, nit, dI, ditems, st, refresh);
+        if (kdtype == GP_F64) launch_bv_fused<double, double>(cpt, false, s, nit, dI, ditems, st, refresh);
+        else if (kdtype == GP_F32) launch_bv_fused<float, float>(cpt, kwaves, s, nit, dI, ditems, st, refresh);
+        else launch_bv_fused<bf16_t, float>(cpt, kwaves, s, nit, dI, ditems, st, refresh);
     };
     auto update = [&](int refresh) {
         if (f64v) hipLaunchKernelGGL((k_bv_update<double, BV_T>), dim3((unsigned)B), dim3(BV_T), 0, s, dI, st, refresh);

@@ -42,7 +42,7 @@ class GPOpts(C.Structure):
                 ("batch_splitk", C.c_int32), ("batch_rows_t", C.c_int32),
                 ("batch_cols_t", C.c_int32), ("var_item_rows", C.c_int32),
                 ("batch_gemm_depth", C.c_int32), ("batch_gemm_tile", C.c_int32),
-                ("lookahead", C.c_int32)]
+                ("lookahead", C.c_int32), ("var_wave_rows", C.c_int32)]
 
 
 class GPResult(C.Structure):
@@ -537,14 +537,14 @@ def _tuned_shared(kdt, n, p, B, kw):
 
 def _tuned_var(kdt, kw):
     """Add the tuned uneven-batch options unless the caller chose any."""
-    if "var_item_rows" in kw or "graph" in kw:
+    if "var_item_rows" in kw or "graph" in kw or "var_wave_rows" in kw:
         return kw
     from . import tune
     t = tune.lookup_var(_DT_NAME[kdt])
     if not t:
         return kw
     kw = dict(kw)
-    for k in ("var_item_rows", "graph"):
+    for k in ("var_item_rows", "graph", "var_wave_rows"):
         if t.get(k):
             kw[k] = int(t[k])
     return kw

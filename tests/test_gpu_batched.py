@@ -396,6 +396,26 @@ def test_var_small_matches_oracle(H, dtype):
     _check_var(insts, X, res, range(7), *tol)
 
 
+@pytest.mark.parametrize("dtype", ["bf16", "f32"])
+def test_var_wave_pass_matches_oracle(H, dtype):
+    """Narrow problems (p <= 1024) run the fused pass one row per wave, each
+    wave leaving its own partial vector: checked against the oracle when every
+    problem is narrow (one column chunk per thread), beside a wide problem (two
+    chunks), with items of 16 rows and with items whose last rows leave waves
+    empty (n = 130, 131 at 64-row items), and beside the workgroup-wide pass
+    (var_wave_rows = -1) on the same problems."""
+    rng = np.random.default_rng(79)
+    narrow = [130, 131] + [int(n) for n in rng.integers(20, 257, size=4)]
+    for label, ns, kw in (("all narrow", narrow, {}), ("all narrow, 16-row items", narrow, dict(var_item_rows=16)),
+                          ("beside a wide problem", narrow + [700], {}),
+                          ("workgroup pass", narrow, dict(var_wave_rows=-1))):
+        say(f"[batched-var] wave pass {dtype}: {label}")
+        insts = [instances.gaussian_instance(n, 4 * n, max(1, n // 20), sigma=1e-2, dtype=dtype, seed=970 + i)
+                 for i, n in enumerate(ns)]
+        X, res = H.solve_batched_var(_var_problems(insts, dtype), tol=1e-13, max_iter=5000, refresh_every=50, **kw)
+        _check_var(insts, X, res, range(len(ns)), 1e-6, 1e-4)
+
+
 def test_var_uneven_sampled(H):
     say("[batched-var] 64 problems, n in [128, 1024], p = 4n, bf16; 4 sampled")
     insts = instances.uneven_batch(64, dtype="bf16", seed=4)
@@ -520,6 +540,7 @@ def test_batched_tuning_options(H):
         H.solve_batched_shared(Kt, Y, batch.rho, batch_cols_t=256, **base)
     assert e.value.code == -1
     for bad in (dict(batch_splitk=100), dict(batch_rows_t=300), dict(var_item_rows=8), dict(batch_gemm_depth=3),
+                dict(var_wave_rows=2),
                 dict(batch_gemm_tile=100), dict(batch_gemm_tile=256, batch_gemm_depth=2),
                 dict(batch_gemm_tile=64, batch_gemm_depth=2)):
         with pytest.raises(gpl1.GPError):
