@@ -20,10 +20,11 @@
 //
 // Tiling: a 256-thread workgroup computes a 128 x 128 tile; its four waves
 // each own a 64 x 64 sub-tile = 4 x 4 MFMA 16x16x32 blocks.  Each k-step of
-// 32 stages the A tile and the NSPLIT B tiles in LDS (rows padded to 40
-// elements against bank conflicts), double buffered with one barrier per
-// step; the next step's global loads are in registers while the current
-// step's MFMAs run.
+// 32 stages the A tile and the NSPLIT B tiles in LDS (64-byte rows whose
+// 16-byte chunks are XOR-swizzled by the row against bank conflicts; the
+// other variants below pad rows to 40 elements instead), double buffered
+// with one barrier per step; the next step's global loads are in registers
+// while the current step's MFMAs run.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -43,7 +44,11 @@ __global__ __launch_bounds__(GM_T) void k_gemm_bf16(const uint16_t* __restrict__
                                                     float* __restrict__ Cpart, int64_t ldc,
                                                     int64_t cstride, const int32_t* __restrict__ nmap) {
     static_assert(NSPLIT >= 1 && NSPLIT <= 3, "one to three bf16 planes");
-    constexpr int TILE = GM_BM * GM_LDS_ROW;               // elements of one staged tile
+    // staged tiles: rows of 32 elements (64 bytes) with the 16-byte chunk kc
+    // of row r stored at chunk kc ^ ((r >> 2) & 3), so that the staging
+    // stores of a wave (sixteen rows of four chunks) and the fragment reads
+    // (sixteen rows, one chunk each) spread over the banks without padding
+    constexpr int TILE = GM_BM * GM_BK;                    // elements of one staged tile
     __shared__ __attribute__((aligned(16))) uint16_t lds[2][(1 + NSPLIT) * TILE];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave & 1, wn = wave >> 1;
@@ -81,8 +86,9 @@ __global__ __launch_bounds__(GM_T) void k_gemm_bf16(const uint16_t* __restrict__
             rb21 = GPL1_LD(b1p, 2 * pstride + ko_);                             \
         }                                                                       \
     }
-#define GPL1_ST(buf_, t_, row_, kc_, v_) \
-    (*reinterpret_cast<uint4*>(&lds[buf_][(t_) * TILE + (row_) * GM_LDS_ROW + (kc_)]) = (v_))
+#define GPL1_ST(buf_, t_, row_, kc_, v_)                                                                       \
+    (*reinterpret_cast<uint4*>(&lds[buf_][(t_) * TILE + (row_) * GM_BK + ((((kc_) >> 3) ^ (((row_) >> 2) & 3)) << 3)]) = \
+         (v_))
 #define GPL1_GEMM_LSTORE(buf_)                                                  \
     {                                                                           \
         GPL1_ST(buf_, 0, row0_, kc0_, ra0);                                     \
@@ -109,19 +115,20 @@ __global__ __launch_bounds__(GM_T) void k_gemm_bf16(const uint16_t* __restrict__
     GPL1_GEMM_LSTORE(0)
     __syncthreads();
     const int fr = lane & 15, fk = (lane >> 4) * 8;   // fragment row/col and k offset of this lane
+    const int fks = ((fk >> 3) ^ ((fr >> 2) & 3)) << 3;   // its chunk in the swizzled rows
     for (int step = 0; step < nsteps; ++step) {
         const int cur = step & 1;
         if (step + 1 < nsteps) GPL1_GEMM_GLOAD(step + 1)
         bf16x8_t af[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i)
-            af[i] = *reinterpret_cast<const bf16x8_t*>(&lds[cur][(wm * 64 + i * 16 + fr) * GM_LDS_ROW + fk]);
+            af[i] = *reinterpret_cast<const bf16x8_t*>(&lds[cur][(wm * 64 + i * 16 + fr) * GM_BK + fks]);
 #pragma unroll
         for (int t = 0; t < NSPLIT; ++t) {
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const bf16x8_t bfr = *reinterpret_cast<const bf16x8_t*>(
-                    &lds[cur][(1 + t) * TILE + (wn * 64 + j * 16 + fr) * GM_LDS_ROW + fk]);
+                    &lds[cur][(1 + t) * TILE + (wn * 64 + j * 16 + fr) * GM_BK + fks]);
 #pragma unroll
                 for (int i = 0; i < 4; ++i)
                     acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr, acc[i][j], 0, 0, 0);
@@ -550,7 +557,7 @@ __global__ __launch_bounds__(GM_T) void k_gemm_bf16_n64(const uint16_t* __restri
                                                         float* __restrict__ Cpart, int64_t ldc,
                                                         int64_t cstride, const int32_t* __restrict__ nmap) {
     static_assert(NSPLIT >= 1 && NSPLIT <= 3, "one to three bf16 planes");
-    constexpr int TA = GM_BM * GM_LDS_ROW, TB = GM3_BN * GM_LDS_ROW;
+    constexpr int TA = GM_BM * GM_BK, TB = GM3_BN * GM_BK;   // swizzled rows, as in k_gemm_bf16
     __shared__ __attribute__((aligned(16))) uint16_t lds[2][TA + NSPLIT * TB];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave & 1, wn = wave >> 1;
@@ -577,14 +584,15 @@ __global__ __launch_bounds__(GM_T) void k_gemm_bf16_n64(const uint16_t* __restri
         if constexpr (NSPLIT > 1) rb1 = GPL1_N3_LD(bp, pstride + ko_);          \
         if constexpr (NSPLIT > 2) rb2 = GPL1_N3_LD(bp, 2 * pstride + ko_);      \
     }
+#define GPL1_N3_SWZ(row_) ((row_) * GM_BK + ((((kc_) >> 3) ^ (((row_) >> 2) & 3)) << 3))
 #define GPL1_N3_ST(buf_, off_, v_) (*reinterpret_cast<uint4*>(&lds[buf_][(off_)]) = (v_))
 #define GPL1_N3_LSTORE(buf_)                                                    \
     {                                                                           \
-        GPL1_N3_ST(buf_, rowA0 * GM_LDS_ROW + kc_, ra0);                        \
-        GPL1_N3_ST(buf_, rowA1 * GM_LDS_ROW + kc_, ra1);                        \
-        GPL1_N3_ST(buf_, TA + rowB * GM_LDS_ROW + kc_, rb0);                    \
-        if constexpr (NSPLIT > 1) GPL1_N3_ST(buf_, TA + TB + rowB * GM_LDS_ROW + kc_, rb1);       \
-        if constexpr (NSPLIT > 2) GPL1_N3_ST(buf_, TA + 2 * TB + rowB * GM_LDS_ROW + kc_, rb2);   \
+        GPL1_N3_ST(buf_, GPL1_N3_SWZ(rowA0), ra0);                              \
+        GPL1_N3_ST(buf_, GPL1_N3_SWZ(rowA1), ra1);                              \
+        GPL1_N3_ST(buf_, TA + GPL1_N3_SWZ(rowB), rb0);                          \
+        if constexpr (NSPLIT > 1) GPL1_N3_ST(buf_, TA + TB + GPL1_N3_SWZ(rowB), rb1);             \
+        if constexpr (NSPLIT > 2) GPL1_N3_ST(buf_, TA + 2 * TB + GPL1_N3_SWZ(rowB), rb2);         \
     }
     f32x4_t acc[4][2];
 #pragma unroll
@@ -595,19 +603,20 @@ __global__ __launch_bounds__(GM_T) void k_gemm_bf16_n64(const uint16_t* __restri
     GPL1_N3_LSTORE(0)
     __syncthreads();
     const int fr = lane & 15, fk = (lane >> 4) * 8;
+    const int fks = ((fk >> 3) ^ ((fr >> 2) & 3)) << 3;   // its chunk in the swizzled rows
     for (int step = 0; step < nsteps; ++step) {
         const int cur = step & 1;
         if (step + 1 < nsteps) GPL1_N3_GLOAD(step + 1)
         bf16x8_t af[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i)
-            af[i] = *reinterpret_cast<const bf16x8_t*>(&lds[cur][(wm * 64 + i * 16 + fr) * GM_LDS_ROW + fk]);
+            af[i] = *reinterpret_cast<const bf16x8_t*>(&lds[cur][(wm * 64 + i * 16 + fr) * GM_BK + fks]);
 #pragma unroll
         for (int t = 0; t < NSPLIT; ++t) {
 #pragma unroll
             for (int j = 0; j < 2; ++j) {
                 const bf16x8_t bfr = *reinterpret_cast<const bf16x8_t*>(
-                    &lds[cur][TA + t * TB + (wn * 32 + j * 16 + fr) * GM_LDS_ROW + fk]);
+                    &lds[cur][TA + t * TB + (wn * 32 + j * 16 + fr) * GM_BK + fks]);
 #pragma unroll
                 for (int i = 0; i < 4; ++i)
                     acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr, acc[i][j], 0, 0, 0);
@@ -633,6 +642,7 @@ __global__ __launch_bounds__(GM_T) void k_gemm_bf16_n64(const uint16_t* __restri
 #undef GPL1_N3_LSTORE
 #undef GPL1_N3_LD
 #undef GPL1_N3_ST
+#undef GPL1_N3_SWZ
 }
 
 }  // namespace gpl1
