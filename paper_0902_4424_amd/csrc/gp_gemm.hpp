@@ -295,7 +295,7 @@ __global__ __launch_bounds__(GM_T) void k_gemm_bf16_d2(const uint16_t* __restric
 // A_l B_h, an FP32-accurate product of two FP32 matrices (the dropped plane
 // products are below 2^-24 of the result) in one pass that stages every
 // plane once.  Same tiling, padding rules and output layout as k_gemm_bf16.
-// LDS holds the (NA + NB) tiles of one k-step (60 KiB for 3 + 3, so two
+// LDS holds the (NA + NB) tiles of one k-step (48 KiB for 3 + 3, so two
 // workgroups fit a CU); the next step waits in registers, two barriers a step.
 template <int NA, int NB>
 __global__ __launch_bounds__(GM_T) void k_gemm_bf16_planes(const uint16_t* __restrict__ A, int64_t lda,
@@ -304,7 +304,7 @@ __global__ __launch_bounds__(GM_T) void k_gemm_bf16_planes(const uint16_t* __res
                                                            float* __restrict__ Cpart, int64_t ldc,
                                                            int64_t cstride, const int32_t* __restrict__ nmap) {
     static_assert(NA >= 1 && NA <= 3 && NB >= 1 && NB <= 3 && NA <= NB, "one to three planes each");
-    constexpr int TILE = GM_BM * GM_LDS_ROW;
+    constexpr int TILE = GM_BM * GM_BK;   // swizzled 64-byte rows, as in k_gemm_bf16
     constexpr int NT = NA + NB;
     __shared__ __attribute__((aligned(16))) uint16_t lds[1][NT * TILE];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -352,8 +352,9 @@ __global__ __launch_bounds__(GM_T) void k_gemm_bf16_planes(const uint16_t* __res
             S_##b21 = GPL1_PL_LD(b1p, 2 * bpstride + ko_);                      \
         }                                                                       \
     }
-#define GPL1_PL_ST(u_, row_, kc_, v_) \
-    (*reinterpret_cast<uint4*>(&lds[0][(u_) * TILE + (row_) * GM_LDS_ROW + (kc_)]) = (v_))
+#define GPL1_PL_ST(u_, row_, kc_, v_)                                                                          \
+    (*reinterpret_cast<uint4*>(&lds[0][(u_) * TILE + (row_) * GM_BK + ((((kc_) >> 3) ^ (((row_) >> 2) & 3)) << 3)]) = \
+         (v_))
 #define GPL1_PL_LSTORE(S_)                                                      \
     {                                                                           \
         GPL1_PL_ST(0, row0_, kc0_, S_##a00);                                    \
@@ -384,11 +385,11 @@ __global__ __launch_bounds__(GM_T) void k_gemm_bf16_planes(const uint16_t* __res
             bf16x8_t af[4];                                                     \
             _Pragma("unroll") for (int i = 0; i < 4; ++i)                       \
                 af[i] = *reinterpret_cast<const bf16x8_t*>(                     \
-                    &lds[0][a * TILE + (wm * 64 + i * 16 + fr) * GM_LDS_ROW + fk]); \
+                    &lds[0][a * TILE + (wm * 64 + i * 16 + fr) * GM_BK + fks]); \
             _Pragma("unroll") for (int t = 0; t + a < NB; ++t)                  \
             _Pragma("unroll") for (int j = 0; j < 4; ++j) {                     \
                 const bf16x8_t bfr = *reinterpret_cast<const bf16x8_t*>(        \
-                    &lds[0][(NA + t) * TILE + (wn * 64 + j * 16 + fr) * GM_LDS_ROW + fk]); \
+                    &lds[0][(NA + t) * TILE + (wn * 64 + j * 16 + fr) * GM_BK + fks]); \
                 _Pragma("unroll") for (int i = 0; i < 4; ++i)                   \
                     acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr, acc[i][j], 0, 0, 0); \
             }                                                                   \
@@ -402,6 +403,7 @@ __global__ __launch_bounds__(GM_T) void k_gemm_bf16_planes(const uint16_t* __res
         for (int j = 0; j < 4; ++j) acc[i][j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
 
     const int fr = lane & 15, fk = (lane >> 4) * 8;
+    const int fks = ((fk >> 3) ^ ((fr >> 2) & 3)) << 3;   // its chunk in the swizzled rows
     GPL1_PL_GLOAD(r0, 0)
     GPL1_PL_LSTORE(r0)
     __syncthreads();
