@@ -10,7 +10,8 @@ Shared-K batches (dtype, n, p, B): the whole batched solve to a relative
 change of 1e-10 over the GEMM output tile and split-K chunk, the per-problem row and column
 kernel widths and graph replay, one option at a time (coordinate search from
 the automatic choice).  Uneven batches (dtype, the 512-problem workload of n
-in [128, 1024], p = 4n): rows per work item and graph replay.
+in [128, 1024], p = 4n): rows per work item, the wave-per-row pass of the
+narrow problems and graph replay.
 
     python -m paper_0902_4424_amd.tune f32:4096x16384 shared:bf16:2048x8192:256 var:bf16:512 ...
 """
@@ -188,7 +189,8 @@ def tune_var(H, dtype, B, reps=3, log=print):
         log(f"  {var_key(dtype)} ({B} problems) {kw or 'automatic'}: {min(ts) * 1e3:.3f} ms")
         return min(ts)
 
-    best, t = _coordinate_search({"var_item_rows": (16, 32, 128, 256), "graph": (1,)}, run, log)
+    best, t = _coordinate_search({"var_item_rows": (16, 32, 128, 256), "var_wave_rows": (-1,), "graph": (1,)},
+                                 run, log)
     return dict(best, solve_ms=round(t * 1e3, 3), problems=B)
 
 
