@@ -152,17 +152,18 @@ __global__ __launch_bounds__(BS_T) void k_bs_init(BsPtrs P, GPParams prm, const 
         }
     }
     if (tid == 0) {
-        GPState s = {};
-        s.prm = prm;
-        s.prm.rho = rb;
-        if (ftarget) s.prm.f_target = ftarget[b];
-        s.f_target0 = s.prm.f_target;
-        s.tau = prm.tau1;
-        s.alpha = prm.amax;
-        s.status = ST_MAX_ITER;
-        s.projected = inside ? 0 : 1;
-        s.live = 1;
-        P.st[b] = s;
+        // written in place (a local copy of the state would go to scratch)
+        GPState* sp = P.st + b;
+        __builtin_memset(sp, 0, sizeof(GPState));
+        sp->prm = prm;
+        sp->prm.rho = rb;
+        if (ftarget) sp->prm.f_target = ftarget[b];
+        sp->f_target0 = sp->prm.f_target;
+        sp->tau = prm.tau1;
+        sp->alpha = prm.amax;
+        sp->status = ST_MAX_ITER;
+        sp->projected = inside ? 0 : 1;
+        sp->live = 1;
         P.done[b] = 0;
     }
 }

@@ -84,17 +84,18 @@ __global__ __launch_bounds__(BV_T) void k_bv_init(const VarInst* __restrict__ I,
         if (j < D.p) D.x[j] = l1_hval(vr[e], m, t, inside, D.rho);
     }
     if (tid == 0) {
-        GPState s = {};
-        s.prm = prm;
-        s.prm.rho = D.rho;
-        s.prm.f_target = D.ftarget;
-        s.f_target0 = D.ftarget;
-        s.tau = prm.tau1;
-        s.alpha = prm.amax;
-        s.status = ST_MAX_ITER;
-        s.projected = inside ? 0 : 1;
-        s.live = 1;
-        st[b] = s;
+        // written in place (a local copy of the state would go to scratch)
+        GPState* sp = st + b;
+        __builtin_memset(sp, 0, sizeof(GPState));
+        sp->prm = prm;
+        sp->prm.rho = D.rho;
+        sp->prm.f_target = D.ftarget;
+        sp->f_target0 = D.ftarget;
+        sp->tau = prm.tau1;
+        sp->alpha = prm.amax;
+        sp->status = ST_MAX_ITER;
+        sp->projected = inside ? 0 : 1;
+        sp->live = 1;
     }
 }
 
