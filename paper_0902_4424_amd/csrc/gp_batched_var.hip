@@ -273,9 +273,13 @@ __global__ __launch_bounds__(T) void k_bv_update(const VarInst* __restrict__ I, 
                                                     int refresh) {
     __shared__ double lds[3 * (T / WAVE)];
     __shared__ double sh[4];
+    // the problem's state, loaded by all threads at once together with the
+    // partial dots (one round trip instead of the scalar thread's dependent
+    // reads), updated in LDS and stored back at the end
+    __shared__ GPState S;
     const int b = blockIdx.x, tid = threadIdx.x;
     GPState* st = st_all + b;
-    if (st->done) return;
+    state_load(S, st);
     const VarInst D = I[b];
     const ACC* wp;
     if constexpr (sizeof(ACC) == 8) wp = (const ACC*)D.wpart64;
@@ -286,7 +290,8 @@ __global__ __launch_bounds__(T) void k_bv_update(const VarInst* __restrict__ I, 
         a[0] += D.spart[SPART * i];
         a[1] += D.spart[SPART * i + 1];
     }
-    block_reduce<T, 2, 1>(a, none, lds);
+    block_reduce<T, 2, 1>(a, none, lds);   // (its barriers also publish S)
+    if (S.done) return;
     const double tt = a[0], tr = a[1];
     auto wsum = [&](int64_t j) {
         double s = 0.0;
@@ -297,20 +302,22 @@ __global__ __launch_bounds__(T) void k_bv_update(const VarInst* __restrict__ I, 
         for (int64_t i = tid; i < D.n; i += T) D.r[i] = D.q[i];
         for (int64_t j = tid; j < D.p; j += T) D.g[j] = 2.0 * wsum(j);
         if (tid == 0) {
-            if (st->k == 0 && st->nhist == 0) { st->hpos = 0; st->nhist = 1; }
-            st->fhist[st->hpos] = tt;
-            st->f = tt;
-            if (!isfinite(tt)) { st->status = ST_NONFINITE; st->done = 1; }
+            if (S.k == 0 && S.nhist == 0) { S.hpos = 0; S.nhist = 1; }
+            S.fhist[S.hpos] = tt;
+            S.f = tt;
+            if (!isfinite(tt)) { S.status = ST_NONFINITE; S.done = 1; }
         }
+        __syncthreads();
+        state_store(st, S);
         return;
     }
     if (tid == 0) {
-        const GPParams& P = st->prm;
-        const double qq = tt, rq = tr, f = st->f, gd = st->gd;
+        const GPParams& P = S.prm;
+        const double qq = tt, rq = tr, f = S.f, gd = S.gd;
         double fmax = f;
-        const int nh = st->nhist < P.M ? st->nhist : P.M;
-        for (int i = 0; i < nh; ++i) fmax = fmax > st->fhist[(st->hpos - i + MAX_M) % MAX_M]
-                                              ? fmax : st->fhist[(st->hpos - i + MAX_M) % MAX_M];
+        const int nh = S.nhist < P.M ? S.nhist : P.M;
+        for (int i = 0; i < nh; ++i) fmax = fmax > S.fhist[(S.hpos - i + MAX_M) % MAX_M]
+                                              ? fmax : S.fhist[(S.hpos - i + MAX_M) % MAX_M];
         double lam = 1.0;
         int nb = 0;
         bool fail = false;
@@ -323,23 +330,26 @@ __global__ __launch_bounds__(T) void k_bv_update(const VarInst* __restrict__ I, 
         sh[0] = lam;
         sh[1] = fail ? 1.0 : 0.0;
         if (fail) {
-            st->status = ST_BACKTRACK;
-            st->done = 1;
+            S.status = ST_BACKTRACK;
+            S.done = 1;
         } else {
             const double fn = f + lam * (2.0 * rq + lam * qq);
-            st->lam = lam;
-            st->nb = nb;
-            st->backtracks += nb;
-            st->rel = (f - fn) / f;
-            st->f = fn;
-            st->k += 1;
-            st->hpos = (st->hpos + 1) % MAX_M;
-            st->fhist[st->hpos] = fn;
-            if (st->nhist < MAX_M) st->nhist++;
+            S.lam = lam;
+            S.nb = nb;
+            S.backtracks += nb;
+            S.rel = (f - fn) / f;
+            S.f = fn;
+            S.k += 1;
+            S.hpos = (S.hpos + 1) % MAX_M;
+            S.fhist[S.hpos] = fn;
+            if (S.nhist < MAX_M) S.nhist++;
         }
     }
     __syncthreads();
-    if (sh[1] != 0.0) return;
+    if (sh[1] != 0.0) {
+        state_store(st, S);
+        return;
+    }
     const double lam = sh[0];
     for (int64_t i = tid; i < D.n; i += T) D.r[i] += lam * D.q[i];
     double dots[2] = {0.0, 0.0};
@@ -391,18 +401,20 @@ __global__ __launch_bounds__(T) void k_bv_update(const VarInst* __restrict__ I, 
     }
     block_reduce<T, 2, 1>(dots, none, lds);
     if (tid == 0) {
-        const GPParams& P = st->prm;
+        const GPParams& P = S.prm;
         // s = lam d, z = 2 lam w: equation (5), then Algorithm 2
         const double l2 = lam * lam;
-        ss_update(st, st->k, l2 * st->dd, 2.0 * l2 * dots[0], 4.0 * l2 * dots[1]);
-        const double fn = st->f;
+        ss_update(&S, S.k, l2 * S.dd, 2.0 * l2 * dots[0], 4.0 * l2 * dots[1]);
+        const double fn = S.f;
         int stop = 0;
-        if (!isfinite(fn)) { st->status = ST_NONFINITE; stop = 1; }
-        else if (P.f_target >= 0.0 && fn <= P.f_target) { st->status = ST_TARGET; stop = 1; }
-        else if (P.tol > 0.0 && st->rel < P.tol) { st->status = ST_OK_TOL; stop = 1; }
-        else if (st->k >= P.max_iter) { st->status = ST_MAX_ITER; stop = 1; }
-        if (stop) st->done = 1;
+        if (!isfinite(fn)) { S.status = ST_NONFINITE; stop = 1; }
+        else if (P.f_target >= 0.0 && fn <= P.f_target) { S.status = ST_TARGET; stop = 1; }
+        else if (P.tol > 0.0 && S.rel < P.tol) { S.status = ST_OK_TOL; stop = 1; }
+        else if (S.k >= P.max_iter) { S.status = ST_MAX_ITER; stop = 1; }
+        if (stop) S.done = 1;
     }
+    __syncthreads();
+    state_store(st, S);
 }
 
 // projection (alpha0 first on init), direction and its dots
