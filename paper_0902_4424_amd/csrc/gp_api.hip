@@ -614,7 +614,9 @@ static int solve_single(gp_handle h, gp_dtype kdtype, const void* K, int64_t n, 
     double* upart = (double*)(ws + P.o_upart);
     void* wpart = ws + P.o_wpart;
     const int vec = 16 / esize(kdtype);
-    const bool aligned = (ldk % vec == 0) && (((uintptr_t)K) % 16 == 0);
+    // the fused pass's branch-free loads need whole chunks: rows 16-byte
+    // aligned and p a multiple of the chunk
+    const bool aligned = (ldk % vec == 0) && (p % vec == 0) && (((uintptr_t)K) % 16 == 0);
     const bool f64v = kdtype == GP_F64;
 
     // lookahead: the update kernel posts its progress to the handle's

@@ -605,8 +605,10 @@ int solve_batched_var_lockstep(gp_handle h, gp_dtype kdtype, const gp_instance* 
         D.nitems = (S.n + D.item_rows - 1) / D.item_rows;
         D.item0 = total_items;
         D.ldw = (S.p + 63) / 64 * 64;
-        D.aligned = (S.ldk % vec == 0) && (((uintptr_t)S.K) % 16 == 0);
-        D.aligned8 = (S.ldk * esz % 8 == 0) && (((uintptr_t)S.K) % 8 == 0);
+        // whole chunks for the fused pass: rows aligned to the chunk and p a
+        // multiple of it
+        D.aligned = (S.ldk % vec == 0) && (S.p % vec == 0) && (((uintptr_t)S.K) % 16 == 0);
+        D.aligned8 = (S.ldk * esz % 8 == 0) && (S.p * esz % 8 == 0) && (((uintptr_t)S.K) % 8 == 0);
         // narrow problems of float or bf16 K with 16-byte aligned rows (or
         // 8-byte aligned bf16 rows) run the wave-per-row pass
         D.waves = (o.var_wave_rows >= 0 && !f64v && S.p <= BV_NARROW &&

@@ -263,7 +263,7 @@ extern "C" int gp_fom_solve(gp_handle h, int32_t method, gp_dtype kdtype, const 
     void* wpart = ws + P.o_wpart;
     const bool f64v = kdtype == GP_F64;
     const int vec = 16 / esize(kdtype);
-    const bool aligned = (ldk % vec == 0) && (((uintptr_t)K) % 16 == 0);
+    const bool aligned = (ldk % vec == 0) && (p % vec == 0) && (((uintptr_t)K) % 16 == 0);   // as in gp_l1_solve
 
     gp_opts po = o;
     po.max_iter = iters;

@@ -611,17 +611,42 @@ struct FusedBlock {
     static constexpr int VEC = KTraits<TK>::VEC;
     static constexpr int NW = T / WAVE;
 
-    template <bool ALIGNED>
+    // BRANCHLESS (rows aligned to the chunk size and p a multiple of VEC, so
+    // every chunk lies wholly before p or wholly past it): each chunk is one
+    // load from a valid address with no branch around it (rows past r1 read
+    // row r1 - 1, chunks past p read column 0), so the compiler's waits can
+    // count the loads still in flight and the next row blocks keep loading
+    // while one is reduced.  A chunk past p multiplies the zeros of the
+    // direction, so the dots are the same, and the partial w it forms there
+    // lies in columns past p, which no reader uses; rows past r1 are skipped
+    // by process.  Otherwise chunks outside the block read as zero.
+    template <bool ALIGNED, bool BRANCHLESS = false>
     __device__ __forceinline__ static void load(KVec<TK> (&buf)[RB][CPT], const TK* K, int64_t ldk,
                                                 int64_t p, int64_t row0, int64_t r1) {
+        if constexpr (BRANCHLESS) {
 #pragma unroll
-        for (int r = 0; r < RB; ++r) {
-            const int64_t row = row0 + r;
+            for (int r = 0; r < RB; ++r) {
+                const int64_t row = row0 + r < r1 ? row0 + r : r1 - 1;
 #pragma unroll
-            for (int c = 0; c < CPT; ++c) {
-                const int64_t col = ((int64_t)c * T + threadIdx.x) * VEC;
-                if (row < r1 && col < p) load_kvec<TK, ALIGNED>(K + row * ldk, col, p, buf[r][c]);
-                else buf[r][c].clear();
+                for (int c = 0; c < CPT; ++c) {
+                    const int64_t col = ((int64_t)c * T + threadIdx.x) * VEC;
+                    const TK* src = K + row * ldk + (col < p ? col : 0);
+                    if constexpr (std::is_same<TK, bf16x4_t>::value)
+                        buf[r][c].raw = *reinterpret_cast<const uint2*>(src);
+                    else
+                        buf[r][c].raw = *reinterpret_cast<const uint4*>(src);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < RB; ++r) {
+                const int64_t row = row0 + r;
+#pragma unroll
+                for (int c = 0; c < CPT; ++c) {
+                    const int64_t col = ((int64_t)c * T + threadIdx.x) * VEC;
+                    if (row < r1 && col < p) load_kvec<TK, ALIGNED>(K + row * ldk, col, p, buf[r][c]);
+                    else buf[r][c].clear();
+                }
             }
         }
     }
@@ -781,23 +806,36 @@ __device__ __forceinline__ void fused_body(const TK* __restrict__ K, int64_t n, 
         kl += RB;
         ++blk;
     };
+    // the next row block's loads.  Branch-free for 2-byte K with three
+    // buffers, issued even past the last block (rows clamped, never reduced):
+    // the bf16 pass is limited by how long each row waits, and measured
+    // 35.4 -> 33.8 us per launch at 4096 x 16384; the FP32 pass streams at
+    // the memory system's pace either way, and the extra loads past the last
+    // block cost it about 1 %, so it keeps its guarded loads
+    constexpr bool BRANCHLESS = ALIGNED && NB > 2 && sizeof(TK) == 2;
+    auto prefetch = [&](KVec<TK> (&buf)[RB][CPT], int64_t row) {
+        if constexpr (BRANCHLESS)
+            FB::template load<true, true>(buf, K, ldk, p, row < lim ? row : lim - 1, lim);
+        else if (row < lim)
+            FB::template load<ALIGNED>(buf, K, ldk, p, row, lim);
+    };
     if constexpr (NB > 2) {
         for (int64_t row = first; row < lim; row += 3 * step) {
-            if (row + 2 * step < lim) FB::template load<ALIGNED>(C, K, ldk, p, row + 2 * step, lim);
+            prefetch(C, row + 2 * step);
             run(A, row);
             if (row + step >= lim) break;
-            if (row + 3 * step < lim) FB::template load<ALIGNED>(A, K, ldk, p, row + 3 * step, lim);
+            prefetch(A, row + 3 * step);
             run(B, row + step);
             if (row + 2 * step >= lim) break;
-            if (row + 4 * step < lim) FB::template load<ALIGNED>(B, K, ldk, p, row + 4 * step, lim);
+            prefetch(B, row + 4 * step);
             run(C, row + 2 * step);
         }
     } else {
         for (int64_t row = first; row < lim; row += 2 * step) {
-            if (row + step < lim) FB::template load<ALIGNED>(B, K, ldk, p, row + step, lim);
+            prefetch(B, row + step);
             run(A, row);
             if (row + step >= lim) break;
-            if (row + 2 * step < lim) FB::template load<ALIGNED>(A, K, ldk, p, row + 2 * step, lim);
+            prefetch(A, row + 2 * step);
             run(B, row + step);
         }
     }
