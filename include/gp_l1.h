@@ -60,6 +60,10 @@ typedef enum {
     GP_E_UNSUPPORTED = -5   /* shape outside what the kernels handle             */
 } gp_status;
 
+/* gp_opts.fused_cfg value of the K pass over column panels (two launches,
+ * K read twice; see gp_l1_solve). */
+#define GP_FUSED_PANELS 13
+
 /* Solver options.  gp_opts_default() fills the values the paper uses for
  * GPSS (end of Section 3): M = 1, theta = 0.5, beta = 1e-4,
  * alpha_min = 1e-10, alpha_max = 1e10, tau1 = 0.5, M_alpha = 2. */
@@ -83,7 +87,8 @@ typedef struct {
     int32_t refresh_every;/* recompute r = Kx - y, g = 2K^T r every R iters (0 = never) */
     int32_t backtrack_cap;/* max reductions of the line-search step            */
     int32_t chunk;        /* iterations enqueued between host status polls     */
-    int32_t fused_cfg;    /* tuning: fused K/K^T kernel shape, 1..12 (0 = automatic) */
+    int32_t fused_cfg;    /* tuning: fused K/K^T kernel shape, 1..12, or GP_FUSED_PANELS
+                             (0 = automatic) */
     int32_t fused_grid;   /* tuning: workgroups (row slabs) of that kernel (0 = automatic) */
     int32_t profile;      /* k > 0: time the fused K/K^T launch of every k-th iteration with HIP
                              events stamped by the launch itself (result.t_fused_ms over
@@ -174,6 +179,14 @@ int gp_l1_project(gp_handle h, gp_dtype vdtype, const void* v, int64_t p,
  * x0: device p, or NULL for x0 = 0 (projected onto the ball if outside).
  * tol: stop when (f_prev - f)/f_prev < tol (0 disables).  x_out: device p.
  * opts: host, NULL = defaults.  res: host, required.
+ * Any p < 2^31 (double K: at most 65535 panels).  Up to 8192 (double K) or 16384 (float, bf16) columns one
+ * pass over K per iteration forms both K d and K^T K d; wider problems cut
+ * the columns into panels of 8192 / 16384 and read K twice per iteration
+ * (K d, then K^T of it), with the same results to rounding.  Explicit
+ * opts.fused_cfg shapes run one pass up to 16384 / 32768 / 65536 columns
+ * (slower there than the panels); one narrower than p gives
+ * GP_E_UNSUPPORTED.  opts.fused_cfg = GP_FUSED_PANELS asks for the panel
+ * pass at any p.
  * Errors: n <= 0, p <= 0, ldk < p, rho < 0 or not finite, tol < 0 -> GP_E_ARG.
  * rho == 0 returns x = 0 with GP_STATIONARY. */
 int gp_l1_solve(gp_handle h, gp_dtype kdtype, const void* K, int64_t n,

@@ -16,6 +16,7 @@
 
 #include "gp_l1.h"
 #include "gp_kernels.hpp"
+#include "gp_wide.hpp"
 #include "gp_internal.hpp"
 #include "gp_verify.hpp"
 
@@ -242,8 +243,13 @@ int pick_fused_cfg(gp_dtype dt, int64_t p, int want) {
         const FusedCfg& c = kFusedCfgs[want - 1];
         return (int64_t)c.T * c.CPT * vec >= p ? want - 1 : -1;
     }
+    // automatic: at most 512 threads and 32 columns per thread.  Wider
+    // one-pass shapes exceed the register budget (1024 threads: 128 per
+    // lane; 64 bf16 columns per thread) and measured 1.3-6x slower than the
+    // pass over column panels that takes over beyond them
     for (int i = 0; i < 6; ++i) {
         const FusedCfg& c = kFusedCfgs[i];
+        if (c.T > 512 || c.CPT * vec > 32) break;
         if ((int64_t)c.T * c.CPT * vec >= p) return i;
     }
     return -1;
@@ -299,7 +305,35 @@ void launch_fused_dt(int cfg, bool aligned, hipStream_t s, int64_t G, const Fuse
 #undef GPL1_FUSED_CASE
 }
 
+// The two launches of a wide pass (grid: slabs x panels).  With timing
+// events, the first launch stamps the start and the second the end.
+template <typename TK, typename ACC, bool AL>
+void launch_wide_one(hipStream_t s, int64_t G, const FusedArgs& a) {
+    constexpr int T = WIDE_T, C = wide_cpt<TK>(), R = WIDE_RB;
+    const dim3 grid((unsigned)G, (unsigned)a.np);
+    hipExtLaunchKernelGGL((k_wide_t<TK, ACC, T, C, R, AL>), grid, dim3(T), 0, s, a.ev0, nullptr, 0, a.st,
+                          (const TK*)a.K, a.n, a.p, a.ldk, a.rows, a.v, a.vsub, a.g, a.v32, a.tpart);
+    hipExtLaunchKernelGGL((k_wide_w<TK, ACC, T, C, R, AL>), grid, dim3(T), 0, s, nullptr, a.ev1, 0, a.st,
+                          (const TK*)a.K, a.n, a.p, a.ldk, a.rows, a.np, (const double*)a.tpart, a.v, a.vsub, a.g,
+                          a.ysub, a.rvec, a.tout, (ACC*)a.wpart, a.ldw, a.spart);
+}
+template <typename TK, typename ACC>
+void launch_wide(bool aligned, hipStream_t s, int64_t G, const FusedArgs& a) {
+    if (aligned) launch_wide_one<TK, ACC, true>(s, G, a);
+    else launch_wide_one<TK, ACC, false>(s, G, a);
+}
+
+int64_t wide_panel_cols(gp_dtype dt) {
+    return dt == GP_F64 ? wide_panel<double>() : dt == GP_F32 ? wide_panel<float>() : wide_panel<bf16_t>();
+}
+
 void launch_fused(gp_dtype dt, int cfg, bool aligned, hipStream_t s, int64_t G, const FusedArgs& a) {
+    if (cfg == kCfgWide) {
+        if (dt == GP_F64) launch_wide<double, double>(aligned, s, G, a);
+        else if (dt == GP_F32) launch_wide<float, float>(aligned, s, G, a);
+        else launch_wide<bf16_t, float>(aligned, s, G, a);
+        return;
+    }
     if (dt == GP_F64) launch_fused_dt<double, double>(cfg, aligned, s, G, a);
     else if (dt == GP_F32) launch_fused_dt<float, float>(cfg, aligned, s, G, a);
     else launch_fused_dt<bf16_t, float>(cfg, aligned, s, G, a);
@@ -374,7 +408,18 @@ void launch_from_f64(hipStream_t s, const double* in, void* out, int64_t n) {
 // ---------------------------------------------------------------------------
 Plan plan_single(gp_dtype dt, int64_t n, int64_t p, const gp_opts& o) {
     Plan P{};
-    P.cfg = pick_fused_cfg(dt, p, o.fused_cfg);
+    // the two-launch pass over column panels: asked for (GP_FUSED_PANELS), or
+    // automatic beyond the widest one-pass configuration
+    const bool panels = o.fused_cfg == GP_FUSED_PANELS;
+    P.cfg = panels ? -1 : pick_fused_cfg(dt, p, o.fused_cfg);
+    P.np = 0;
+    if (panels || (P.cfg < 0 && o.fused_cfg <= 0)) {
+        const int64_t np = (p + wide_panel_cols(dt) - 1) / wide_panel_cols(dt);
+        if (np <= 65535) {   // the panels are the grid's second dimension
+            P.cfg = kCfgWide;
+            P.np = (int)np;
+        }
+    }
     P.G = pick_fused_grid(n, p, dt, o.fused_grid);
     P.rows = (n + P.G - 1) / P.G;
     P.G = (n + P.rows - 1) / P.rows;
@@ -401,6 +446,7 @@ Plan plan_single(gp_dtype dt, int64_t n, int64_t p, const gp_opts& o) {
     P.o_vitem = take(sizeof(VerItem) * P.nvitems);
     P.o_vpart = take(sizeof(double) * P.nvitems);
     P.o_vidx = take(sizeof(int32_t) * 4);
+    P.o_tpart = take(sizeof(double) * (size_t)P.np * n);
     P.bytes = off;
     return P;
 }
@@ -641,10 +687,12 @@ static int solve_single(gp_handle h, gp_dtype kdtype, const void* K, int64_t n, 
     // the state and the float copy of d, and the fused and update kernels
     // recompute h from x and g; d only parks P(x0) during the x0 check
     const int il = o.fused_interleave;
-    const FusedArgs fa_refresh{st, K, n, p, ldk, P.rows, x, nullptr, nullptr, y64, nullptr, q, wpart, P.ldw, spart, il,
-                               nullptr};
+    FusedArgs fa_refresh{st, K, n, p, ldk, P.rows, x, nullptr, nullptr, y64, nullptr, q, wpart, P.ldw, spart, il,
+                         nullptr};
     // iteration: h is recomputed from x and g inside the fused kernel (v NULL)
-    const FusedArgs fa_iter{st, K, n, p, ldk, P.rows, nullptr, x, g, nullptr, r, q, wpart, P.ldw, spart, il, d32};
+    FusedArgs fa_iter{st, K, n, p, ldk, P.rows, nullptr, x, g, nullptr, r, q, wpart, P.ldw, spart, il, d32};
+    fa_refresh.tpart = fa_iter.tpart = (double*)(ws + P.o_tpart);
+    fa_refresh.np = fa_iter.np = P.np;
     auto refresh = [&]() {
         launch_fused(kdtype, P.cfg, aligned, s, P.G, fa_refresh);
         launch_update(kdtype, s, st, UM_REFRESH, spart, (int)P.G, wpart, P.ldw, p, n, x, g, r, q, upart);

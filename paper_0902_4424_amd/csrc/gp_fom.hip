@@ -298,12 +298,14 @@ extern "C" int gp_fom_solve(gp_handle h, int32_t method, gp_dtype kdtype, const 
             tk = tn;
         }
     }
-    const FusedArgs fa_x{st, K, n, p, ldk, P.rows, x, nullptr, nullptr, y64, nullptr, t, wpart, P.ldw, spart,
-                         o.fused_interleave, nullptr};
-    const FusedArgs fa_z{st, K, n, p, ldk, P.rows, zr, nullptr, nullptr, y64, nullptr, t, wpart, P.ldw, spart,
-                         o.fused_interleave, nullptr};
-    const FusedArgs fa_r{st, K, n, p, ldk, P.rows, zr, nullptr, nullptr, nullptr, nullptr, t, wpart, P.ldw, spart,
-                         o.fused_interleave, nullptr};
+    FusedArgs fa_x{st, K, n, p, ldk, P.rows, x, nullptr, nullptr, y64, nullptr, t, wpart, P.ldw, spart,
+                   o.fused_interleave, nullptr};
+    FusedArgs fa_z{st, K, n, p, ldk, P.rows, zr, nullptr, nullptr, y64, nullptr, t, wpart, P.ldw, spart,
+                   o.fused_interleave, nullptr};
+    FusedArgs fa_r{st, K, n, p, ldk, P.rows, zr, nullptr, nullptr, nullptr, nullptr, t, wpart, P.ldw, spart,
+                   o.fused_interleave, nullptr};
+    fa_x.tpart = fa_z.tpart = fa_r.tpart = (double*)(ws + P.o_tpart);
+    fa_x.np = fa_z.np = fa_r.np = P.np;
     const unsigned nbp = (unsigned)P.nbp;
     auto cols = [&](int step, double thr, double c) {
         if (f64v)

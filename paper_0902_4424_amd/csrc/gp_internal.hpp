@@ -45,6 +45,10 @@ struct Plan {
     // partial sums, the (one) checked problem and its item range
     size_t o_vprob, o_vitem, o_vpart, o_vidx;
     int nvitems;
+    // wide problems: column panels (0 when one workgroup holds every column)
+    // and the panels' partial dots (np * n)
+    int np;
+    size_t o_tpart;
 };
 
 // Arguments of one fused K / K^T launch (see k_fused).
@@ -54,7 +58,12 @@ struct FusedArgs {
     int interleave;
     const float* v32;   // float copy of the multiplied vector, or NULL
     hipEvent_t ev0 = nullptr, ev1 = nullptr;   // timing: recorded by the launch itself
+    // wide problems (cfg == kCfgWide): np column panels and their partial dots
+    double* tpart = nullptr;
+    int np = 0;
 };
+// The fused configuration index of the two-launch pass over column panels.
+constexpr int kCfgWide = 1000;
 void launch_fused(gp_dtype dt, int cfg, bool aligned, hipStream_t s, int64_t G, const FusedArgs& a);
 Plan plan_single(gp_dtype dt, int64_t n, int64_t p, const gp_opts& o);
 int esize(gp_dtype dt);

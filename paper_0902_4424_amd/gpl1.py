@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(PKG, "lib", "libgpl1.so")
 
 GP_F64, GP_F32, GP_BF16 = 0, 1, 2
 GP_ISTA, GP_FISTA, GP_PSD = 0, 1, 2
+GP_FUSED_PANELS = 13          # gp_opts.fused_cfg: the K pass over column panels
 FOM_METHODS = {"ista": GP_ISTA, "fista": GP_FISTA, "psd": GP_PSD}
 STATUS = {0: "ok_tol", 1: "stationary", 2: "max_iter", 3: "reached_target",
           4: "backtrack_limit", -1: "bad_argument", -2: "nonfinite",

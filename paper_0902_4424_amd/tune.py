@@ -3,7 +3,8 @@
 Single problems (K dtype, n, p): it times the fused K / K^T kernel (HIP
 events around every 4th launch, `profile` option) and the whole iteration
 over the candidate kernel shapes (threads, column chunks per thread, rows
-per block) and grid sizes (row slabs), and records the fastest; the binding
+per block, or the two-launch pass over column panels) and grid sizes (row
+slabs), and records the fastest; the binding
 passes it through gp_opts.fused_cfg / fused_grid / fused_interleave.
 
 Shared-K batches (dtype, n, p, B): the whole batched solve to a relative
@@ -29,6 +30,7 @@ TABLE = os.path.join(PKG, "tuned.json")
 CFG_COVER = {1: (256, 1), 2: (256, 2), 3: (256, 4), 4: (512, 4), 5: (512, 8), 6: (1024, 8),
              7: (256, 4), 8: (512, 4), 9: (512, 8), 10: (1024, 4), 11: (1024, 4), 12: (1024, 2)}
 ESIZE = {"f64": 8, "f32": 4, "bf16": 2}
+PANELS = 13   # gp_opts.fused_cfg of the pass over column panels (GP_FUSED_PANELS)
 GRIDS = (64, 128, 192, 256, 384, 512)
 
 
@@ -60,6 +62,10 @@ def candidates(dtype, n, p):
                 if g <= n:
                     for il in (0, 1):
                         out.append((c, g, il))
+    # the pass over column panels (two launches, K read twice): the automatic
+    # choice past 8192 / 16384 columns, a candidate from 4096 on
+    if p > 4096:
+        out += [(PANELS, g, 0) for g in GRIDS if g <= n]
     return out
 
 

@@ -114,3 +114,11 @@ def test_option_helpers_without_gpu():
     assert {"fused_cfg", "fused_grid", "fused_interleave"} <= set(kw)
     assert gpl1._tuned(gpl1.GP_F32, 4096, 16384, {"fused_cfg": 2}) == {"fused_cfg": 2}
     assert gpl1._tuned(gpl1.GP_F32, 3, 5, {}) == {}
+
+
+def test_header_constants_match_binding():
+    src = open(HEADER).read()
+    m = re.search(r"#define\s+GP_FUSED_PANELS\s+(\d+)", src)
+    assert m and int(m.group(1)) == gpl1.GP_FUSED_PANELS
+    m = re.search(r"#define\s+GP_NOALLOC_SCRATCH_BYTES\s+\((\d+)u\s*<<\s*(\d+)\)", src)
+    assert m and (int(m.group(1)) << int(m.group(2))) == 32 << 20
