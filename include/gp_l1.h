@@ -132,7 +132,21 @@ typedef struct {
                                  p <= 1024 run the fused pass one row per wave (dots reduced within
                                  the wave, no barrier per row); -1 = the workgroup-wide pass for
                                  every item.  The two round differently (both FP32-level). */
+    double* trace;            /* gp_l1_solve: device ring of trace_cap records of GP_TRACE_FIELDS
+                                 doubles, written by the device as it iterates (NULL = off, no
+                                 cost).  Update k (1-based) goes to record (k - 1) % trace_cap:
+                                 {k, f after the update, alpha of its projection, lambda of the
+                                 line search, backtracks, tau and rule of the steplength rule that
+                                 gave alpha (Algorithm 2: 0 alpha_max, 1 BB1 alpha^(1), 2 the
+                                 windowed alpha^(2); -1 for the first update, whose alpha is
+                                 alpha_0), mu of the projection (0 inside the ball), the size of
+                                 its active set {|v_i| > mu} (-1 inside the ball), the threshold
+                                 search's passes}.  Ignored by the batched solvers. */
+    int32_t trace_cap;        /* records in `trace` (> 0 when trace is set)             */
 } gp_opts;
+
+/* doubles per record of gp_opts.trace */
+#define GP_TRACE_FIELDS 10
 
 typedef struct {
     int32_t status;       /* gp_status                                         */

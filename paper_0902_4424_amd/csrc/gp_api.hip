@@ -183,6 +183,8 @@ GPParams make_params(const gp_opts& o, double rho, double tol) {
     P.bt_cap = o.backtrack_cap;
     P.x0_fallback = o.x0_fallback ? 1 : 0;
     P.progress = nullptr;
+    P.trace = nullptr;
+    P.trace_cap = 0;
     return P;
 }
 
@@ -193,6 +195,7 @@ int check_opts(gp_handle h, const gp_opts& o) {
     if (!(o.alpha_min > 0.0 && o.alpha_min < o.alpha_max && std::isfinite(o.alpha_max)))
         return fail(h, GP_E_ARG, "need 0 < alpha_min < alpha_max < inf");
     if (!(o.tau1 > 0.0 && o.tau1 < 1.0)) return fail(h, GP_E_ARG, "opts.tau1 must be in (0,1)");
+    if (o.trace && o.trace_cap <= 0) return fail(h, GP_E_ARG, "opts.trace needs opts.trace_cap > 0");
     if (!(o.M_alpha >= 0 && o.M_alpha <= MAX_RING - 1)) return fail(h, GP_E_ARG, "opts.M_alpha must be in 0..3");
     if (o.max_iter < 0) return fail(h, GP_E_ARG, "opts.max_iter must be >= 0");
     if (o.refresh_every < 0) return fail(h, GP_E_ARG, "opts.refresh_every must be >= 0");
@@ -673,6 +676,10 @@ static int solve_single(gp_handle h, gp_dtype kdtype, const void* K, int64_t n, 
     {
         GPParams prm = make_params(o, rho, tol);
         if (ahead) prm.progress = h->progress_dev;
+        if (o.trace) {
+            prm.trace = o.trace;
+            prm.trace_cap = o.trace_cap;
+        }
         const unsigned sg = (unsigned)((std::max(n, p) + 255) / 256);
         if (f64v)
             hipLaunchKernelGGL(k_setup<double>, dim3(sg), dim3(256), 0, s, st, prm,

@@ -38,6 +38,7 @@ constexpr int PROJ_T = 1024;
 constexpr int UPD_T = 256;
 constexpr int UPD_COLS = 32;   // columns per p-part workgroup of k_update
 constexpr int UPD_ROWS = 256;  // rows per n-part workgroup of k_update
+constexpr int TRACE_FIELDS = 10;   // doubles per record of the per-update trace
 constexpr int SPART = 8;       // doubles per fused-kernel workgroup in spart:
                                // t't, t'r, g'd, d'd, ||d||_inf
 
@@ -432,6 +433,7 @@ __global__ __launch_bounds__(T) void k_proj(GPState* __restrict__ st, int mode, 
     const bool inside = Sv <= rho;
     double t = 0.0;     // mu - m
     int passes = 0;
+    int nact = inside ? -1 : 0;   // the final pass's active set
     // Outside the ball the register slots are turned into b = |v| - m once
     // (-inf for slots past p) with the signs kept in `neg`, so that a pass is
     // one compare and one add per slot.
@@ -476,7 +478,10 @@ __global__ __launch_bounds__(T) void k_proj(GPState* __restrict__ st, int mode, 
             // c >= 1: the largest entry has b = 0 > t.  After the first
             // (Newton) step t is kept monotone, so the sets are nested in
             // floating point too and the loop ends within p + 1 passes.
-            if (c == cprev || passes >= (1 << 20)) break;
+            if (c == cprev || passes >= (1 << 20)) {
+                nact = c;
+                break;
+            }
             cprev = c;
             const double tn = (sum - rho) / (double)c;
             t = first ? tn : fmax(t, tn);
@@ -555,6 +560,7 @@ __global__ __launch_bounds__(T) void k_proj(GPState* __restrict__ st, int mode, 
             S.hmode = inside ? 1 : (rho > 0.0 ? 0 : 2);
             S.michelot_iters = passes;
             S.michelot_total += passes;
+            S.nactive = nact;
             S.live = 1;
         }
     } else if (mode == PM_ALPHA0) {
@@ -1115,6 +1121,19 @@ __global__ __launch_bounds__(UPD_T) void k_update(GPState* __restrict__ st, int 
             else if (S.k + 1 >= P.max_iter) st->status = ST_MAX_ITER;
             else stop = false;
             if (stop) st->stop_req = 1;
+            if (P.trace) {
+                double* rec = P.trace + (int64_t)(S.k % P.trace_cap) * TRACE_FIELDS;
+                rec[0] = S.k + 1;
+                rec[1] = fn;
+                rec[2] = S.alpha;
+                rec[3] = lam;
+                rec[4] = nb;
+                rec[5] = S.tau;
+                rec[6] = S.k == 0 ? -1 : S.rule;
+                rec[7] = S.mu;
+                rec[8] = S.nactive;
+                rec[9] = S.michelot_iters;
+            }
             post_progress(P, S.k + 1, stop);
         } else {
             st->f_new = qq;              // sum of t_i^2 = ||K x - y||^2

@@ -35,6 +35,9 @@ struct GPParams {
     // host-mapped word the update kernel posts its progress to (updates
     // completed, bit 31 once a stop is requested), or NULL
     uint32_t* progress;
+    // ring of per-update records (GP_TRACE_FIELDS doubles each), or NULL
+    double* trace;
+    int32_t trace_cap;
 };
 
 struct GPState {
@@ -69,7 +72,7 @@ struct GPState {
     int32_t tcheck;            // 1: a stop at the target passed the check
     int32_t reopened;          // checks that failed and reopened the problem
     int32_t reproj;            // uneven batches: reopened, needs a projection before its next sweep
-    int32_t pad_;
+    int32_t nactive;           // the last threshold search's active set size (-1: inside the ball)
 };
 
 }  // namespace gpl1

@@ -17,6 +17,8 @@ LIB_PATH = os.path.join(PKG, "lib", "libgpl1.so")
 GP_F64, GP_F32, GP_BF16 = 0, 1, 2
 GP_ISTA, GP_FISTA, GP_PSD = 0, 1, 2
 GP_FUSED_PANELS = 13          # gp_opts.fused_cfg: the K pass over column panels
+TRACE_FIELDS = 10             # GP_TRACE_FIELDS: doubles per record of gp_opts.trace
+TRACE_COLUMNS = ("k", "f", "alpha", "lam", "backtracks", "tau", "rule", "mu", "nactive", "passes")
 FOM_METHODS = {"ista": GP_ISTA, "fista": GP_FISTA, "psd": GP_PSD}
 STATUS = {0: "ok_tol", 1: "stationary", 2: "max_iter", 3: "reached_target",
           4: "backtrack_limit", -1: "bad_argument", -2: "nonfinite",
@@ -43,7 +45,8 @@ class GPOpts(C.Structure):
                 ("batch_splitk", C.c_int32), ("batch_rows_t", C.c_int32),
                 ("batch_cols_t", C.c_int32), ("var_item_rows", C.c_int32),
                 ("batch_gemm_depth", C.c_int32), ("batch_gemm_tile", C.c_int32),
-                ("lookahead", C.c_int32), ("var_wave_rows", C.c_int32)]
+                ("lookahead", C.c_int32), ("var_wave_rows", C.c_int32),
+                ("trace", C.POINTER(C.c_double)), ("trace_cap", C.c_int32)]
 
 
 class GPResult(C.Structure):
@@ -258,7 +261,9 @@ class Handle:
     # -- one problem ----------------------------------------------------
     def solve(self, K, y, rho: float, x0=None, tol: float = 1e-10, out=None,
               opts: GPOpts | None = None, stream=None, **kw):
-        """gp_l1_solve: the handle's workspace grows as needed."""
+        """gp_l1_solve: the handle's workspace grows as needed.  `trace=N`
+        keeps the device's last N per-update records (gp_opts.trace) in
+        result["trace"], rows in update order, columns TRACE_COLUMNS."""
         return self._solve(self.lib.gp_l1_solve, K, y, rho, x0, tol, out, opts, stream, kw)
 
     def solve_noalloc(self, K, y, rho: float, x0=None, tol: float = 1e-10, out=None,
@@ -284,12 +289,30 @@ class Handle:
             out = torch.empty(p, dtype=vdt, device=K.device)
         elif out.dtype != vdt or out.numel() != p or not out.is_contiguous() or not out.is_cuda:
             raise ValueError(f"out must be a contiguous device {vdt} tensor of length {p}")
+        kw = dict(kw)
+        cap = int(kw.pop("trace", 0) or 0)
+        if cap < 0:
+            raise ValueError("trace must be >= 0 (records kept)")
         o = opts if opts is not None else default_opts(**_tuned(kdt, n, p, kw))
+        tbuf = None
+        if cap:
+            # the device ring of per-update records (gp_opts.trace)
+            tbuf = torch.full((cap, TRACE_FIELDS), float("nan"), dtype=torch.float64, device=K.device)
+            o.trace = C.cast(C.c_void_p(tbuf.data_ptr()), C.POINTER(C.c_double))
+            o.trace_cap = cap
         res = GPResult()
         rc = fn(self.h, kdt, _ptr(K), n, p, ldk, _ptr(y), float(rho), _ptr(x0), float(tol),
                 _ptr(out), C.byref(o), C.byref(res), _stream(stream))
         self._raise(rc)
-        return out, res.as_dict()
+        d = res.as_dict()
+        if tbuf is not None:
+            # the last min(iters, cap) records in update order
+            it = d["iters"]
+            rows = tbuf.cpu().numpy()
+            keep = min(it, cap)
+            order = [(k - 1) % cap for k in range(it - keep + 1, it + 1)]
+            d["trace"] = rows[order] if keep else rows[:0]
+        return out, d
 
     # -- the comparison methods of Section 2 ------------------------------
     def fom(self, method: str, K, y, param: float, iters: int, tau: float = 1.0, x0=None, out=None,

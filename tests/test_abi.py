@@ -49,6 +49,7 @@ int main(void) {
   printf("%zu %zu %zu\n", offsetof(gp_result, f), offsetof(gp_result, lambda_est),
          offsetof(gp_result, l1norm));
   printf("%zu %zu\n", offsetof(gp_instance, n), offsetof(gp_instance, rho));
+  printf("%zu %zu\n", offsetof(gp_opts, trace), offsetof(gp_opts, trace_cap));
   return 0;
 }''')
     exe = tmp_path / "sz"
@@ -61,7 +62,7 @@ int main(void) {
             O.theta.offset, O.M_alpha.offset, O.f_target.offset, O.chunk.offset,
             O.fused_grid.offset, O.f_targets.offset, O.x0_fallback.offset, R.x0_rejected.offset, O.graph.offset,
             R.reopened.offset, O.lookahead.offset, R.f.offset, R.lambda_est.offset, R.l1norm.offset,
-            I.n.offset, I.rho.offset]
+            I.n.offset, I.rho.offset, O.trace.offset, O.trace_cap.offset]
     assert vals == want
 
 
@@ -120,5 +121,7 @@ def test_header_constants_match_binding():
     src = open(HEADER).read()
     m = re.search(r"#define\s+GP_FUSED_PANELS\s+(\d+)", src)
     assert m and int(m.group(1)) == gpl1.GP_FUSED_PANELS
+    m = re.search(r"#define\s+GP_TRACE_FIELDS\s+(\d+)", src)
+    assert m and int(m.group(1)) == gpl1.TRACE_FIELDS == len(gpl1.TRACE_COLUMNS)
     m = re.search(r"#define\s+GP_NOALLOC_SCRATCH_BYTES\s+\((\d+)u\s*<<\s*(\d+)\)", src)
     assert m and (int(m.group(1)) << int(m.group(2))) == 32 << 20
