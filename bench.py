@@ -277,6 +277,48 @@ def forms_legs(H, inst, np, torch, gpl1, instances, out, with_cpu):
         "K_GB_per_sweep": round(kbytes / 1e9, 3),
         "K_GBps_streamed": round(streamed / tvar / 1e9, 1)}
     log(f"batched uneven: {tvar * 1e3:.1f} ms for 512 problems; plain {tseq * 1e3:.2f} ms/problem")
+    res["wide_fp32"] = wide_leg(H, np, torch, gpl1, instances)
+    return res
+
+
+def wide_leg(H, np, torch, gpl1, instances):
+    """A problem past the fused kernel's width: 4096 x 65536 FP32 K (1 GiB),
+    whose K pass runs over four column panels in two launches (K read twice per
+    iteration); a fixed budget of iterations, the pass timed by its own events."""
+    dev = torch.device("cuda:0")
+    n, p = 4096, 65536
+    t0 = time.time()
+    inst = instances.gaussian_instance(n, p, 400, amp="normal", sigma=1e-2, rho_scale=0.9,
+                                       kscale=1 / 64, dtype="f32", seed=23, name="gauss_4096x65536")
+    log(f"{n}x{p} instance generated in {time.time() - t0:.1f}s")
+    K = torch.from_numpy(inst.K_store).to(dev)
+    y = torch.from_numpy(inst.y_store).to(dev)
+    rho = inst.rho
+    del inst
+    iters = 60
+    o = gpl1.opts_for(K, max_iter=iters, refresh_every=REFRESH, profile=PROFILE_EVERY)
+    H.solve(K, y, rho, tol=0.0, opts=o)
+    torch.cuda.synchronize()
+    _, r = H.solve(K, y, rho, tol=0.0, opts=o)
+    us = r["t_fused_ms"] * 1e3 / max(r["n_fused"], 1)
+    o2 = gpl1.opts_for(K, max_iter=iters, refresh_every=REFRESH)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, r2 = H.solve(K, y, rho, tol=0.0, opts=o2)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    kb = n * p * 4
+    alg = 2 * kb + 8 * p + 16 * n + 4 * p
+    res = {"workload": f"gauss {n}x{p} fp32 (1 GiB), 400-sparse N(0,1), rho = 0.9 ||x_true||_1, "
+                       f"{iters} iterations",
+           "panels": (p + 16383) // 16384, "iterations": r2["iters"], "status": r2["status_name"],
+           "iterations_per_s": round(r2["iters"] / dt, 1), "pass_avg_us": round(us, 2),
+           "K_read_GBps": round(2 * kb / us / 1e3, 1), "alg_bytes_per_pass": alg,
+           "frac_of_8TBps": round(alg / us / 1e3 / HBM_PEAK_GBS, 4)}
+    log(f"wide 4096x65536: pass {us:.1f} us ({2 * kb / us / 1e3:.0f} GB/s of K reads), "
+        f"{r2['iters'] / dt:.0f} it/s")
+    del K
+    torch.cuda.empty_cache()
     return res
 
 

@@ -221,7 +221,8 @@ int gp_l1_solve(gp_handle h, gp_dtype kdtype, const void* K, int64_t n,
  * Limits: the workspace needed for (kdtype, n, p) must fit the scratch --
  * about (36 + 4G) p + 24 n bytes for float or bf16 K and (36 + 8G) p + 24 n
  * for double K, where G <= 256 is the number of row slabs the K pass uses
- * (256 once K holds 32 MB or more), so a 4096 x 16384 float K fits --
+ * (256 once K holds 32 MB or more), plus 8 n per column panel of a wide
+ * problem, so a 4096 x 16384 float K fits --
  * otherwise GP_E_UNSUPPORTED is returned before anything is launched;
  * opts.graph and opts.profile must be 0 (GP_E_ARG).
  * Every call on one device shares that device's scratch, which keeps the

@@ -307,6 +307,7 @@ __global__ __launch_bounds__(T) void k_proj(GPState* __restrict__ st, int mode, 
                                                  const double* __restrict__ upart, int GU,
                                                  double* __restrict__ vbuf, float* __restrict__ d32) {
     constexpr int NV = VPT > 0 ? VPT : 1;
+    constexpr int PU = 8;   // streamed form (VPT = 0): elements per thread per round
     static_assert(NV <= 32, "the sign mask of the shifted slots has 32 bits");
     __shared__ double lds[3 * (T / WAVE)];
     __shared__ __align__(16) double slots[4 * (T / WAVE)];   // the threshold passes' reductions
@@ -413,7 +414,25 @@ __global__ __launch_bounds__(T) void k_proj(GPState* __restrict__ st, int mode, 
             Sm_m[0] = fmax(Sm_m[0], a);
         }
     } else {
-        for (int64_t j = tid; j < p; j += T) {
+        // PU loads per operand in flight per thread (one L2 round trip per
+        // PU elements instead of per element), summed in the same j order
+        int64_t j = tid;
+        for (; j + (PU - 1) * T < p; j += PU * T) {
+            double xv[PU], gv[PU];
+#pragma unroll
+            for (int u = 0; u < PU; ++u) {
+                xv[u] = x[j + u * T];
+                gv[u] = use_g ? g[j + u * T] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < PU; ++u) {
+                const double vj = use_g ? fma(-alpha, gv[u], xv[u]) : xv[u];
+                vbuf[j + u * T] = vj;
+                Sm_s[0] += fabs(vj);
+                Sm_m[0] = fmax(Sm_m[0], fabs(vj));
+            }
+        }
+        for (; j < p; j += T) {
             const double vj = use_g ? fma(-alpha, g[j], x[j]) : x[j];
             vbuf[j] = vj;
             Sm_s[0] += fabs(vj);
@@ -467,7 +486,16 @@ __global__ __launch_bounds__(T) void k_proj(GPState* __restrict__ st, int mode, 
                     if (a) sum += vr[e];
                 }
             } else {
-                for (int64_t j = tid; j < p; j += T) {
+                int64_t j = tid;
+                for (; j + (PU - 1) * T < p; j += PU * T) {
+                    double b[PU];
+#pragma unroll
+                    for (int u = 0; u < PU; ++u) b[u] = fabs(vbuf[j + u * T]) - m;
+#pragma unroll
+                    for (int u = 0; u < PU; ++u)
+                        if (b[u] > t) { ++c; sum += b[u]; }
+                }
+                for (; j < p; j += T) {
                     const double b = fabs(vbuf[j]) - m;
                     if (b > t) { ++c; sum += b; }
                 }
@@ -551,7 +579,18 @@ __global__ __launch_bounds__(T) void k_proj(GPState* __restrict__ st, int mode, 
                 }
             }
         } else if (d32) {
-            for (int64_t j = tid; j < p; j += T) d32[j] = (float)(hval(vbuf[j]) - x[j]);
+            int64_t j = tid;
+            for (; j + (PU - 1) * T < p; j += PU * T) {
+                double vv[PU], xv[PU];
+#pragma unroll
+                for (int u = 0; u < PU; ++u) {
+                    vv[u] = vbuf[j + u * T];
+                    xv[u] = x[j + u * T];
+                }
+#pragma unroll
+                for (int u = 0; u < PU; ++u) d32[j + u * T] = (float)(hval(vv[u]) - xv[u]);
+            }
+            for (; j < p; j += T) d32[j] = (float)(hval(vbuf[j]) - x[j]);
         }
         if (tid == 0) {
             S.mu = inside ? 0.0 : m + t;
