@@ -241,8 +241,11 @@ extern "C" int gp_fom_solve(gp_handle h, int32_t method, gp_dtype kdtype, const 
     if (o.chunk < 1) return fail(h, GP_E_ARG, "opts.chunk must be >= 1");
     if (!K || !y || !x_out) return fail(h, GP_E_ARG, "null pointer argument");
     if (n > ((int64_t)1 << 31)) return fail(h, GP_E_UNSUPPORTED, "n too large");
+    // PSD projects in registers (up to 32 values per thread of one workgroup);
+    // ISTA and FISTA take any p
     const int nv = fom_nv(p);
-    if (nv == 0) return fail(h, GP_E_UNSUPPORTED, "p = " + std::to_string(p) + " exceeds 32768");
+    if (method == GP_PSD && nv == 0)
+        return fail(h, GP_E_UNSUPPORTED, "PSD: p = " + std::to_string(p) + " exceeds 32768");
     Plan P = plan_single(kdtype, n, p, o);
     if (P.cfg < 0)
         return fail(h, GP_E_UNSUPPORTED, "p = " + std::to_string(p) + " exceeds the fused kernel's column capacity");

@@ -184,3 +184,22 @@ def test_explicit_one_pass_beyond_the_panel_width(H, dt, p):
     gap = _rel_gap(inst, x.cpu().numpy(), ref)
     say(f"   gpu iters={res['iters']} status={res['status_name']} gap={gap:.2e}")
     assert gap <= 1e-6, (gap, res)
+
+
+def test_first_order_methods_past_32768_columns(H):
+    """ISTA and FISTA take any p (double K, p = 40001: five panels); PSD, which
+    projects in registers, refuses p past 32768."""
+    say("[wide] FP64 24x40001: ISTA and FISTA, 6 steps; PSD refused")
+    inst = instances.gaussian_instance(24, 40001, 4, dtype="f64", seed=690)
+    L = float(np.linalg.norm(inst.K64, 2) ** 2)
+    lam = 0.05 * float(np.abs(inst.K64.T @ inst.y64).max())
+    K, y = _K(inst), _dev(inst.y_store)
+    for name, fn in (("ista", ista), ("fista", fista)):
+        ref = fn(inst.K64, inst.y64, lam, tau=1.0 / L, max_iter=6)
+        x, r = H.fom(name, K, y, lam, 6, tau=1.0 / L)
+        err = np.linalg.norm(x.cpu().numpy() - ref["x"]) / max(np.linalg.norm(ref["x"]), 1e-300)
+        say(f"   {name} x rel err {err:.2e}")
+        assert r["iters"] == 6 and err <= 1e-10, (name, err)
+    with pytest.raises(gpl1.GPError) as e:
+        H.fom("psd", K, y, inst.rho, 3)
+    assert e.value.code == -5
