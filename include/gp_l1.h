@@ -290,9 +290,9 @@ typedef enum { GP_ISTA = 0, GP_FISTA = 1, GP_PSD = 2 } gp_fom_method;
  * chunk fields are used (NULL = automatic).  res (host): iters, f = the
  * method's objective at the returned x (F for ISTA and FISTA, f for PSD)
  * computed in double from the returned x, l1norm; lambda_est is not set.
- * Any p for ISTA and FISTA (their K passes as in gp_l1_solve, column panels past
- * 8192 / 16384 columns); PSD: p <= 32768 (GP_E_UNSUPPORTED beyond).  Errors as
- * gp_l1_solve (GP_E_ARG for an unknown method). */
+ * Any p (the K passes as in gp_l1_solve, column panels past 8192 / 16384
+ * columns; PSD's projection streams past 32768 columns, where result.proj_passes
+ * is not counted).  Errors as gp_l1_solve (GP_E_ARG for an unknown method). */
 int gp_fom_solve(gp_handle h, int32_t method, gp_dtype kdtype, const void* K,
                  int64_t n, int64_t p, int64_t ldk, const void* y, double param,
                  double tau, const void* x0, int32_t iters, void* x_out,

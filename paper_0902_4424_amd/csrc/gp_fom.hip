@@ -178,6 +178,42 @@ __global__ __launch_bounds__(T) void k_fom_psd_proj(GPState* __restrict__ st, do
     }
 }
 
+// PSD past the register projection's width: every workgroup forms beta from
+// the same partial sums in the same order, then v = x + beta r into `v`; the
+// projection kernel's streamed form (PM_PLAIN) writes P_Omega(v) into x next.
+// r = 0 or K r = 0 requests the stop, which that kernel turns into live = 0.
+__global__ __launch_bounds__(256) void k_fom_psd_v(GPState* __restrict__ st, const double* __restrict__ x,
+                                                   const double* __restrict__ r, int64_t p,
+                                                   const double* __restrict__ rpart, int nr,
+                                                   const double* __restrict__ spart, int GF,
+                                                   double* __restrict__ v) {
+    __shared__ double lds[3 * (256 / WAVE)];
+    __shared__ int live;
+    const int tid = threadIdx.x;
+    if (tid == 0) live = st->live;
+    __syncthreads();
+    if (!live) return;
+    double s[2] = {0.0, 0.0}, none[1] = {0.0};
+    for (int i = tid; i < nr; i += 256) s[0] += rpart[i];
+    for (int i = tid; i < GF; i += 256) s[1] += spart[SPART * i];
+    block_reduce<256, 2, 1>(s, none, lds);
+    const double rr = s[0], kk = s[1];
+    if (!(rr > 0.0) || !(kk > 0.0)) {
+        if (blockIdx.x == 0 && tid == 0) {
+            st->status = isfinite(rr) && isfinite(kk) ? ST_STATIONARY : ST_NONFINITE;
+            st->stop_req = 1;
+        }
+        return;
+    }
+    const double beta = rr / kk;
+    for (int64_t j = (int64_t)blockIdx.x * 256 + tid; j < p; j += (int64_t)gridDim.x * 256)
+        v[j] = fma(beta, r[j], x[j]);
+    if (blockIdx.x == 0 && tid == 0) {
+        st->k += 1;
+        st->lam = beta;
+    }
+}
+
 // End of a run: x narrowed into the caller's output and ||x||_1 of the
 // returned values.
 template <typename TV>
@@ -243,9 +279,9 @@ extern "C" int gp_fom_solve(gp_handle h, int32_t method, gp_dtype kdtype, const 
     if (n > ((int64_t)1 << 31)) return fail(h, GP_E_UNSUPPORTED, "n too large");
     // PSD projects in registers (up to 32 values per thread of one workgroup);
     // ISTA and FISTA take any p
+    // PSD projects in registers up to 32 values per thread of one workgroup,
+    // beyond that through the projection kernel's streamed form
     const int nv = fom_nv(p);
-    if (method == GP_PSD && nv == 0)
-        return fail(h, GP_E_UNSUPPORTED, "PSD: p = " + std::to_string(p) + " exceeds 32768");
     Plan P = plan_single(kdtype, n, p, o);
     if (P.cfg < 0)
         return fail(h, GP_E_UNSUPPORTED, "p = " + std::to_string(p) + " exceeds the fused kernel's column capacity");
@@ -318,7 +354,16 @@ extern "C" int gp_fom_solve(gp_handle h, int32_t method, gp_dtype kdtype, const 
             hipLaunchKernelGGL(k_fom_cols<float>, dim3(nbp), dim3(UPD_T), 0, s, st, step, (const float*)wpart,
                                P.ldw, (int)P.G, p, x, zr, zr, rpart, thr, tau, c);
     };
+    double* vd = (double*)(ws + P.o_d);      // PSD past 32768 columns: v = x + beta r
     auto psd_proj = [&]() {
+        if (nv == 0) {
+            const unsigned gb = (unsigned)std::min<int64_t>((p + 255) / 256, 1024);
+            hipLaunchKernelGGL(k_fom_psd_v, dim3(gb), dim3(256), 0, s, st, (const double*)x, (const double*)zr, p,
+                               (const double*)rpart, (int)nbp, (const double*)spart, (int)P.G, vd);
+            hipLaunchKernelGGL((k_proj<0, 1024>), dim3(1), dim3(1024), 0, s, st, (int)PM_PLAIN, p, vd,
+                               (const double*)nullptr, x, (const double*)nullptr, 0, vb, (float*)nullptr);
+            return;
+        }
         switch (nv) {
 #define GPL1_FOM_PROJ(V) \
     case V: \

@@ -171,7 +171,6 @@ def test_psd_stationary_and_errors(H):
     assert lib.gp_fom_solve(H.h, 7, gpl1.GP_F64, p, 3, 3, 3, p, 1.0, 1.0, None, 5, p, ro, rr, None) == -1
     assert lib.gp_fom_solve(H.h, gpl1.GP_ISTA, gpl1.GP_F64, p, 3, 3, 3, p, -1.0, 1.0, None, 5, p, ro, rr,
                             None) == -1
-    # PSD with p above its projection's register capacity: refused before any
-    # launch (ISTA and FISTA take any p)
-    assert lib.gp_fom_solve(H.h, gpl1.GP_PSD, gpl1.GP_F32, p, 3, 40000, 40000, p, 1.0, 1.0, None, 5, p, ro,
-                            rr, None) == -5
+    # ldk < p: refused before any launch
+    assert lib.gp_fom_solve(H.h, gpl1.GP_PSD, gpl1.GP_F64, p, 3, 3, 2, p, 1.0, 1.0, None, 5, p, ro,
+                            rr, None) == -1

@@ -19,7 +19,7 @@ torch = pytest.importorskip("torch")
 
 sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
 from oracle import gpss
-from oracle.fom import fista, ista
+from oracle.fom import fista, ista, psd
 from paper_0902_4424_amd import gpl1, instances
 
 pytestmark = pytest.mark.gpu
@@ -187,9 +187,10 @@ def test_explicit_one_pass_beyond_the_panel_width(H, dt, p):
 
 
 def test_first_order_methods_past_32768_columns(H):
-    """ISTA and FISTA take any p (double K, p = 40001: five panels); PSD, which
-    projects in registers, refuses p past 32768."""
-    say("[wide] FP64 24x40001: ISTA and FISTA, 6 steps; PSD refused")
+    """ISTA, FISTA and PSD take any p (double K, p = 40001: five panels; PSD's
+    projection in its streamed form past 32768 columns): the FP64 iterates
+    equal the oracle's."""
+    say("[wide] FP64 24x40001: ISTA, FISTA and PSD, 6 steps")
     inst = instances.gaussian_instance(24, 40001, 4, dtype="f64", seed=690)
     L = float(np.linalg.norm(inst.K64, 2) ** 2)
     lam = 0.05 * float(np.abs(inst.K64.T @ inst.y64).max())
@@ -200,6 +201,20 @@ def test_first_order_methods_past_32768_columns(H):
         err = np.linalg.norm(x.cpu().numpy() - ref["x"]) / max(np.linalg.norm(ref["x"]), 1e-300)
         say(f"   {name} x rel err {err:.2e}")
         assert r["iters"] == 6 and err <= 1e-10, (name, err)
-    with pytest.raises(gpl1.GPError) as e:
-        H.fom("psd", K, y, inst.rho, 3)
-    assert e.value.code == -5
+    for rho in (inst.rho, 0.2 * inst.rho):
+        ref = psd(inst.K64, inst.y64, rho, max_iter=6)
+        x, r = H.fom("psd", K, y, rho, 6)
+        xn = x.cpu().numpy()
+        err = np.linalg.norm(xn - ref["x"]) / np.linalg.norm(ref["x"])
+        say(f"   psd rho={rho:.3g} x rel err {err:.2e}")
+        assert r["iters"] == ref["iters"] == 6 and err <= 1e-10
+        assert r["f"] == pytest.approx(ref["f"], rel=1e-10)
+        assert np.abs(xn).sum() <= rho * (1 + 1e-12)
+    # from an x0 outside the ball (projected first), and a stationary start
+    x0 = np.random.default_rng(3).standard_normal(40001)
+    ref = psd(inst.K64, inst.y64, inst.rho, x0=x0, max_iter=4)
+    x, r = H.fom("psd", K, y, inst.rho, 4, x0=_dev(x0))
+    err = np.linalg.norm(x.cpu().numpy() - ref["x"]) / np.linalg.norm(ref["x"])
+    assert err <= 1e-10
+    x, r = H.fom("psd", K, torch.zeros_like(y), inst.rho, 5)
+    assert r["status_name"] == "stationary" and r["iters"] == 0 and not x.any().item()
