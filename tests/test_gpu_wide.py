@@ -218,3 +218,34 @@ def test_first_order_methods_past_32768_columns(H):
     assert err <= 1e-10
     x, r = H.fom("psd", K, torch.zeros_like(y), inst.rho, 5)
     assert r["status_name"] == "stationary" and r["iters"] == 0 and not x.any().item()
+
+
+def test_batched_forms_route_wide_problems_through_the_panels(H):
+    """A shared-K batch past the matrix-core path's 16384 columns, and an
+    uneven batch holding a wide problem, run each problem on the single solver
+    and so on the panel pass: every solution at the FP32 bar."""
+    say("[wide] shared-K batch 32x20001 f32, B = 3; uneven batch with a 32x40000 problem")
+    inst = instances.gaussian_instance(32, 20001, 3, dtype="f32", seed=700)
+    rng = np.random.default_rng(701)
+    ys = [inst.y64.astype(np.float32)]
+    for _ in range(2):
+        xt = np.zeros(20001)
+        xt[rng.choice(20001, 3, replace=False)] = rng.choice([-1.0, 1.0], 3)
+        ys.append((inst.K64 @ xt + 1e-2 * rng.standard_normal(32)).astype(np.float32))
+    rhos = [inst.rho, 2.0, 3.0]
+    K = _K(inst)
+    X, rs = H.solve_batched_shared(K, _dev(np.stack(ys)), rhos, tol=1e-13, max_iter=20000)
+    for b in range(3):
+        y64 = ys[b].astype(np.float64)
+        ref = gpss(inst.K64, y64, rhos[b], tol=1e-13, max_iter=20000)
+        x = X[b].cpu().numpy().astype(np.float64)
+        fx = float(np.sum((inst.K64 @ x - y64) ** 2))
+        scale = max(ref["f"], 1e-3 * float(y64 @ y64))
+        assert (fx - ref["f"]) / scale <= 1e-6, (b, fx, ref["f"], rs[b])
+    wide = instances.gaussian_instance(32, 40000, 3, dtype="f32", seed=702)
+    small = instances.gaussian_instance(16, 500, 3, dtype="f32", seed=703)
+    probs = [(_K(i), _dev(i.y_store), i.rho) for i in (wide, small)]
+    xs, rv = H.solve_batched_var(probs, tol=1e-13, max_iter=20000)
+    for i, x, r in zip((wide, small), xs, rv):
+        ref = gpss(i.K64, i.y64, i.rho, tol=1e-13, max_iter=20000)
+        assert _rel_gap(i, x.cpu().numpy(), ref) <= 1e-6, r
