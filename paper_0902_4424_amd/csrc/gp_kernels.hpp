@@ -611,7 +611,15 @@ __global__ __launch_bounds__(T) void k_proj(GPState* __restrict__ st, int mode, 
                 if (j < p) hmax = fmax(hmax, fabs(hreg(e)));
             }
         } else {
-            for (int64_t j = tid; j < p; j += T) hmax = fmax(hmax, fabs(hval(vbuf[j])));
+            int64_t j = tid;
+            for (; j + (PU - 1) * T < p; j += PU * T) {
+                double vv[PU];
+#pragma unroll
+                for (int u = 0; u < PU; ++u) vv[u] = vbuf[j + u * T];
+#pragma unroll
+                for (int u = 0; u < PU; ++u) hmax = fmax(hmax, fabs(hval(vv[u])));
+            }
+            for (; j < p; j += T) hmax = fmax(hmax, fabs(hval(vbuf[j])));
         }
         hmax = block_max<T>(hmax, lds);
         if (tid == 0) {
@@ -628,7 +636,15 @@ __global__ __launch_bounds__(T) void k_proj(GPState* __restrict__ st, int mode, 
                 if (j < p) out[j] = hreg(e);
             }
         } else {
-            for (int64_t j = tid; j < p; j += T) out[j] = hval(vbuf[j]);
+            int64_t j = tid;
+            for (; j + (PU - 1) * T < p; j += PU * T) {
+                double vv[PU];
+#pragma unroll
+                for (int u = 0; u < PU; ++u) vv[u] = vbuf[j + u * T];
+#pragma unroll
+                for (int u = 0; u < PU; ++u) out[j + u * T] = hval(vv[u]);
+            }
+            for (; j < p; j += T) out[j] = hval(vbuf[j]);
         }
         if (tid == 0) {
             S.mu = inside ? 0.0 : (rho > 0.0 ? m + t : m);
