@@ -99,3 +99,16 @@ def test_trace_ring_keeps_the_last_records(H):
     assert f[-1] == pytest.approx(full["f"], rel=1e-5)
     with pytest.raises(ValueError):
         H.solve(K, y, inst.rho, trace=-1)
+
+
+def test_trace_same_under_graph_replay_and_noalloc(H):
+    """Captured-graph chunks and the allocation-free entry point write the
+    same records, bit for bit, as plain launches."""
+    say("[trace] FP64 256x1024: plain, graph chunks of 8, allocation-free")
+    inst = instances.plain_small(seed=2, dtype="f64")
+    K, y = _dev(inst.K_store), _dev(inst.y_store)
+    _, a = H.solve(K, y, inst.rho, tol=0.0, max_iter=30, trace=32)
+    _, b = H.solve(K, y, inst.rho, tol=0.0, max_iter=30, trace=32, graph=1, chunk=8)
+    _, c = H.solve_noalloc(K, y, inst.rho, tol=0.0, max_iter=30, trace=32)
+    assert a["trace"].shape == (30, gpl1.TRACE_FIELDS)
+    assert np.array_equal(a["trace"], b["trace"]) and np.array_equal(a["trace"], c["trace"])

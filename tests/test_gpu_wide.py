@@ -249,3 +249,17 @@ def test_batched_forms_route_wide_problems_through_the_panels(H):
     for i, x, r in zip((wide, small), xs, rv):
         ref = gpss(i.K64, i.y64, i.rho, tol=1e-13, max_iter=20000)
         assert _rel_gap(i, x.cpu().numpy(), ref) <= 1e-6, r
+
+
+@pytest.mark.parametrize("dt", ["f32", "bf16"])
+def test_panels_and_one_pass_agree_at_the_same_width(H, dt):
+    """At p = 16384 (one panel) the panel pass asked for and the automatic
+    one-pass kernel both reach the oracle's solution at the FP32 bar."""
+    say(f"[wide] {dt} 96x16384: one pass against GP_FUSED_PANELS")
+    inst = instances.gaussian_instance(96, 16384, 5, dtype=dt, seed=710)
+    ref = gpss(inst.K64, inst.y64, inst.rho, tol=1e-13, max_iter=20000)
+    K, y = _K(inst), _dev(inst.y_store)
+    x1, r1 = H.solve(K, y, inst.rho, tol=1e-13, max_iter=20000)
+    x2, r2 = H.solve(K, y, inst.rho, tol=1e-13, max_iter=20000, fused_cfg=gpl1.GP_FUSED_PANELS, fused_grid=32)
+    for x, r in ((x1, r1), (x2, r2)):
+        assert _rel_gap(inst, x.cpu().numpy(), ref) <= 1e-6, r
